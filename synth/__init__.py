@@ -1,0 +1,497 @@
+"""Seeded synthetic inputs shared by the oracle and the HIP path.
+
+This module produces *inputs* only: the prime, the hidden polynomials or
+rational functions that play the role of the black box, the sampling schedule
+(the random points the method draws, passed into both implementations), and
+a host black-box evaluator (``blackbox.c``).  It contains none of the
+reconstruction method's arithmetic (no Vandermonde solve, no Newton or Thiele
+interpolation).
+
+Randomness: SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom
+number generators", OOPSLA 2014), a counter-based generator: output i of a
+stream with seed s is mix(s + (i+1)*gamma).  Uniform integers in [lo, hi) use
+rejection: draw u, accept iff u < floor(2^64/n)*n with n = hi-lo, return
+lo + u mod n.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_GAMMA = 0x9E3779B97F4A7C15
+_M1 = 0xBF58476D1CE4E5B9
+_M2 = 0x94D049BB133111EB
+_MASK = (1 << 64) - 1
+
+PRIME_SEED = 20250530
+
+
+def _mix_np(z: np.ndarray) -> np.ndarray:
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(_M1)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(_M2)
+        return z ^ (z >> np.uint64(31))
+
+
+def _mix(z: int) -> int:
+    z = ((z ^ (z >> 30)) * _M1) & _MASK
+    z = ((z ^ (z >> 27)) * _M2) & _MASK
+    return z ^ (z >> 31)
+
+
+class SplitMix64:
+    """Stream of SplitMix64 outputs; ``next()`` and ``block(n)`` consume in order."""
+
+    def __init__(self, seed: int):
+        self.state = seed & _MASK
+
+    def next(self) -> int:
+        self.state = (self.state + _GAMMA) & _MASK
+        return _mix(self.state)
+
+    def block(self, n: int) -> np.ndarray:
+        """The next n outputs as a uint64 array (vectorised, same stream)."""
+        if n <= 0:
+            return np.zeros(0, dtype=np.uint64)
+        idx = np.arange(1, n + 1, dtype=np.uint64)
+        with np.errstate(over="ignore"):
+            st = np.uint64(self.state) + idx * np.uint64(_GAMMA)
+        self.state = (self.state + n * _GAMMA) & _MASK
+        return _mix_np(st)
+
+    def uniform(self, lo: int, hi: int) -> int:
+        n = hi - lo
+        assert n >= 1
+        lim = ((1 << 64) // n) * n
+        while True:
+            u = self.next()
+            if lim == (1 << 64) or u < lim:
+                return lo + u % n
+
+    def uniform_block(self, lo: int, hi: int, count: int) -> np.ndarray:
+        """``count`` draws of ``uniform(lo, hi)``, identical to calling it in a loop."""
+        n = hi - lo
+        assert n >= 1
+        lim = ((1 << 64) // n) * n
+        out = np.empty(count, dtype=np.uint64)
+        got = 0
+        while got < count:
+            need = count - got
+            raw = self.block(need)
+            if lim == (1 << 64):
+                ok = np.ones(need, dtype=bool)
+            else:
+                ok = raw < np.uint64(lim)
+            if ok.all():
+                out[got:] = np.uint64(lo) + raw % np.uint64(n)
+                got = count
+            else:
+                # keep the accepted prefix up to the first rejection, re-sync the
+                # stream just after that rejection, and continue
+                first_bad = int(np.argmin(ok))
+                out[got:got + first_bad] = np.uint64(lo) + raw[:first_bad] % np.uint64(n)
+                got += first_bad
+                self.state = (self.state - (need - first_bad - 1) * _GAMMA) & _MASK
+        return out
+
+
+# --------------------------------------------------------------------------
+# primes (input generation: the prime is an input to the method)
+
+_MR_BASES = (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37)
+
+
+def is_prime(n: int) -> bool:
+    """Deterministic Miller-Rabin for n < 3.3e24 with the first twelve prime bases."""
+    if n < 2:
+        return False
+    for b in _MR_BASES:
+        if n % b == 0:
+            return n == b
+    d, s = n - 1, 0
+    while d % 2 == 0:
+        d //= 2
+        s += 1
+    for a in _MR_BASES:
+        x = pow(a, d, n)
+        if x in (1, n - 1):
+            continue
+        for _ in range(s - 1):
+            x = x * x % n
+            if x == n - 1:
+                break
+        else:
+            return False
+    return True
+
+
+def make_prime(seed: int = PRIME_SEED) -> int:
+    """Smallest prime >= an odd seeded value in [2^62, 2^63)."""
+    g = SplitMix64(seed)
+    x = g.uniform(1 << 62, 1 << 63) | 1
+    while not is_prime(x):
+        x += 2
+        if x >= (1 << 63):
+            x = (1 << 62) + 1
+    return x
+
+
+# --------------------------------------------------------------------------
+# hidden polynomials
+
+@dataclass
+class SparsePoly:
+    """Polynomial over F_p: exps [nterms][nvars] (uint16), coefs [nterms] (uint64), lex-sorted."""
+    p: int
+    nvars: int
+    exps: np.ndarray
+    coefs: np.ndarray
+
+    @property
+    def nterms(self) -> int:
+        return int(self.coefs.shape[0])
+
+    def sorted(self) -> "SparsePoly":
+        if self.nterms == 0:
+            return self
+        order = np.lexsort(self.exps.T[::-1])
+        return SparsePoly(self.p, self.nvars, np.ascontiguousarray(self.exps[order]),
+                          np.ascontiguousarray(self.coefs[order]))
+
+    def as_dict(self):
+        return {tuple(int(x) for x in e): int(c) for e, c in zip(self.exps, self.coefs)}
+
+    def degrees(self) -> List[int]:
+        if self.nterms == 0:
+            return [0] * self.nvars
+        return [int(x) for x in self.exps.max(axis=0)]
+
+
+def _distinct_exponents(g: SplitMix64, nvars: int, nterms: int, draw_row) -> np.ndarray:
+    seen = {}
+    rows = []
+    while len(rows) < nterms:
+        e = draw_row()
+        key = bytes(e.astype(np.uint16).tobytes())
+        if key in seen:
+            continue
+        seen[key] = True
+        rows.append(e)
+    return np.array(rows, dtype=np.uint16).reshape(nterms, nvars)
+
+
+def random_poly(p: int, nvars: int, deg: Sequence[int] | int, nterms: int, seed: int) -> SparsePoly:
+    """t distinct exponent vectors uniform in prod [0, D_v], coefficients uniform in [1, p)."""
+    if isinstance(deg, int):
+        deg = [deg] * nvars
+    space = 1
+    for d in deg:
+        space *= d + 1
+    assert nterms <= space, "more terms than monomials"
+    g = SplitMix64(seed)
+    if nterms * 4 > space:
+        # dense regime: draw a random subset of all monomials by index
+        idx = []
+        seen = set()
+        while len(idx) < nterms:
+            u = g.uniform(0, space)
+            if u not in seen:
+                seen.add(u)
+                idx.append(u)
+        exps = np.zeros((nterms, nvars), dtype=np.uint16)
+        for r, u in enumerate(idx):
+            for v in range(nvars - 1, -1, -1):
+                exps[r, v] = u % (deg[v] + 1)
+                u //= deg[v] + 1
+    else:
+        # draw candidate rows in bulk; first occurrences in stream order win
+        exps_list = []
+        seen = set()
+        bulk = max(1024, nterms * 2)
+        while len(exps_list) < nterms:
+            cols = [g.uniform_block(0, deg[v] + 1, bulk) for v in range(nvars)]
+            cand = np.stack(cols, axis=1).astype(np.uint16)
+            for row in cand:
+                key = row.tobytes()
+                if key in seen:
+                    continue
+                seen.add(key)
+                exps_list.append(row)
+                if len(exps_list) == nterms:
+                    break
+        exps = np.array(exps_list, dtype=np.uint16).reshape(nterms, nvars)
+    coefs = g.uniform_block(1, p, nterms)
+    return SparsePoly(p, nvars, exps, coefs).sorted()
+
+
+def _simplex_row(g: SplitMix64, nvars: int, total: int) -> np.ndarray:
+    """Uniform exponent vector with sum <= total (stars and bars: a uniform
+    nvars-subset of {0..total+nvars-1} gives the bar positions)."""
+    npos = total + nvars
+    chosen = set()
+    while len(chosen) < nvars:
+        chosen.add(g.uniform(0, npos))
+    bars = sorted(chosen)
+    e = np.empty(nvars, dtype=np.uint16)
+    prev = -1
+    for v, b in enumerate(bars):
+        e[v] = b - prev - 1
+        prev = b
+    return e
+
+
+def random_poly_total_degree(p: int, nvars: int, total: int, nterms: int, seed: int,
+                             with_constant_one: bool = False) -> SparsePoly:
+    """t distinct exponents uniform over {e : sum(e) <= total}; coefficients in [1, p).
+    With ``with_constant_one`` the zero monomial is included with coefficient 1."""
+    g = SplitMix64(seed)
+    rows = []
+    seen = set()
+    if with_constant_one:
+        z = np.zeros(nvars, dtype=np.uint16)
+        rows.append(z)
+        seen.add(z.tobytes())
+    while len(rows) < nterms:
+        e = _simplex_row(g, nvars, total)
+        key = e.tobytes()
+        if key in seen:
+            continue
+        seen.add(key)
+        rows.append(e)
+    exps = np.array(rows, dtype=np.uint16).reshape(nterms, nvars)
+    coefs = g.uniform_block(1, p, nterms)
+    if with_constant_one:
+        coefs[0] = 1
+    return SparsePoly(p, nvars, exps, coefs).sorted()
+
+
+# --------------------------------------------------------------------------
+# sampling schedule (the random points the method draws; an input to both sides)
+
+@dataclass
+class Schedule:
+    """y_v (Zippel bases), anchors c_v, per-variable extra nodes c_v^(1..J_v), probe points."""
+    p: int
+    y: np.ndarray          # [nvars]
+    anchor: np.ndarray     # [nvars]
+    nodes: List[np.ndarray]  # nodes[v] has J_v entries, all distinct and != anchor[v]
+    probes: np.ndarray     # [nprobes][nvars]
+
+    def nodes_concat(self) -> np.ndarray:
+        if not self.nodes:
+            return np.zeros(0, dtype=np.uint64)
+        return np.concatenate([np.asarray(n, dtype=np.uint64) for n in self.nodes]).astype(np.uint64)
+
+    def counts(self) -> np.ndarray:
+        return np.array([len(n) for n in self.nodes], dtype=np.uint32)
+
+
+def make_schedule(p: int, nvars: int, nnodes: Sequence[int], seed: int, nprobes: int = 0) -> Schedule:
+    """Draw order: y_1..y_n in [2, p-1); c_1..c_n in [1, p); for each variable k its
+    nodes in [1, p), redrawing any value equal to c_k or to an earlier node of k;
+    finally nprobes points, each n values in [1, p)."""
+    g = SplitMix64(seed)
+    y = np.array([g.uniform(2, p - 1) for _ in range(nvars)], dtype=np.uint64)
+    anchor = np.array([g.uniform(1, p) for _ in range(nvars)], dtype=np.uint64)
+    nodes = []
+    for k in range(nvars):
+        used = {int(anchor[k])}
+        lst = []
+        while len(lst) < nnodes[k]:
+            x = g.uniform(1, p)
+            if x in used:
+                continue
+            used.add(x)
+            lst.append(x)
+        nodes.append(np.array(lst, dtype=np.uint64))
+    probes = np.array([[g.uniform(1, p) for _ in range(nvars)] for _ in range(nprobes)],
+                      dtype=np.uint64).reshape(nprobes, nvars)
+    return Schedule(p, y, anchor, nodes, probes)
+
+
+def thiele_nodes_needed(dnum: int, dden: int) -> int:
+    """Nodes beyond the anchor for a univariate rational function of type at most
+    (dnum, dden): the continued fraction needs m = max(2a-1, 2b) + 1 samples and one
+    more sample confirms it."""
+    m = max(2 * dnum - 1, 2 * dden, 0)
+    return m + 1
+
+
+# --------------------------------------------------------------------------
+# workload configurations (shapes of the paper's sparse workloads, synthetic)
+
+@dataclass
+class PolyWorkload:
+    name: str
+    p: int
+    hidden: SparsePoly
+    deg: List[int]
+    schedule: Schedule
+
+
+@dataclass
+class RationalWorkload:
+    name: str
+    p: int
+    num: SparsePoly
+    den: SparsePoly
+    deg_num: List[int]
+    deg_den: List[int]
+    schedule: Schedule
+
+
+POLY_CONFIGS = {
+    # name: (nvars, per-variable degree bound, nterms)
+    "cfg1_n3_d10_t50": (3, 10, 50),
+    "cfg2_n6_d30_t1e4": (6, 30, 10_000),
+    "cfg3_n8_d40_t5e5": (8, 40, 500_000),
+}
+
+
+def poly_workload(name: str, nvars: int, deg: int, nterms: int, poly_seed: int,
+                  sched_seed: int, nprobes: int = 2, p: Optional[int] = None) -> PolyWorkload:
+    p = make_prime() if p is None else p
+    hidden = random_poly(p, nvars, deg, nterms, poly_seed)
+    degs = [deg] * nvars
+    sched = make_schedule(p, nvars, degs, sched_seed, nprobes)
+    return PolyWorkload(name, p, hidden, degs, sched)
+
+
+def config_workload(idx: int, nprobes: int = 2) -> PolyWorkload:
+    """Polynomial configurations 1-3: hidden-polynomial seed = idx, schedule seed = 1000+idx."""
+    name = list(POLY_CONFIGS)[idx - 1]
+    n, d, t = POLY_CONFIGS[name]
+    return poly_workload(name, n, d, t, idx, 1000 + idx, nprobes)
+
+
+def rational_workload(nvars: int, total_deg: int, tnum: int, tden: int, seed: int,
+                      nprobes: int = 2, p: Optional[int] = None,
+                      name: str = "rational") -> RationalWorkload:
+    """P/Q with Q(0)=1; exponents uniform over the total-degree simplex; per-variable
+    bounds = total_deg for both."""
+    p = make_prime() if p is None else p
+    num = random_poly_total_degree(p, nvars, total_deg, tnum, seed * 2 + 1)
+    den = random_poly_total_degree(p, nvars, total_deg, tden, seed * 2 + 2, with_constant_one=True)
+    dn = [total_deg] * nvars
+    dd = [total_deg] * nvars
+    J = [thiele_nodes_needed(a, b) for a, b in zip(dn, dd)]
+    sched = make_schedule(p, nvars, J, 1000 + seed, nprobes)
+    return RationalWorkload(name, p, num, den, dn, dd, sched)
+
+
+def loguniform_int(g: SplitMix64, lo: int, hi: int) -> int:
+    u = g.uniform(0, 1 << 53) / float(1 << 53)
+    return int(round(math.exp(math.log(lo) + u * (math.log(hi) - math.log(lo)))))
+
+
+# --------------------------------------------------------------------------
+# host black box (C, OpenMP): evaluates a hidden polynomial or P/Q at the
+# structured Zippel points or at explicit points
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+class _PolyDesc(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_uint64), ("nvars", ctypes.c_uint32), ("nterms", ctypes.c_uint32),
+                ("exps", ctypes.c_void_p), ("coefs", ctypes.c_void_p)]
+
+
+class _BoxDesc(ctypes.Structure):
+    _fields_ = [("num", _PolyDesc), ("den", _PolyDesc), ("rational", ctypes.c_int32),
+                ("nthreads", ctypes.c_int32)]
+
+
+def lib_path() -> str:
+    return os.path.join(_HERE, "libzsynth.so")
+
+
+def build(verbose: bool = False) -> str:
+    import subprocess
+    src = os.path.join(_HERE, "blackbox.c")
+    out = lib_path()
+    cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11", "-o", out + ".tmp", src]
+    subprocess.run(cmd, check=True, capture_output=not verbose)
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(lib_path()):
+            build()
+        L = ctypes.CDLL(lib_path())
+        L.zs_eval_points.restype = ctypes.c_int
+        L.zs_eval_points.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                                     ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                     ctypes.c_void_p, ctypes.c_void_p]
+        _LIB = L
+    return _LIB
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+class BlackBox:
+    """Evaluates a hidden polynomial (or P/Q) mod p.
+
+    ``eval(k, i_first, ni, y, anchor, xk)`` returns values at the nj*ni points
+    (jj, ii): x_v = y_v^(i_first+ii) for v < k, x_k = xk[jj], x_v = anchor_v for
+    v > k (k is 1-based), laid out [jj][ii].
+    """
+
+    def __init__(self, num: SparsePoly, den: Optional[SparsePoly] = None, nthreads: int = 0):
+        self.num = num
+        self.den = den
+        self.p = num.p
+        self.nvars = num.nvars
+        self._keep = []
+        self.desc = _BoxDesc()
+        self.desc.num = self._pd(num)
+        if den is not None:
+            self.desc.den = self._pd(den)
+            self.desc.rational = 1
+        else:
+            self.desc.rational = 0
+        self.desc.nthreads = nthreads
+        self.calls = 0
+
+    def _pd(self, poly: SparsePoly) -> _PolyDesc:
+        e = _arr(poly.exps, np.uint16)
+        c = _arr(poly.coefs, np.uint64)
+        self._keep += [e, c]
+        return _PolyDesc(poly.p, poly.nvars, poly.nterms, e.ctypes.data, c.ctypes.data)
+
+    def ctx(self) -> int:
+        return ctypes.addressof(self.desc)
+
+    def eval(self, k: int, i_first: int, ni: int, y, anchor, xk) -> np.ndarray:
+        y = _arr(y, np.uint64)
+        anchor = _arr(anchor, np.uint64)
+        xk = _arr(xk, np.uint64)
+        out = np.zeros(len(xk) * ni, dtype=np.uint64)
+        rc = lib().zs_eval_points(ctypes.addressof(self.desc), self.nvars, k, i_first, ni,
+                                  y.ctypes.data, anchor.ctypes.data, len(xk), xk.ctypes.data,
+                                  out.ctypes.data)
+        self.calls += 1
+        if rc != 0:
+            raise ZeroDivisionError("black box: denominator vanishes at a requested point")
+        return out
+
+    def at(self, point) -> int:
+        """Value at one explicit point."""
+        pt = _arr(point, np.uint64)
+        n = self.nvars
+        return int(self.eval(n, 1, 1, pt[:n - 1] if n > 1 else np.zeros(1, np.uint64),
+                             np.zeros(n, np.uint64), pt[n - 1:n])[0])
+
+    @staticmethod
+    def c_function_address() -> int:
+        return ctypes.cast(lib().zs_eval_points, ctypes.c_void_p).value
