@@ -1,0 +1,199 @@
+/* zippel.h — C ABI of the MI355X (gfx950) sparse Zippel reconstruction library.
+ *
+ * What is computed (Smirnov, Rozhnov, Voevodin, "GPU Implementation of Zippel
+ * Method for Feynman Integral Reconstruction", 2025):
+ *   - The unknown is a black-box function over F_p, p a prime below 2^63, that
+ *     the caller evaluates at points the library chooses (Introduction: modular
+ *     black-box reconstruction; a result is accepted when further probes match).
+ *   - Polynomials are reconstructed variable by variable (Introduction, eq. 1):
+ *     stage k assumes the skeleton of stage k-1, samples at the Zippel points
+ *     (y_1^i, ..., y_{k-1}^i), i = 1..t, solves one transposed Vandermonde
+ *     system of size t per stage for D_k right-hand sides in O(t^2) (§1, §2.2),
+ *     and lifts every term by univariate Newton interpolation in x_k (eq. 1).
+ *   - Rational functions P/Q use the balanced Zippel variant (§1, §2.2 and its
+ *     balancing equation): per-slice Thiele reconstruction (eq. 2) in x_k, a
+ *     per-slice factor that makes all slices share one normalisation, then the
+ *     polynomial step on numerator and denominator separately.
+ *
+ * Conventions for every entry point:
+ *   - Return a zr_status; nothing throws across the ABI.  On error no output
+ *     is produced (zr_poly outputs are left empty).
+ *   - Device pointers ("d_") are caller-owned HIP device memory; host pointers
+ *     ("h_" or plain const arrays in structs) are caller-owned host memory.
+ *   - All device work is ordered on the caller's stream.  zippel_* calls return
+ *     after their host results are ready; vandermonde_solve_batch is
+ *     asynchronous and reports per-system status in device memory.
+ *   - Values handed in must lie in [0, p), otherwise ZR_EINVAL (host inputs are
+ *     checked; device inputs are the caller's responsibility).
+ *   - Calls on different streams may run concurrently; calls are otherwise
+ *     not synchronised with each other.
+ */
+#ifndef ZIPPEL_H
+#define ZIPPEL_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ZR_OK = 0,
+  ZR_EINVAL = -1,     /* bad argument (sizes, p out of range, value >= p) */
+  ZR_ENOTPRIME = -2,  /* p fails deterministic Miller-Rabin */
+  ZR_ESINGULAR = -3,  /* two monomial values coincide or one is zero: the Zippel system is singular */
+  ZR_EDEGEN = -4,     /* degenerate interpolation (vanishing inverse difference, slice degrees differ) */
+  ZR_EPROBE = -5,     /* the result does not reproduce the black box at a probe point, or samples ran out */
+  ZR_ENORM = -6,      /* rational result: the denominator has no constant term */
+  ZR_ENOMEM = -7,     /* device or host allocation failed */
+  ZR_EDEVICE = -8,    /* a HIP runtime call failed */
+  ZR_EBLACKBOX = -9   /* the black box returned nonzero */
+} zr_status;
+
+const char* zr_strerror(int status);
+
+/* Result polynomial.  Library-owned host memory; release with zr_poly_free. */
+typedef struct {
+  uint32_t nvars;
+  uint64_t nterms;
+  uint16_t* exps;   /* [nterms][nvars] row-major, lexicographically ascending on (e_1..e_n) */
+  uint64_t* coeffs; /* [nterms], each in [1, p) */
+} zr_poly;
+void zr_poly_free(zr_poly* poly);
+
+/* Points the black box must evaluate.  Point (ii, jj), ii in [0, ni), jj in [0, nj):
+ *   x_v = y[v]^(i_first + ii)   for v < k-1   (0-based v; the Zippel powers of §1)
+ *   x_v = xk[jj]                for v = k-1   (values of the variable being added)
+ *   x_v = anchor[v]             for v > k-1   (variables not yet reached)
+ * and its value goes to d_vals[jj * ni + ii].  All three arrays are host memory.
+ * A single explicit point x is expressed as k = nvars, ni = 1, i_first = 1,
+ * y = x[0..n-2], xk = {x[n-1]}. */
+typedef struct {
+  uint32_t nvars;
+  uint32_t k;          /* stage, 1-based */
+  uint64_t i_first;
+  uint64_t ni;
+  uint64_t nj;
+  const uint64_t* y;
+  const uint64_t* anchor;
+  const uint64_t* xk;
+  uint64_t p;
+} zr_points;
+
+/* Black box: fill d_vals[nj*ni] (device memory) with values in [0, p), ordered
+ * before later work on `stream` (enqueue on it, or finish before returning).
+ * Nonzero return -> ZR_EBLACKBOX. */
+typedef int (*zr_blackbox_fn)(void* ctx, const zr_points* pts, uint64_t* d_vals, hipStream_t stream);
+
+/* Reconstruction parameters.
+ * Sampling schedule (the random choices of the method): either explicit
+ * (y, anchor, nodes non-NULL) or derived from `seed` by zr_schedule().
+ *   y[v]      Zippel base of variable v, 2 <= y < p-1
+ *   anchor[v] value c_v of x_v while it is not yet reconstructed, 1 <= c < p
+ *   nodes     per variable v, nnodes[v] further distinct values of x_v (not equal
+ *             to anchor[v]), concatenated in variable order.  Polynomial path:
+ *             nnodes[v] >= deg[v].  Balanced path: nnodes[v] >= zr_thiele_nodes(...).
+ * Degree bounds: deg[v] bounds deg_{x_v} of the polynomial (of the numerator for
+ * the balanced path); deg_den[v] bounds the denominator (balanced only). */
+typedef struct {
+  uint64_t p;                /* prime, 3 <= p < 2^63 */
+  uint32_t nvars;            /* 1..64 */
+  const uint32_t* deg;       /* [nvars] */
+  const uint32_t* deg_den;   /* [nvars] or NULL */
+  uint64_t seed;             /* used when y/anchor/nodes are NULL */
+  const uint64_t* y;         /* [nvars] or NULL */
+  const uint64_t* anchor;    /* [nvars] or NULL */
+  const uint64_t* nodes;     /* concatenated, or NULL */
+  const uint32_t* nnodes;    /* [nvars] counts of `nodes`, or NULL with seed-derived nodes */
+  uint32_t nprobes;          /* random-point checks of the final result (0 = off) */
+  const uint64_t* probes;    /* [nprobes][nvars] or NULL (then derived from seed) */
+  uint32_t last_stage;       /* 0 = all; L stops after stage L and returns f(x_1..x_L, anchors) */
+} zr_params;
+
+/* Number of nodes beyond the anchor that the balanced path needs for a variable
+ * with numerator/denominator degree bounds (a, b): a continued fraction with
+ * coefficients b_0..b_m has type (ceil(m/2), floor(m/2)), so m = max(2a-1, 2b),
+ * plus one confirming sample (eq. 2). */
+uint32_t zr_thiele_nodes(uint32_t deg_num, uint32_t deg_den);
+
+/* Seeded sampling schedule (SplitMix64, Steele-Lea-Flood 2014; uniform draws in
+ * [lo, hi) by rejection of u >= floor(2^64/n)*n).  Draw order: y_1..y_n in
+ * [2, p-1); anchors in [1, p); for each variable its nnodes[v] nodes in [1, p),
+ * redrawing repeats of the anchor or of earlier nodes; then nprobes points.
+ * Outputs are host arrays sized nvars, sum(nnodes), nprobes*nvars. */
+zr_status zr_schedule(uint64_t p, uint32_t nvars, const uint32_t* nnodes, uint64_t seed, uint32_t nprobes,
+                      uint64_t* y, uint64_t* anchor, uint64_t* nodes, uint64_t* probes);
+
+/* Deterministic Miller-Rabin (first twelve prime bases; exact for all 64-bit n). */
+int zr_is_prime(uint64_t n);
+
+/* Polynomial Zippel reconstruction (§1): returns f with deg_{x_v} f <= deg[v],
+ * terms with nonzero coefficients in lexicographic order. */
+zr_status zippel_reconstruct(const zr_params* params, zr_blackbox_fn bb, void* ctx, hipStream_t stream,
+                             zr_poly* out);
+
+/* Balanced Zippel for a rational function (§1, §2.2): returns num/den in
+ * lowest terms with den(0,...,0) = 1 (ZR_ENORM if den has no constant term). */
+zr_status zippel_balanced_reconstruct(const zr_params* params, zr_blackbox_fn bb, void* ctx, hipStream_t stream,
+                                      zr_poly* num, zr_poly* den);
+
+/* Batched transposed Vandermonde solve (the O(t^2) step of §1 and §2.2, many
+ * systems and right-hand sides at once).  System s has t_s unknowns and R_s
+ * right-hand sides; for each right-hand side j it solves
+ *      sum_l a_l * m_l^i = v_i,   i = 1..t_s
+ * (Zippel powers start at 1).
+ *   d_sys_off [nsys+1] device, prefix sums of t_s; m for system s at d_mono[d_sys_off[s] ..]
+ *   d_mono    device, monomial values, distinct and nonzero within a system
+ *   h_nrhs    [nsys] host, R_s
+ *   h_sys_off [nsys+1] host copy of d_sys_off (sizes drive the launch)
+ *   d_rhs_off [nsys+1] device, prefix sums of R_s * t_s; h_rhs_off the host copy
+ *   d_rhs     device, system s at d_rhs + rhs_off[s], laid out [R_s][t_s]: v_i at [j][i-1]
+ *   d_out     device, same layout as d_rhs: a_l at [j][l]  (may not alias d_rhs)
+ *   d_status  [nsys] device int32: ZR_OK or ZR_ESINGULAR (outputs of that system are 0)
+ * Asynchronous on `stream`; host-side argument errors return immediately. */
+zr_status vandermonde_solve_batch(size_t nsys, uint64_t p, const uint64_t* d_sys_off, const uint64_t* h_sys_off,
+                                  const uint64_t* d_mono, const uint32_t* h_nrhs, const uint64_t* d_rhs_off,
+                                  const uint64_t* h_rhs_off, const uint64_t* d_rhs, uint64_t* d_out,
+                                  int32_t* d_status, hipStream_t stream);
+
+/* ---- helpers for callers and black boxes ---------------------------------- */
+
+/* Synchronous copies between host and device memory on `stream`. */
+zr_status zr_copy_h2d(void* d_dst, const void* h_src, size_t bytes, hipStream_t stream);
+zr_status zr_copy_d2h(void* h_dst, const void* d_src, size_t bytes, hipStream_t stream);
+zr_status zr_copy_d2d(void* d_dst, const void* d_src, size_t bytes, hipStream_t stream);
+
+/* Record/replay black box: wraps another black box, records every call's device
+ * output; later replays them in the same order (descriptor sizes must match,
+ * else the replay call returns nonzero).  For benchmarks that exclude the
+ * black box's own cost. */
+typedef struct zr_recorder zr_recorder;
+zr_status zr_recorder_create(zr_recorder** rec, zr_blackbox_fn inner, void* inner_ctx);
+void zr_recorder_destroy(zr_recorder* rec);
+void zr_recorder_rewind(zr_recorder* rec);          /* next call replays record 0 */
+void zr_recorder_set_replay(zr_recorder* rec, int replay);
+int zr_recorder_blackbox(void* rec, const zr_points* pts, uint64_t* d_vals, hipStream_t stream);
+
+/* Kernel timing: when enabled, the library brackets each launch of its named
+ * kernels with HIP events on the launch stream and accumulates durations. */
+void zr_timing_enable(int on);
+void zr_timing_reset(void);
+/* Returns the number of timed launches of `kernel` and their total in ms. */
+uint64_t zr_timing_get(const char* kernel, double* total_ms);
+
+/* Algorithmic work counters of the last zippel_* call on this thread. */
+typedef struct {
+  uint64_t mulmods;       /* algorithmic modular products (each multiply-accumulate counts 1) */
+  uint64_t solve_mulmods; /* of which in the Vandermonde solves: R t^2 + 2 t(t-1) per system */
+  uint64_t vsolve_terms;  /* sum of t*R over all solved systems */
+  uint32_t stages;
+  uint64_t max_t;
+} zr_counters;
+void zr_last_counters(zr_counters* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ZIPPEL_H */

@@ -1,0 +1,372 @@
+"""MI355X (gfx950) sparse Zippel reconstruction over F_p.
+
+Thin ctypes binding of ``libzippel_hip.so`` (C ABI in ``include/zippel.h``).
+Every step of the reconstruction runs in the library's HIP kernels; this module
+only marshals arguments.  PyTorch is used for device memory and streams.
+The library must be built (``paper_2505_24256_amd.build.build()``); importing
+the binding on a machine without it raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Callable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libzippel_hip.so")
+
+ZR_OK, ZR_EINVAL, ZR_ENOTPRIME, ZR_ESINGULAR, ZR_EDEGEN = 0, -1, -2, -3, -4
+ZR_EPROBE, ZR_ENORM, ZR_ENOMEM, ZR_EDEVICE, ZR_EBLACKBOX = -5, -6, -7, -8, -9
+
+# every symbol include/zippel.h declares
+EXPORTS = [
+    "zr_strerror", "zr_poly_free", "zr_thiele_nodes", "zr_schedule", "zr_is_prime", "zippel_reconstruct",
+    "zippel_balanced_reconstruct", "vandermonde_solve_batch", "zr_copy_h2d", "zr_copy_d2h", "zr_copy_d2d",
+    "zr_recorder_create", "zr_recorder_destroy", "zr_recorder_rewind", "zr_recorder_set_replay",
+    "zr_recorder_blackbox", "zr_timing_enable", "zr_timing_reset", "zr_timing_get", "zr_last_counters",
+    "zr_microbench",
+]
+MB_KINDS = {"mad_u64_u32": 0, "mul_lo_u32": 1, "mul_hi_u32": 2, "add_u32": 3, "mac192": 4, "shoup": 5, "copy": 6}
+
+
+class ZippelError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        msg = lib().zr_strerror(code).decode() if _LIB is not None else str(code)
+        super().__init__(f"{what}: status {code} ({msg})")
+        self.code = code
+
+
+class ZrPoints(ctypes.Structure):
+    _fields_ = [("nvars", ctypes.c_uint32), ("k", ctypes.c_uint32), ("i_first", ctypes.c_uint64),
+                ("ni", ctypes.c_uint64), ("nj", ctypes.c_uint64), ("y", ctypes.POINTER(ctypes.c_uint64)),
+                ("anchor", ctypes.POINTER(ctypes.c_uint64)), ("xk", ctypes.POINTER(ctypes.c_uint64)),
+                ("p", ctypes.c_uint64)]
+
+
+class ZrPoly(ctypes.Structure):
+    _fields_ = [("nvars", ctypes.c_uint32), ("nterms", ctypes.c_uint64), ("exps", ctypes.POINTER(ctypes.c_uint16)),
+                ("coeffs", ctypes.POINTER(ctypes.c_uint64))]
+
+
+class ZrParams(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_uint64), ("nvars", ctypes.c_uint32), ("deg", ctypes.c_void_p),
+                ("deg_den", ctypes.c_void_p), ("seed", ctypes.c_uint64), ("y", ctypes.c_void_p),
+                ("anchor", ctypes.c_void_p), ("nodes", ctypes.c_void_p), ("nnodes", ctypes.c_void_p),
+                ("nprobes", ctypes.c_uint32), ("probes", ctypes.c_void_p), ("last_stage", ctypes.c_uint32)]
+
+
+class ZrCounters(ctypes.Structure):
+    _fields_ = [("mulmods", ctypes.c_uint64), ("solve_mulmods", ctypes.c_uint64), ("vsolve_terms", ctypes.c_uint64),
+                ("stages", ctypes.c_uint32), ("max_t", ctypes.c_uint64)]
+
+
+BLACKBOX_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ZrPoints), ctypes.c_void_p,
+                               ctypes.c_void_p)
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"HIP library not built: {LIB_PATH} (run paper_2505_24256_amd.build.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        u64, u32, vp, sz, i32 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+        L.zr_strerror.restype = ctypes.c_char_p
+        L.zr_strerror.argtypes = [i32]
+        L.zr_poly_free.argtypes = [ctypes.POINTER(ZrPoly)]
+        L.zr_poly_free.restype = None
+        L.zr_thiele_nodes.restype = u32
+        L.zr_thiele_nodes.argtypes = [u32, u32]
+        L.zr_schedule.argtypes = [u64, u32, vp, u64, u32, vp, vp, vp, vp]
+        L.zr_is_prime.argtypes = [u64]
+        L.zippel_reconstruct.argtypes = [ctypes.POINTER(ZrParams), vp, vp, vp, ctypes.POINTER(ZrPoly)]
+        L.zippel_balanced_reconstruct.argtypes = [ctypes.POINTER(ZrParams), vp, vp, vp, ctypes.POINTER(ZrPoly),
+                                                  ctypes.POINTER(ZrPoly)]
+        L.vandermonde_solve_batch.argtypes = [sz, u64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        for n in ("zr_copy_h2d", "zr_copy_d2h", "zr_copy_d2d"):
+            getattr(L, n).argtypes = [vp, vp, sz, vp]
+        L.zr_recorder_create.argtypes = [ctypes.POINTER(vp), vp, vp]
+        L.zr_recorder_destroy.argtypes = [vp]
+        L.zr_recorder_destroy.restype = None
+        L.zr_recorder_rewind.argtypes = [vp]
+        L.zr_recorder_rewind.restype = None
+        L.zr_recorder_set_replay.argtypes = [vp, i32]
+        L.zr_recorder_set_replay.restype = None
+        L.zr_timing_enable.argtypes = [i32]
+        L.zr_timing_enable.restype = None
+        L.zr_timing_reset.restype = None
+        L.zr_timing_get.restype = u64
+        L.zr_timing_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double)]
+        L.zr_last_counters.argtypes = [ctypes.POINTER(ZrCounters)]
+        L.zr_last_counters.restype = None
+        L.zr_microbench.argtypes = [i32, u32, u32, u64, vp, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]
+        _LIB = L
+    return _LIB
+
+
+def _u64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.uint64))
+
+
+def _u32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.uint32))
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None or a.size == 0 else a.ctypes.data
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def is_prime(n: int) -> bool:
+    return bool(lib().zr_is_prime(n))
+
+
+def thiele_nodes(deg_num: int, deg_den: int) -> int:
+    return int(lib().zr_thiele_nodes(deg_num, deg_den))
+
+
+def schedule(p: int, nnodes: Sequence[int], seed: int, nprobes: int = 0):
+    """The library's seeded schedule: (y, anchor, nodes_concat, probes)."""
+    nv = len(nnodes)
+    cnt = _u32(nnodes)
+    y = np.zeros(nv, np.uint64)
+    a = np.zeros(nv, np.uint64)
+    nodes = np.zeros(max(int(cnt.sum()), 1), np.uint64)
+    pr = np.zeros(max(nprobes * nv, 1), np.uint64)
+    st = lib().zr_schedule(p, nv, _ptr(cnt), seed, nprobes, y.ctypes.data, a.ctypes.data, nodes.ctypes.data,
+                           pr.ctypes.data)
+    if st != ZR_OK:
+        raise ZippelError(st, "zr_schedule")
+    return y, a, nodes[:int(cnt.sum())], pr[:nprobes * nv].reshape(nprobes, nv)
+
+
+# ---------------------------------------------------------------------------
+# black boxes
+
+class HostBlackBox:
+    """Wraps a host evaluator ``f(k, i_first, ni, y, anchor, xk) -> uint64[nj*ni]``
+    (e.g. ``synth.BlackBox.eval``) as a device black box: values are computed on
+    the host and copied to the device buffer the library provides."""
+
+    def __init__(self, fn: Callable, nvars: int):
+        self.fn = fn
+        self.nvars = nvars
+        self.calls = 0
+        self.error: Optional[BaseException] = None
+        self._cb = BLACKBOX_FN(self._call)
+
+    def _call(self, ctx, pts_ptr, d_vals, stream):
+        try:
+            pts = pts_ptr.contents
+            nv = pts.nvars
+            y = np.ctypeslib.as_array(pts.y, shape=(nv,)).copy() if nv else np.zeros(0, np.uint64)
+            a = np.ctypeslib.as_array(pts.anchor, shape=(nv,)).copy()
+            xk = np.ctypeslib.as_array(pts.xk, shape=(pts.nj,)).copy()
+            vals = _u64(self.fn(pts.k, pts.i_first, pts.ni, y, a, xk)).reshape(-1)
+            if vals.size != pts.ni * pts.nj:
+                return 11
+            st = lib().zr_copy_h2d(d_vals, vals.ctypes.data, vals.nbytes, stream)
+            self.calls += 1
+            return 0 if st == ZR_OK else 12
+        except BaseException as e:  # noqa: BLE001 - reported through the status code
+            self.error = e
+            return 13
+
+    @property
+    def fn_ptr(self):
+        return ctypes.cast(self._cb, ctypes.c_void_p)
+
+    ctx = None
+
+
+class Recorder:
+    """Record a black box's outputs once on the device, then replay them."""
+
+    def __init__(self, inner: HostBlackBox):
+        self.inner = inner
+        h = ctypes.c_void_p()
+        st = lib().zr_recorder_create(ctypes.byref(h), inner.fn_ptr, None)
+        if st != ZR_OK:
+            raise ZippelError(st, "zr_recorder_create")
+        self.handle = h
+
+    def replay(self, on: bool = True):
+        lib().zr_recorder_set_replay(self.handle, 1 if on else 0)
+
+    @property
+    def fn_ptr(self):
+        return ctypes.cast(lib().zr_recorder_blackbox, ctypes.c_void_p)
+
+    @property
+    def ctx(self):
+        return self.handle
+
+    def close(self):
+        if self.handle:
+            lib().zr_recorder_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+
+# ---------------------------------------------------------------------------
+# reconstruction
+
+def _take(poly: ZrPoly, nvars: int):
+    n = poly.nterms
+    if n:
+        e = np.ctypeslib.as_array(poly.exps, shape=(n * nvars,)).reshape(n, nvars).copy()
+        c = np.ctypeslib.as_array(poly.coeffs, shape=(n,)).copy()
+    else:
+        e = np.zeros((0, nvars), np.uint16)
+        c = np.zeros(0, np.uint64)
+    lib().zr_poly_free(ctypes.byref(poly))
+    return e, c
+
+
+class _ParamsHolder:
+    def __init__(self, p, deg, deg_den, sched, seed, nprobes, last_stage):
+        self.deg = _u32(deg)
+        self.deg_den = _u32(deg_den) if deg_den is not None else None
+        self.s = ZrParams()
+        self.s.p = p
+        self.s.nvars = len(deg)
+        self.s.deg = _ptr(self.deg)
+        self.s.deg_den = _ptr(self.deg_den)
+        self.s.seed = seed
+        self.s.last_stage = last_stage
+        if sched is not None:
+            self.y = _u64(sched.y)
+            self.anchor = _u64(sched.anchor)
+            self.nodes = _u64(sched.nodes_concat())
+            self.nnodes = _u32(sched.counts())
+            self.probes = _u64(sched.probes).reshape(-1)
+            self.s.y = _ptr(self.y)
+            self.s.anchor = _ptr(self.anchor)
+            self.s.nodes = self.nodes.ctypes.data
+            self.s.nnodes = _ptr(self.nnodes)
+            self.s.nprobes = sched.probes.shape[0] if nprobes is None else nprobes
+            self.s.probes = _ptr(self.probes)
+        else:
+            self.s.nprobes = nprobes or 0
+
+
+def _box_args(box):
+    if isinstance(box, (HostBlackBox, Recorder)):
+        return box.fn_ptr, box.ctx
+    raise TypeError("black box must be a HostBlackBox or Recorder")
+
+
+def reconstruct(p: int, deg: Sequence[int], box, sched=None, seed: int = 0, nprobes: Optional[int] = None,
+                last_stage: int = 0, stream=None):
+    """Polynomial Zippel on the GPU.  Returns (exps [nterms][nvars] uint16, coefs uint64)."""
+    h = _ParamsHolder(p, deg, None, sched, seed, nprobes, last_stage)
+    out = ZrPoly()
+    fn, ctx = _box_args(box)
+    st = lib().zippel_reconstruct(ctypes.byref(h.s), fn, ctx, _stream(stream), ctypes.byref(out))
+    if st != ZR_OK:
+        err = getattr(box, "error", None)
+        raise ZippelError(st, f"zippel_reconstruct{' (' + repr(err) + ')' if err else ''}")
+    return _take(out, len(deg))
+
+
+def balanced_reconstruct(p: int, deg_num: Sequence[int], deg_den: Sequence[int], box, sched=None, seed: int = 0,
+                         nprobes: Optional[int] = None, last_stage: int = 0, stream=None):
+    """Balanced Zippel on the GPU.  Returns ((exps, coefs) of num, (exps, coefs) of den), den(0) = 1."""
+    h = _ParamsHolder(p, deg_num, deg_den, sched, seed, nprobes, last_stage)
+    on, od = ZrPoly(), ZrPoly()
+    fn, ctx = _box_args(box)
+    st = lib().zippel_balanced_reconstruct(ctypes.byref(h.s), fn, ctx, _stream(stream), ctypes.byref(on),
+                                           ctypes.byref(od))
+    if st != ZR_OK:
+        raise ZippelError(st, "zippel_balanced_reconstruct")
+    return _take(on, len(deg_num)), _take(od, len(deg_num))
+
+
+def vandermonde_solve_batch(p: int, systems: List[Tuple[np.ndarray, np.ndarray]], stream=None):
+    """Solve sum_l a_l m_l^i = v_i (i = 1..t) for a list of (m [t], rhs [R][t]) on
+    the GPU.  Returns (list of a [R][t] arrays, status array)."""
+    import torch
+    nsys = len(systems)
+    t = np.array([len(m) for m, _ in systems], dtype=np.uint64)
+    def nrhs(m, r):
+        r = np.asarray(r)
+        if r.ndim == 2:
+            return r.shape[0]
+        return r.size // len(m) if len(m) else 0
+
+    R = np.array([nrhs(m, r) for m, r in systems], dtype=np.uint32)
+    sys_off = np.zeros(nsys + 1, np.uint64)
+    sys_off[1:] = np.cumsum(t)
+    rhs_off = np.zeros(nsys + 1, np.uint64)
+    rhs_off[1:] = np.cumsum(t * R.astype(np.uint64))
+    mono = np.concatenate([_u64(m) for m, _ in systems] + [np.zeros(1, np.uint64)])
+    rhs = np.concatenate([_u64(r).reshape(-1) for _, r in systems] + [np.zeros(1, np.uint64)])
+    dev = torch.device("cuda")
+    d_sys_off = torch.from_numpy(sys_off.view(np.int64)).to(dev)
+    d_rhs_off = torch.from_numpy(rhs_off.view(np.int64)).to(dev)
+    d_mono = torch.from_numpy(mono.view(np.int64)).to(dev)
+    d_rhs = torch.from_numpy(rhs.view(np.int64)).to(dev)
+    d_out = torch.zeros_like(d_rhs)
+    d_status = torch.zeros(max(nsys, 1), dtype=torch.int32, device=dev)
+    s = _stream(stream)
+    st = lib().vandermonde_solve_batch(nsys, p, d_sys_off.data_ptr(), sys_off.ctypes.data, d_mono.data_ptr(),
+                                       R.ctypes.data, d_rhs_off.data_ptr(), rhs_off.ctypes.data, d_rhs.data_ptr(),
+                                       d_out.data_ptr(), d_status.data_ptr(), s)
+    if st != ZR_OK:
+        raise ZippelError(st, "vandermonde_solve_batch")
+    torch.cuda.synchronize()
+    out = d_out.cpu().numpy().view(np.uint64)
+    res = [out[int(rhs_off[i]):int(rhs_off[i + 1])].reshape(int(R[i]), int(t[i])) for i in range(nsys)]
+    return res, d_status.cpu().numpy()[:nsys]
+
+
+# ---------------------------------------------------------------------------
+# timing and counters
+
+def timing(enable: bool = True):
+    lib().zr_timing_enable(1 if enable else 0)
+
+
+def timing_reset():
+    lib().zr_timing_reset()
+
+
+def timing_get(name: str) -> Tuple[int, float]:
+    ms = ctypes.c_double()
+    n = lib().zr_timing_get(name.encode(), ctypes.byref(ms))
+    return int(n), float(ms.value)
+
+
+def last_counters() -> dict:
+    c = ZrCounters()
+    lib().zr_last_counters(ctypes.byref(c))
+    return {k: int(getattr(c, k)) for k, _ in ZrCounters._fields_}
+
+
+def microbench(kind: str, blocks: int = 2048, iters: int = 4096, nbytes: int = 1 << 30, stream=None):
+    """(ms, ops) of one timed launch of a throughput probe (see include/zippel_microbench.h)."""
+    ms = ctypes.c_double()
+    ops = ctypes.c_double()
+    st = lib().zr_microbench(MB_KINDS[kind], blocks, iters, nbytes, _stream(stream), ctypes.byref(ms),
+                             ctypes.byref(ops))
+    if st != 0:
+        raise ZippelError(st, f"zr_microbench({kind})")
+    return ms.value, ops.value

@@ -1,0 +1,265 @@
+// gfx950 kernels of the balanced (rational) Zippel path: per-slice Thiele
+// reconstruction (eq. 2), the transposed Vandermonde apply that evaluates the
+// previous stage's numerator/denominator at the Zippel points, and the
+// balancing factors that make all slices share one normalisation (§2.2).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "field.hpp"
+#include "kernels.hpp"
+
+namespace zr {
+
+static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+// ----------------------------------------------------------------------------
+// Thiele, one lane per slice.  Samples F[j][i] at nodes X[j], j < nk.
+// Inverse differences phi_{s+1}(x_j) = (x_j - x_s) / (phi_s(x_j) - phi_s(x_s)),
+// b_s = phi_s(x_s); stop at the first m whose continued fraction reproduces the
+// sample at node m+1 (evaluated as a fraction P/Q, so without inverses).
+// Then (A, B) <- (b_m, 1), (A, B) <- (b_s A + (x - x_s) B, A) for s = m-1..0,
+// and scale so that the lowest nonzero coefficient of B is 1.
+// Arrays are SoA [index][T] so that consecutive lanes touch consecutive words.
+// ----------------------------------------------------------------------------
+__global__ void k_thiele(zr_mod M, uint32_t T, uint32_t nk, const uint64_t* __restrict__ X,
+                         const uint64_t* __restrict__ F, uint64_t* __restrict__ A, uint64_t* __restrict__ B,
+                         int32_t* __restrict__ degA, int32_t* __restrict__ degB, int32_t* __restrict__ st,
+                         uint64_t* __restrict__ scratch) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= T) return;
+  uint64_t* phi = scratch;
+  uint64_t* b = phi + (size_t)nk * T;
+  uint64_t* NA = b + (size_t)nk * T;
+#define PHI(j) phi[(size_t)(j) * T + i]
+#define BB(j) b[(size_t)(j) * T + i]
+#define FV(j) F[(size_t)(j) * T + i]
+  for (uint32_t j = 0; j < nk; ++j) PHI(j) = FV(j);
+  BB(0) = PHI(0);
+  uint32_t m = 0;
+  int32_t status = 0;
+  for (;;) {
+    if (m + 1 >= nk) {
+      status = -5;  // samples exhausted without confirmation
+      break;
+    }
+    const uint64_t x = X[m + 1];
+    uint64_t P = BB(m), Q = 1 % M.p;
+    bool ok = true;
+    for (uint32_t s = m; s-- > 0;) {
+      if (P == 0) {
+        ok = false;
+        break;
+      }
+      const uint64_t nP = zr_add(M, zr_mul(M, BB(s), P), zr_mul(M, zr_sub(M, x, X[s]), Q));
+      Q = P;
+      P = nP;
+    }
+    if (ok && P == zr_mul(M, FV(m + 1), Q)) break;
+    const uint64_t pm = PHI(m), xm = X[m];
+    for (uint32_t j = m + 1; j < nk; ++j) {
+      const uint64_t den = zr_sub(M, PHI(j), pm);
+      if (den == 0) {
+        status = -4;
+        break;
+      }
+      PHI(j) = zr_mul(M, zr_sub(M, X[j], xm), zr_inv(M, den));
+    }
+    if (status) break;
+    BB(m + 1) = PHI(m + 1);
+    ++m;
+  }
+  if (status) {
+    st[i] = status;
+    degA[i] = -1;
+    degB[i] = -1;
+    return;
+  }
+#define AA(r) A[(size_t)(r) * T + i]
+#define BQ(r) B[(size_t)(r) * T + i]
+#define NN(r) NA[(size_t)(r) * T + i]
+  const uint32_t cap = nk + 1;
+  for (uint32_t r = 0; r < cap; ++r) {
+    AA(r) = 0;
+    BQ(r) = 0;
+  }
+  AA(0) = BB(m);
+  BQ(0) = 1 % M.p;
+  for (uint32_t s = m; s-- > 0;) {
+    const uint64_t bs = BB(s), xs = X[s];
+    const uint32_t top = std::min(cap - 1, m + 1);
+    for (uint32_t r = 0; r <= top; ++r) {
+      uint64_t v = zr_sub(M, zr_mul(M, bs, AA(r)), zr_mul(M, xs, BQ(r)));
+      if (r > 0) v = zr_add(M, v, BQ(r - 1));
+      NN(r) = v;
+    }
+    for (uint32_t r = 0; r <= top; ++r) {
+      BQ(r) = AA(r);
+      AA(r) = NN(r);
+    }
+  }
+  int32_t da = -1, db = -1;
+  for (uint32_t r = 0; r < cap; ++r) {
+    if (AA(r)) da = (int32_t)r;
+    if (BQ(r)) db = (int32_t)r;
+  }
+  if (db < 0) {
+    st[i] = -4;
+    degA[i] = -1;
+    degB[i] = -1;
+    return;
+  }
+  uint32_t low = 0;
+  while (BQ(low) == 0) ++low;
+  const uint64_t sc = zr_inv(M, BQ(low));
+  for (int32_t r = 0; r <= da; ++r) AA(r) = zr_mul(M, AA(r), sc);
+  for (int32_t r = 0; r <= db; ++r) BQ(r) = zr_mul(M, BQ(r), sc);
+  if (da < 0) da = 0;
+  degA[i] = da;
+  degB[i] = db;
+  st[i] = 0;
+#undef PHI
+#undef BB
+#undef FV
+#undef AA
+#undef BQ
+#undef NN
+}
+
+hipError_t thiele_slices(const zr_mod& M, uint32_t T, uint32_t nk, const uint64_t* X, const uint64_t* F, uint64_t* A,
+                         uint64_t* B, int32_t* degA, int32_t* degB, int32_t* st, uint64_t* scratch, hipStream_t s) {
+  if (T == 0) return hipSuccess;
+  TimedLaunch tl("thiele", s);
+  hipLaunchKernelGGL(k_thiele, dim3(cdiv(T, 64)), dim3(64), 0, s, M, T, nk, X, F, A, B, degA, degB, st, scratch);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Transposed Vandermonde apply out[i] = sum_l a_l m_l^(i+1): one lane per term
+// l walks its power chain over a block of i with a fixed Shoup multiplier; the
+// per-i partial sums are reduced across the wave with lane shuffles and across
+// the workgroup in LDS (the substitution kernel of §2.2 with its warp
+// reduction, on 64-lane wavefronts).
+// ----------------------------------------------------------------------------
+constexpr int kApW = 4;      // waves per workgroup
+constexpr int kApB = 128;    // powers i per workgroup
+
+__device__ __forceinline__ uint64_t wave_sum_mod(const zr_mod& M, uint64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor(v, off, 64);
+    v = zr_add(M, v, o);
+  }
+  return v;
+}
+
+__global__ void __launch_bounds__(kApW * 64) k_vapply(zr_mod M, uint32_t t, const uint64_t* __restrict__ mono,
+                                                      const uint64_t* __restrict__ a, uint32_t T,
+                                                      uint64_t* __restrict__ partial) {
+  __shared__ uint64_t sh[kApW][kApB];
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t l = blockIdx.y * (kApW * 64) + threadIdx.x;
+  const uint32_t i0 = blockIdx.x * kApB;
+  const uint32_t nb = std::min<uint32_t>(kApB, T - i0);
+  uint64_t m = 0, mp = 0, b = 0;
+  if (l < t) {
+    m = mono[l];
+    mp = zr_shoup_pre(M, m);
+    b = zr_mul(M, a[l], zr_pow(M, m, i0 + 1));
+  }
+  for (uint32_t ii = 0; ii < nb; ++ii) {
+    const uint64_t s = wave_sum_mod(M, b);
+    if (lane == 0) sh[wave][ii] = s;
+    b = zr_shoup(M, b, m, mp);
+  }
+  __syncthreads();
+  for (uint32_t ii = threadIdx.x; ii < nb; ii += blockDim.x) {
+    uint64_t s = sh[0][ii];
+    for (int w = 1; w < kApW; ++w) s = zr_add(M, s, sh[w][ii]);
+    partial[(size_t)blockIdx.y * T + i0 + ii] = s;
+  }
+}
+
+__global__ void k_vapply_sum(zr_mod M, uint32_t T, uint32_t nparts, const uint64_t* __restrict__ partial,
+                             uint64_t* __restrict__ out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= T) return;
+  uint64_t s = 0;
+  for (uint32_t c = 0; c < nparts; ++c) s = zr_add(M, s, partial[(size_t)c * T + i]);
+  out[i] = s;
+}
+
+size_t vapply_work_words(uint32_t t, uint32_t T) {
+  return (size_t)std::max<uint32_t>(1, cdiv(t, kApW * 64)) * std::max<uint32_t>(T, 1) + 64;
+}
+
+hipError_t vapply(const zr_mod& M, uint32_t t, const uint64_t* mono, const uint64_t* a, uint32_t T, uint64_t* out,
+                  uint64_t* work, size_t work_words, hipStream_t s) {
+  if (T == 0) return hipSuccess;
+  if (t == 0) return fill_u64(out, 0, T, s);
+  const uint32_t nparts = cdiv(t, kApW * 64);
+  if (work_words < (size_t)nparts * T) return hipErrorInvalidValue;
+  TimedLaunch tl("vapply", s);
+  hipLaunchKernelGGL(k_vapply, dim3(cdiv(T, kApB), nparts), dim3(kApW * 64), 0, s, M, t, mono, a, T, work);
+  hipLaunchKernelGGL(k_vapply_sum, dim3(cdiv(T, 256)), dim3(256), 0, s, M, T, nparts, work, out);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Balancing: beta_i = N_{k-1}(y^i) / A_i(x_0) (fallback D_{k-1}(y^i) / B_i(x_0))
+// and the balanced right-hand sides beta_i A_i(x_j), beta_i B_i(x_j), j >= 1.
+// ----------------------------------------------------------------------------
+__device__ uint64_t horner_col(const zr_mod& M, const uint64_t* c, uint32_t T, uint32_t i, int32_t deg, uint64_t x) {
+  uint64_t v = 0;
+  for (int32_t r = deg; r >= 0; --r) v = zr_add(M, zr_mul(M, v, x), c[(size_t)r * T + i]);
+  return v;
+}
+
+__global__ void k_balance(zr_mod M, uint32_t T, const uint64_t* __restrict__ X, const uint64_t* __restrict__ A,
+                          const uint64_t* __restrict__ B, const int32_t* __restrict__ degA,
+                          const int32_t* __restrict__ degB, const uint64_t* __restrict__ nprev,
+                          const uint64_t* __restrict__ dprev, uint32_t tN, int32_t rhoN, uint64_t* __restrict__ vN,
+                          size_t ldN, uint32_t tD, int32_t rhoD, uint64_t* __restrict__ vD, size_t ldD,
+                          int32_t* __restrict__ st) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= T) return;
+  const int32_t da = degA[i], db = degB[i];
+  const uint64_t a0 = horner_col(M, A, T, i, da, X[0]);
+  const uint64_t b0 = horner_col(M, B, T, i, db, X[0]);
+  uint64_t beta = 0;
+  if (nprev[i] != 0 && a0 != 0) beta = zr_mul(M, nprev[i], zr_inv(M, a0));
+  else if (dprev[i] != 0 && b0 != 0) beta = zr_mul(M, dprev[i], zr_inv(M, b0));
+  else st[i] = -4;
+  if (i < tN)
+    for (int32_t j = 1; j <= rhoN; ++j)
+      vN[(size_t)(j - 1) * ldN + i] = zr_mul(M, beta, horner_col(M, A, T, i, da, X[j]));
+  if (i < tD)
+    for (int32_t j = 1; j <= rhoD; ++j)
+      vD[(size_t)(j - 1) * ldD + i] = zr_mul(M, beta, horner_col(M, B, T, i, db, X[j]));
+}
+
+hipError_t balance_rhs(const zr_mod& M, uint32_t T, uint32_t nk, const uint64_t* X, const uint64_t* A,
+                       const uint64_t* B, const int32_t* degA, const int32_t* degB, const uint64_t* nprev,
+                       const uint64_t* dprev, uint32_t tN, int32_t rhoN, uint64_t* vN, size_t ldN, uint32_t tD,
+                       int32_t rhoD, uint64_t* vD, size_t ldD, int32_t* st, hipStream_t s) {
+  (void)nk;
+  if (T == 0) return hipSuccess;
+  TimedLaunch tl("balance", s);
+  hipLaunchKernelGGL(k_balance, dim3(cdiv(T, 128)), dim3(128), 0, s, M, T, X, A, B, degA, degB, nprev, dprev, tN, rhoN,
+                     vN, ldN, tD, rhoD, vD, ldD, st);
+  return hipGetLastError();
+}
+
+__global__ void k_scale(zr_mod M, uint64_t* v, size_t n, uint64_t c, uint64_t cp) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = zr_shoup(M, v[i], c, cp);
+}
+
+hipError_t scale_u64(const zr_mod& M, uint64_t* v, size_t n, uint64_t c, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale, dim3(cdiv(n, 256)), dim3(256), 0, s, M, v, n, c, zr_shoup_pre(M, c));
+  return hipGetLastError();
+}
+
+}  // namespace zr

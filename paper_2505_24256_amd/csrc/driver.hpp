@@ -1,0 +1,82 @@
+// Host-side pieces of the reconstruction driver shared by the polynomial,
+// balanced and batched paths.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <memory>
+#include <vector>
+
+#include "../../include/zippel.h"
+#include "field.hpp"
+
+namespace zr {
+
+struct Error {
+  int code;
+  explicit Error(int c) : code(c) {}
+};
+
+void check(hipError_t e);
+void h2d(void* d, const void* h, size_t bytes, hipStream_t s);
+void d2h_sync(void* h, const void* d, size_t bytes, hipStream_t s);
+
+// Stream-ordered device allocations released (stream-ordered) on destruction.
+struct DevArena {
+  hipStream_t s;
+  std::vector<void*> ptrs;
+  explicit DevArena(hipStream_t st);
+  ~DevArena();
+  DevArena(const DevArena&) = delete;
+  DevArena& operator=(const DevArena&) = delete;
+  void* raw(size_t bytes);
+  template <class T>
+  T* alloc(size_t n) {
+    return (T*)raw(n * sizeof(T));
+  }
+};
+
+// Validated parameters and the materialised sampling schedule.
+struct Params {
+  uint64_t p;
+  zr_mod M;
+  uint32_t nvars, last, nprobes;
+  std::vector<uint32_t> deg, deg_den, need, nnodes;
+  std::vector<uint64_t> y, anchor, nodes, probes;
+  std::vector<size_t> node_off;
+  Params(const zr_params* P, bool balanced);
+  // anchor of variable v followed by its first count-1 nodes
+  std::vector<uint64_t> node_list(uint32_t v, uint32_t count) const;
+};
+
+// Device-resident skeleton: exponents SoA [nvars][t], coefficients, monomial
+// values m_l = prod_{v<k} y_v^{e_{l,v}} for the next stage.
+struct Skeleton {
+  uint32_t nvars = 0, t = 0;
+  uint16_t* exps = nullptr;
+  uint64_t* coef = nullptr;
+  uint64_t* mono = nullptr;
+  void alloc(DevArena& A, uint32_t nv, uint32_t n);
+};
+
+bool is_prime_u64(uint64_t n);
+void make_schedule(uint64_t p, uint32_t nvars, const uint32_t* nnodes, uint64_t seed, uint32_t nprobes,
+                   uint64_t* y, uint64_t* anchor, uint64_t* nodes, uint64_t* probes);
+std::vector<uint64_t> newton_consts(const zr_mod& M, const std::vector<uint64_t>& X);
+uint32_t target_waves();
+zr_counters& counters();
+void count_solve(uint64_t t, uint64_t R);
+void count_newton(uint64_t t, uint64_t D1);
+
+void call_bb(zr_blackbox_fn bb, void* ctx, const Params& P, uint32_t k, uint64_t ni, const uint64_t* y,
+             const uint64_t* xk, uint64_t nj, uint64_t* d_vals, hipStream_t s);
+uint32_t lift_stage(const Params& P, uint32_t kvar, const Skeleton& S, const uint64_t* d_vals, uint32_t D1,
+                    const std::vector<uint64_t>& X, DevArena& keep, Skeleton& out, hipStream_t s,
+                    int32_t* d_status, int32_t* h_status_out);
+void solve_stage(const Params& P, const Skeleton& S, uint64_t* vals, uint32_t R, hipStream_t s, int32_t* d_status);
+void download(const Skeleton& S, hipStream_t s, zr_poly* out);
+uint64_t eval_at(const Params& P, const Skeleton& S, const uint64_t* pt, const std::vector<uint32_t>& maxdeg,
+                 hipStream_t s);
+uint64_t bb_at(const Params& P, zr_blackbox_fn bb, void* ctx, const uint64_t* pt, hipStream_t s);
+
+}  // namespace zr
