@@ -1,0 +1,186 @@
+#!/usr/bin/env python
+"""Benchmark of the plain polynomial Zippel reconstruction on one MI355X.
+
+Workload: synthetic sparse polynomial, n = 6 variables, per-variable degree
+<= 30, t = 10^4 terms with uniform distinct exponents, coefficients uniform
+mod a seeded 63-bit prime (hidden-polynomial seed 2, schedule seed 1002).
+One step = one full reconstruction (6 stages; Vandermonde systems of size up
+to 10^4 with 30 right-hand sides each, Newton lifts, expansions, 2 probes).
+The black box's samples are computed once on the host, recorded on the device
+and replayed (a device-to-device copy per stage) inside the timed region.
+
+Prints one JSON line.  ``--microbench`` instead prints the throughput probes
+used for the roofline (see include/zippel_microbench.h).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz.  On gfx950 the 32x32->64-bit
+# multiply-add (v_mad_u64_u32) issues at close to the full VALU rate (measured
+# by the throughput probe of include/zippel_microbench.h), so the ceiling is one
+# 32-bit multiply per lane per clock; a 64x64-bit product needs four.
+CU, SIMD, LANES, CLOCK_GHZ = 256, 4, 16, 2.4
+MUL32_PEAK_TOPS = CU * SIMD * LANES * CLOCK_GHZ * 1e9 / 1e12
+MUL32_PER_MULMOD = 4
+
+
+class CachingBox:
+    """Host black box (synth) whose answers are kept for re-use."""
+
+    def __init__(self, inner):
+        self.inner = inner
+        self.cache = {}
+
+    def eval(self, k, i_first, ni, y, anchor, xk):
+        key = (int(k), int(i_first), int(ni), tuple(int(v) for v in y[:max(int(k) - 1, 0)]),
+               tuple(int(v) for v in anchor[int(k):]), tuple(int(v) for v in xk))
+        v = self.cache.get(key)
+        if v is None:
+            v = self.inner.eval(k, i_first, ni, y, anchor, xk)
+            self.cache[key] = v
+        return v
+
+
+def microbench(zr):
+    out = {}
+    for kind in ("add_u32", "mul_lo_u32", "mul_hi_u32", "mad_u64_u32", "mac192", "shoup"):
+        ms, ops = zr.microbench(kind, blocks=2048, iters=4096)
+        out[kind] = {"ms": round(ms, 4), "Gops_per_s": round(ops / ms / 1e6, 1)}
+    ms, nbytes = zr.microbench("copy", blocks=8192, nbytes=2 << 30)
+    out["copy"] = {"ms": round(ms, 4), "GB_per_s": round(nbytes / ms / 1e6, 1), "bytes": nbytes}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--microbench", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=16)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; the reconstruction of independent instances would "
+              "shard across GPUs with no communication, but no multi-GPU run is part of it.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    import paper_2505_24256_amd as zr
+    import synth
+    zr.lib()  # raises if the HIP library is missing
+
+    if args.microbench:
+        print(json.dumps({"microbench": microbench(zr)}), flush=True)
+        return
+
+    w = synth.config_workload(2)
+    cache = CachingBox(synth.BlackBox(w.hidden, nthreads=args.cpu_threads))
+    rec = zr.Recorder(zr.HostBlackBox(cache.eval, w.hidden.nvars))
+    stream = torch.cuda.current_stream()
+
+    # recording run: also checks the result against the hidden polynomial
+    e, c = zr.reconstruct(w.p, w.deg, rec, sched=w.schedule, stream=stream)
+    exact = bool(np.array_equal(e, w.hidden.exps) and np.array_equal(c, w.hidden.coefs))
+    if not exact:
+        print("bench.py: reconstruction does not match the hidden polynomial", file=sys.stderr)
+        sys.exit(3)
+    rec.replay(True)
+    for _ in range(args.warmup):
+        zr.lib().zr_recorder_rewind(rec.handle)
+        zr.reconstruct(w.p, w.deg, rec, sched=w.schedule, stream=stream)
+    cnt = zr.last_counters()
+    torch.cuda.synchronize()
+
+    zr.timing(True)
+    zr.timing_reset()
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        zr.lib().zr_recorder_rewind(rec.handle)
+        e, c = zr.reconstruct(w.p, w.deg, rec, sched=w.schedule, stream=stream)
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    zr.timing(False)
+    exact = exact and bool(np.array_equal(e, w.hidden.exps) and np.array_equal(c, w.hidden.coefs))
+
+    n_dots, ms_dots = zr.timing_get("vs_dots")
+    kernels = {}
+    for name in ("master", "vs_pack", "vs_chain", "vs_scan", "vs_dots", "vs_finish", "newton", "scan", "expand"):
+        n, ms = zr.timing_get(name)
+        if n:
+            kernels[name] = {"launches": n, "ms_total": round(ms, 3)}
+    steps = args.steps
+    mulmods = cnt["mulmods"] * steps
+    value = mulmods / elapsed
+    solve_alg = cnt["solve_mulmods"] * steps          # R t^2 + 2 t (t-1) per system: what vs_dots computes
+    achieved_mulmod_s = solve_alg / (ms_dots / 1e3) if ms_dots else 0.0
+    achieved = achieved_mulmod_s * MUL32_PER_MULMOD / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(MUL32_PEAK_TOPS, 3),
+                "unit": "TOP/s (32x32-bit multiplies; one 64x64-bit modular product or multiply-accumulate = 4)",
+                "frac": round(achieved / MUL32_PEAK_TOPS, 4), "traffic": None,
+                "kernel": "k_vs_dots", "launches_per_step": n_dots // steps if steps else 0,
+                "avg_launch_ms": round(ms_dots / n_dots, 4) if n_dots else None}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        nthr = max(1, min(args.cpu_threads, os.cpu_count() or 1))
+        tc = time.perf_counter()
+        oe, oc = oracle.zippel(w.p, w.deg, w.schedule, cache.eval, nthreads=nthr)
+        tcpu = time.perf_counter() - tc
+        same = bool(np.array_equal(oe, e) and np.array_equal(oc, c))
+        cpu = {"value": round(cnt["mulmods"] / tcpu, 1), "unit": "mulmod/s", "cores": nthr, "kind": "oracle",
+               "sample": "one full reconstruction of the same workload (all 6 stages) with the black box's "
+                         "samples served from the host cache; unsigned __int128 products reduced with %",
+               "seconds": round(tcpu, 2), "matches_gpu": same}
+
+    out = {
+        "metric": "mulmod/s (algorithmic modular products per second, whole reconstruction)",
+        "value": round(value, 1),
+        "unit": "mulmod/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64 mod p (63-bit prime), 128/192-bit integer intermediates",
+        "data": "synthetic",
+        "config": {"workload": "plain polynomial Zippel, n=6, per-variable degree<=30, t=10^4 terms, uniform "
+                               "distinct exponents, coefficients uniform mod a seeded 63-bit prime",
+                   "p": w.p, "stage_sizes": None, "parallelism": "single GPU"},
+        "reconstructions_per_s": round(steps / elapsed, 3),
+        "vandermonde_terms_per_s": round(cnt["vsolve_terms"] * steps / elapsed, 1),
+        "latency_ms": {"p50": round(statistics.median(lat) * 1e3, 3),
+                       "p99": round(float(np.percentile(lat, 99)) * 1e3, 3)},
+        "bit_exact": exact,
+        "mulmods_per_step": cnt["mulmods"],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

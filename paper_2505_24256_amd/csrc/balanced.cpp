@@ -115,6 +115,7 @@ static void reconstruct_balanced(const zr_params* params, zr_blackbox_fn bb, voi
     const uint32_t nk = P.nnodes[kvar] + 1;
     std::vector<uint64_t> X = P.node_list(kvar, nk);
     auto* kp = new DevArena(s);
+    arenas.emplace_back(kp);
     Skeleton nN, nD;
     {
       DevArena A(s);
@@ -153,13 +154,14 @@ static void reconstruct_balanced(const zr_params* params, zr_blackbox_fn bb, voi
         if (v) throw Error(ZR_EDEGEN);
       solve_stage(P, SN, valsN, (uint32_t)rhoN, s, d_status);
       solve_stage(P, SD, valsD, (uint32_t)rhoD, s, d_status);
-      std::vector<uint64_t> XN(X.begin(), X.begin() + D1N), XD(X.begin(), X.begin() + D1D);
-      lift_stage(P, kvar, SN, valsN, D1N, XN, *kp, nN, s, d_status, nullptr);
-      lift_stage(P, kvar, SD, valsD, D1D, XD, *kp, nD, s, d_status, nullptr);
+      std::vector<uint32_t> dn(P.nvars, 0), dd(P.nvars, 0);
+      dn[kvar] = D1N;
+      dd[kvar] = D1D;
+      StageConsts KN(P, A, dn, s), KD(P, A, dd, s);
+      lift_stage(P, kvar, SN, valsN, D1N, KN.W(kvar), KN.ypow(kvar), *kp, nN, s, d_status);
+      lift_stage(P, kvar, SD, valsD, D1D, KD.W(kvar), KD.ypow(kvar), *kp, nD, s, d_status);
     }
-    arenas.front().reset();
     arenas.erase(arenas.begin());
-    arenas.emplace_back(kp);
     SN = nN;
     SD = nD;
     counters().stages = k;
@@ -178,17 +180,7 @@ static void reconstruct_balanced(const zr_params* params, zr_blackbox_fn bb, voi
     const uint64_t ci = zr_inv(P.M, c0);
     check(scale_u64(P.M, SN.coef, SN.t, ci, s));
     check(scale_u64(P.M, SD.coef, SD.t, ci, s));
-    if (P.nprobes) {
-      std::vector<uint32_t> mx(P.nvars);
-      for (uint32_t v = 0; v < P.nvars; ++v) mx[v] = std::max(P.deg[v], P.deg_den[v]);
-      for (uint32_t q = 0; q < P.nprobes; ++q) {
-        const uint64_t* pt = P.probes.data() + (size_t)q * P.nvars;
-        const uint64_t f = bb_at(P, bb, ctx, pt, s);
-        const uint64_t nv = eval_at(P, SN, pt, mx, s);
-        const uint64_t dv = eval_at(P, SD, pt, mx, s);
-        if (nv != zr_mul(P.M, f, dv)) throw Error(ZR_EPROBE);
-      }
-    }
+    if (P.nprobes) check_probes(P, bb, ctx, SN, &SD, s);
   }
   download(SN, s, num);
   download(SD, s, den);

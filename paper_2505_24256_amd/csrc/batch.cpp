@@ -24,10 +24,10 @@ static void solve_batch(size_t nsys, uint64_t p, const uint64_t* h_sys_off, cons
   for (size_t i = 0; i < nsys; ++i) {
     const uint64_t t = h_sys_off[i + 1] - h_sys_off[i];
     tmax = std::max(tmax, t);
-    if (t && h_nrhs[i]) wmax = std::max(wmax, vsolve_workspace_words(vsolve_plan((uint32_t)t, h_nrhs[i], target_waves())));
+    if (t && h_nrhs[i]) wmax = std::max(wmax, vsolve_workspace_words(vsolve_plan((uint32_t)t, h_nrhs[i], device_cus())));
   }
   uint64_t* Mc = A.alloc<uint64_t>(std::max<uint64_t>(tmax, 1));
-  uint64_t* tmp = A.alloc<uint64_t>(std::max<uint64_t>(tmax, 1));
+  uint64_t* tmp = A.alloc<uint64_t>(master_tmp_words((uint32_t)std::max<uint64_t>(tmax, 1)));
   uint64_t* work = A.alloc<uint64_t>(std::max<size_t>(wmax, 1));
   for (size_t i = 0; i < nsys; ++i) {
     const uint32_t t = (uint32_t)(h_sys_off[i + 1] - h_sys_off[i]);
@@ -35,7 +35,7 @@ static void solve_batch(size_t nsys, uint64_t p, const uint64_t* h_sys_off, cons
     if (t == 0 || R == 0) continue;
     const uint64_t* mono = d_mono + h_sys_off[i];
     check(master_poly(M, t, mono, Mc, tmp, s));
-    const VsolvePlan plan = vsolve_plan(t, R, target_waves());
+    const VsolvePlan plan = vsolve_plan(t, R, device_cus());
     check(vsolve(M, plan, mono, Mc, d_rhs + h_rhs_off[i], t, d_out + h_rhs_off[i], t, work, d_status + i, s));
   }
 }

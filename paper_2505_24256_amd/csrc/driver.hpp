@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "../../include/zippel.h"
@@ -62,21 +63,30 @@ struct Skeleton {
 bool is_prime_u64(uint64_t n);
 void make_schedule(uint64_t p, uint32_t nvars, const uint32_t* nnodes, uint64_t seed, uint32_t nprobes,
                    uint64_t* y, uint64_t* anchor, uint64_t* nodes, uint64_t* probes);
-std::vector<uint64_t> newton_consts(const zr_mod& M, const std::vector<uint64_t>& X);
-uint32_t target_waves();
+std::vector<uint32_t> newton_matrix_limbs(const zr_mod& M, const std::vector<uint64_t>& X);
+uint32_t device_cus();
 zr_counters& counters();
 void count_solve(uint64_t t, uint64_t R);
 void count_newton(uint64_t t, uint64_t D1);
 
 void call_bb(zr_blackbox_fn bb, void* ctx, const Params& P, uint32_t k, uint64_t ni, const uint64_t* y,
              const uint64_t* xk, uint64_t nj, uint64_t* d_vals, hipStream_t s);
+// Per-variable device constants (Newton matrix limbs, powers of y_v).
+struct StageConsts {
+  uint32_t* base = nullptr;
+  std::vector<size_t> woff, yoff;  // offsets in 32-bit words
+  StageConsts(const Params& P, DevArena& A, const std::vector<uint32_t>& D1s, hipStream_t s);
+  const uint32_t* W(uint32_t v) const { return base + woff[v]; }
+  const uint64_t* ypow(uint32_t v) const { return (const uint64_t*)(base + yoff[v]); }
+};
+
+int32_t* host_scratch();
 uint32_t lift_stage(const Params& P, uint32_t kvar, const Skeleton& S, const uint64_t* d_vals, uint32_t D1,
-                    const std::vector<uint64_t>& X, DevArena& keep, Skeleton& out, hipStream_t s,
-                    int32_t* d_status, int32_t* h_status_out);
+                    const uint32_t* d_W, const uint64_t* d_ypow, DevArena& keep, Skeleton& out, hipStream_t s,
+                    int32_t* d_status);
+void check_probes(const Params& P, zr_blackbox_fn bb, void* ctx, const Skeleton& N, const Skeleton* D,
+                  hipStream_t s);
 void solve_stage(const Params& P, const Skeleton& S, uint64_t* vals, uint32_t R, hipStream_t s, int32_t* d_status);
 void download(const Skeleton& S, hipStream_t s, zr_poly* out);
-uint64_t eval_at(const Params& P, const Skeleton& S, const uint64_t* pt, const std::vector<uint32_t>& maxdeg,
-                 hipStream_t s);
-uint64_t bb_at(const Params& P, zr_blackbox_fn bb, void* ctx, const uint64_t* pt, hipStream_t s);
 
 }  // namespace zr

@@ -27,30 +27,37 @@ static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b -
 // per wave through the scalar cache.  The length-t vector q_l is never stored.
 // ============================================================================
 
-VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t target_waves) {
+// Right-hand sides per tile: nine accumulator registers each, so that a tile
+// of 20 still leaves room for the chain state within 256 VGPRs.
+constexpr uint32_t kMaxRT = 20;
+
+static uint32_t dots_waves_per_cu(uint32_t RT);
+
+// Chunking: enough (row block, chunk, tile) waves for about four rounds of the
+// device's resident wave slots, so the tail of the launch stays short, with
+// chunks of at least 128 steps.
+VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
   VsolvePlan P;
   P.t = t;
   P.R = R;
-  const uint32_t kMaxRT = 32;
   P.ntile = R == 0 ? 1 : cdiv(R, kMaxRT);
-  uint32_t rt = R == 0 ? 2 : cdiv(R, P.ntile);
-  P.RT = (rt + 1) & ~1u;
-  P.ldv = P.RT * P.ntile;
-  const uint32_t row_waves = std::max<uint32_t>(1, cdiv(t, 64));
-  uint32_t S = std::max<uint32_t>(1, cdiv(target_waves, row_waves * P.ntile));
-  const uint32_t minL = 48;
-  S = std::min<uint32_t>(S, std::max<uint32_t>(1, t / minL));
+  P.RT = R == 0 ? 1 : cdiv(R, P.ntile);
+  P.ldv = (3 * P.RT + 2 + 15) & ~15u;  // 32-bit words per packed row: 3 limbs per value + M_r, 64-byte groups
+  const uint32_t slots = std::max<uint32_t>(1, num_cus) * dots_waves_per_cu(P.RT);
+  const uint32_t row_blocks = std::max<uint32_t>(1, cdiv(t, 64));
+  uint32_t S = std::max<uint32_t>(1, cdiv(4ull * slots, (uint64_t)row_blocks * P.ntile));
+  S = std::min<uint32_t>(S, std::max<uint32_t>(1, t / 128));
   S = std::min<uint32_t>(S, 256);
   P.L = std::max<uint32_t>(1, cdiv(t, S));
   P.S = std::max<uint32_t>(1, cdiv(t, P.L));
   return P;
 }
 
-// workspace layout: VT [t][ldv] | mono_p [t] | Bc [S][t] | qstart [S][t] | mL [t] |
-//                   spart [S][R][t] | hpart [S][t]
+// workspace layout (64-bit words): VT [ntile][t][ldv/2] | mono_p [t] | Bc [S][t] |
+//                   qstart [S][t] | mL [t] | spart [S][R][t] | hpart [S][t] | winv [2t]
 size_t vsolve_workspace_words(const VsolvePlan& P) {
   const size_t t = P.t, S = P.S;
-  return t * P.ldv + t + 2 * S * t + t + S * (size_t)P.R * t + S * t + 64;
+  return P.ntile * t * (P.ldv / 2) + t + 2 * S * t + t + S * (size_t)P.R * t + S * t + 2 * t + 64;
 }
 
 struct VsArgs {
@@ -71,14 +78,31 @@ __device__ __forceinline__ void chunk_range(uint32_t t, uint32_t L, uint32_t c, 
   lo = hi > L ? hi - L : 0;
 }
 
-__global__ void k_pack(uint32_t t, uint32_t R, uint32_t ldv, const uint64_t* __restrict__ rhs, size_t ld_rhs,
-                       uint64_t* __restrict__ VT, const uint64_t* __restrict__ mono, uint64_t* __restrict__ mono_p,
+// Packed row r of tile `tile` (32-bit words): for jj < RT the value
+// v = v^(tile*RT + jj)_{r+1} as three limbs v & (2^22-1), (v >> 22) & (2^22-1),
+// v >> 44 at words 3jj..3jj+2; M_r at words 3RT, 3RT+1; zero padding.
+__global__ void k_pack(uint32_t t, uint32_t R, uint32_t RT, uint32_t ntile, uint32_t ldv,
+                       const uint64_t* __restrict__ rhs, size_t ld_rhs, const uint64_t* __restrict__ Mc,
+                       uint32_t* __restrict__ VT, const uint64_t* __restrict__ mono, uint64_t* __restrict__ mono_p,
                        zr_mod M) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t total = (size_t)t * ldv;
+  const size_t total = (size_t)ntile * t * ldv;
   if (idx < total) {
-    const uint32_t r = (uint32_t)(idx / ldv), j = (uint32_t)(idx % ldv);
-    VT[idx] = j < R ? rhs[(size_t)j * ld_rhs + r] : 0;
+    const uint32_t w = (uint32_t)(idx % ldv);
+    const size_t rest = idx / ldv;
+    const uint32_t r = (uint32_t)(rest % t), tile = (uint32_t)(rest / t);
+    uint32_t out = 0;
+    if (w < 3 * RT) {
+      const uint32_t jj = w / 3, limb = w % 3;
+      const uint32_t j = tile * RT + jj;
+      const uint64_t v = j < R ? rhs[(size_t)j * ld_rhs + r] : 0;
+      out = (uint32_t)((v >> (22 * limb)) & (limb < 2 ? 0x3FFFFFu : 0xFFFFFFFFu));
+    } else if (w == 3 * RT) {
+      out = (uint32_t)Mc[r];
+    } else if (w == 3 * RT + 1) {
+      out = (uint32_t)(Mc[r] >> 32);
+    }
+    VT[idx] = out;
   }
   if (idx < t) mono_p[idx] = zr_shoup_pre(M, mono[idx]);
 }
@@ -111,66 +135,247 @@ __global__ void k_vs_scan(VsArgs a, uint64_t* __restrict__ qstart, uint64_t* __r
   }
 }
 
+// Exact sum of 64x64-bit products in column form.  With q = q0 + q1 2^32 and
+// v = v0 + v1 2^32 (32-bit halves),
+//     q v = q0 v0 + (q0 v1 + q1 v0) 2^32 + q1 v1 2^64,
+// and each column is accumulated in 64 bits by v_mad_u64_u32 (32x32 product
+// plus 64-bit addend, carry out); the carries are counted in 32-bit registers.
+// The represented value is  A + B 2^32 + (C + KA) 2^64 + KB 2^96 + KC 2^128,
+// exact for up to 2^32 terms: 4 multiplies and 4 carry additions per term,
+// nine registers per right-hand side, one reduction mod p at the end.
+struct ColAcc {
+  uint64_t A, B, C;
+  uint32_t KA, KB, KC;
+};
+
+__device__ __forceinline__ void col_zero(ColAcc& a) {
+  a.A = 0;
+  a.B = 0;
+  a.C = 0;
+  a.KA = 0;
+  a.KB = 0;
+  a.KC = 0;
+}
+
+// The four products write distinct carry registers; each carry is consumed
+// three instructions after it is produced.  v0, v1 are wave-uniform (SGPR).
+__device__ __forceinline__ void col_mac(ColAcc& a, uint32_t q0, uint32_t q1, uint32_t v0, uint32_t v1) {
+  uint64_t c0, c1, c2, c3, d;
+  asm("v_mad_u64_u32 %[A], %[c0], %[q0], %[v0], %[A]\n\t"
+      "v_mad_u64_u32 %[B], %[c1], %[q0], %[v1], %[B]\n\t"
+      "v_mad_u64_u32 %[C], %[c3], %[q1], %[v1], %[C]\n\t"
+      "v_mad_u64_u32 %[B], %[c2], %[q1], %[v0], %[B]\n\t"
+      "v_addc_co_u32_e64 %[KA], %[d], 0, %[KA], %[c0]\n\t"
+      "v_addc_co_u32_e64 %[KB], %[d], 0, %[KB], %[c1]\n\t"
+      "v_addc_co_u32_e64 %[KC], %[d], 0, %[KC], %[c3]\n\t"
+      "v_addc_co_u32_e64 %[KB], %[d], 0, %[KB], %[c2]"
+      : [A] "+v"(a.A), [B] "+v"(a.B), [C] "+v"(a.C), [KA] "+v"(a.KA), [KB] "+v"(a.KB), [KC] "+v"(a.KC),
+        [c0] "=&s"(c0), [c1] "=&s"(c1), [c2] "=&s"(c2), [c3] "=&s"(c3), [d] "=&s"(d)
+      : [q0] "v"(q0), [q1] "v"(q1), [v0] "s"(v0), [v1] "s"(v1));
+}
+
+__device__ __forceinline__ uint64_t col_reduce(const zr_mod& M, const ColAcc& a) {
+  uint64_t w0 = a.A, w1, w2 = 0;
+  const uint64_t bl = a.B << 32, bh = a.B >> 32;
+  w0 += bl;
+  w1 = bh + (w0 < bl);
+  w1 += a.C;
+  w2 += w1 < a.C;
+  w1 += a.KA;
+  w2 += w1 < (uint64_t)a.KA;
+  const uint64_t kb = (uint64_t)a.KB << 32;
+  w1 += kb;
+  w2 += w1 < kb;
+  w2 += a.KC;
+  uint64_t r = zr_mod128(M, 0, w2);
+  r = zr_mod128(M, r, w1);
+  return zr_mod128(M, r, w0);
+}
+
+// Carry-free exact dot products.  q = q0 + q1 2^32 (32-bit halves, per lane)
+// and v = v0 + v1 2^22 + v2 2^44 (22-bit limbs, packed once per system), so
+//   q v = q0 v0 + q0 v1 2^22 + q1 v0 2^32 + q0 v2 2^44 + q1 v1 2^54 + q1 v2 2^76,
+// six 32x32 products below 2^54, each summed by one v_mad_u64_u32 into its own
+// 64-bit column.  A column absorbs 1024 such products; every kFold steps the
+// bits above each column's range are moved into the column of matching weight
+// (exact shifts and adds), so chunks of any length stay exact.
+struct Acc6 {
+  uint64_t w0, w22, w32, w44, w54, w76;
+};
+constexpr uint32_t kFold = 512;
+
+__device__ __forceinline__ void acc6_zero(Acc6& a) {
+  a.w0 = a.w22 = a.w32 = a.w44 = a.w54 = a.w76 = 0;
+}
+
+__device__ __forceinline__ void acc6_mac(Acc6& a, uint32_t q0, uint32_t q1, uint32_t v0, uint32_t v1, uint32_t v2) {
+  a.w0 += (uint64_t)q0 * v0;
+  a.w22 += (uint64_t)q0 * v1;
+  a.w44 += (uint64_t)q0 * v2;
+  a.w32 += (uint64_t)q1 * v0;
+  a.w54 += (uint64_t)q1 * v1;
+  a.w76 += (uint64_t)q1 * v2;
+}
+
+// Move everything above bit 54 of each weight-0..44 column into w54, and
+// everything above bit 22 of w54 into w76.
+__device__ __forceinline__ void acc6_fold(Acc6& a) {
+  a.w54 += (a.w0 >> 54) + (a.w22 >> 32) + (a.w32 >> 22) + (a.w44 >> 10);
+  a.w0 &= (1ull << 54) - 1;
+  a.w22 &= (1ull << 32) - 1;
+  a.w32 &= (1ull << 22) - 1;
+  a.w44 &= (1ull << 10) - 1;
+  a.w76 += a.w54 >> 22;
+  a.w54 &= (1ull << 22) - 1;
+}
+
+// add x * 2^s (x < 2^64, s < 128) to the 192-bit (w[0], w[1], w[2])
+__device__ __forceinline__ void add_shift192(uint64_t w[3], uint64_t x, uint32_t s) {
+  const uint32_t o = s >> 6, b = s & 63;
+  const zr_u128 v = ((zr_u128)x) << b;
+  const uint64_t lo = (uint64_t)v, hi = (uint64_t)(v >> 64);
+  if (o == 0) {
+    zr_u128 t = (zr_u128)w[0] + lo;
+    w[0] = (uint64_t)t;
+    t = (zr_u128)w[1] + hi + (uint64_t)(t >> 64);
+    w[1] = (uint64_t)t;
+    w[2] += (uint64_t)(t >> 64);
+  } else {
+    zr_u128 t = (zr_u128)w[1] + lo;
+    w[1] = (uint64_t)t;
+    w[2] += hi + (uint64_t)(t >> 64);
+  }
+}
+
+__device__ __forceinline__ uint64_t acc6_reduce(const zr_mod& M, const Acc6& a) {
+  uint64_t w[3] = {0, 0, 0};
+  add_shift192(w, a.w0, 0);
+  add_shift192(w, a.w22, 22);
+  add_shift192(w, a.w32, 32);
+  add_shift192(w, a.w44, 44);
+  add_shift192(w, a.w54, 54);
+  add_shift192(w, a.w76, 76);
+  uint64_t r = zr_mod128(M, 0, w[2]);
+  r = zr_mod128(M, r, w[1]);
+  return zr_mod128(M, r, w[0]);
+}
+
 // Pass 2: chain + Horner + RT right-hand-side dot products over one chunk.
+// One lane per row.  Packed row r of a tile is identical for all lanes: each
+// 64-byte group of it is one scalar load, issued for step r-1 as soon as step
+// r has consumed the group, so its latency hides behind the remaining work.
+struct alignas(64) VGroup {
+  uint32_t w[16];
+};
+
 template <int RT>
-__global__ void __launch_bounds__(256) k_vs_dots(VsArgs a) {
-  const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(64) k_vs_dots(VsArgs a) {
+  constexpr int LDV = (3 * RT + 2 + 15) & ~15;
+  constexpr int G = LDV / 16;
+  const uint32_t l0 = blockIdx.x * 64 + threadIdx.x;
   const uint32_t c = blockIdx.y;
   const uint32_t tile = blockIdx.z;
-  if (l >= a.t) return;
+  const bool live = l0 < a.t;
+  const uint32_t l = live ? l0 : a.t - 1;
   uint32_t lo, hi;
   chunk_range(a.t, a.L, c, lo, hi);
   const zr_mod M = a.M;
   const uint64_t m = a.mono[l], mp = a.mono_p[l];
   uint64_t q = a.qstart ? a.qstart[(size_t)c * a.t + l] : 1 % M.p;
   uint64_t h = 0;
-  zr_acc192 acc[RT];
+  Acc6 acc[RT];
 #pragma unroll
-  for (int j = 0; j < RT; ++j) zr_acc_zero(acc[j]);
-  const uint64_t* __restrict__ VT = a.VT + (size_t)tile * RT;
-  for (uint32_t r = hi; r-- > lo;) {
-    const uint64_t* __restrict__ v = VT + (size_t)r * a.ldv;
+  for (int j = 0; j < RT; ++j) acc6_zero(acc[j]);
+  const VGroup* __restrict__ rows = (const VGroup*)((const uint32_t*)a.VT + (size_t)tile * a.t * LDV);
+  const bool horner = tile == 0;
+  uint32_t r = hi - 1;
+  uint32_t since = 0;
+  VGroup buf[G];
 #pragma unroll
-    for (int j = 0; j < RT; ++j) zr_acc_mac(acc[j], q, v[j]);
-    h = zr_add(M, zr_shoup(M, h, m, mp), q);
-    q = zr_add(M, zr_shoup(M, q, m, mp), a.Mc[r]);
+  for (int g = 0; g < G; ++g) buf[g] = rows[(size_t)r * G + g];
+  for (;;) {
+    const uint32_t rn = r > lo ? r - 1 : r;
+    const uint32_t q0 = (uint32_t)q, q1 = (uint32_t)(q >> 32);
+    uint32_t mlo = 0, mhi = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+#pragma unroll
+      for (int jj = 0; jj < RT; ++jj) {
+        if (3 * jj / 16 == g) {
+          // the three limbs of value jj may straddle two groups
+          const int w0 = 3 * jj, w1 = 3 * jj + 1, w2 = 3 * jj + 2;
+          const uint32_t v0 = buf[w0 / 16].w[w0 % 16];
+          const uint32_t v1 = buf[w1 / 16].w[w1 % 16];
+          const uint32_t v2 = buf[w2 / 16].w[w2 % 16];
+          acc6_mac(acc[jj], q0, q1, v0, v1, v2);
+        }
+      }
+      if ((3 * RT) / 16 == g) mlo = buf[g].w[(3 * RT) % 16];
+      if ((3 * RT + 1) / 16 == g) mhi = buf[g].w[(3 * RT + 1) % 16];
+      // every later read of this step lies in groups > g (a value's limbs
+      // only extend forward), so group g can be refilled for step r-1 now
+      buf[g] = rows[(size_t)rn * G + g];
+    }
+    const uint64_t Mr = ((uint64_t)mhi << 32) | mlo;
+    if (horner) h = zr_add(M, zr_shoup(M, h, m, mp), q);
+    q = zr_add(M, zr_shoup(M, q, m, mp), Mr);
+    if (++since == kFold) {
+#pragma unroll
+      for (int j = 0; j < RT; ++j) acc6_fold(acc[j]);
+      since = 0;
+    }
+    if (r == lo) break;
+    r = rn;
   }
+  if (!live) return;
   const uint32_t j0 = tile * RT;
 #pragma unroll
   for (int j = 0; j < RT; ++j)
-    if (j0 + j < a.R) a.spart[((size_t)c * a.R + j0 + j) * a.t + l] = zr_acc_reduce(M, acc[j]);
-  if (tile == 0) a.hpart[(size_t)c * a.t + l] = h;
+    if (j0 + j < a.R) a.spart[((size_t)c * a.R + j0 + j) * a.t + l] = acc6_reduce(M, acc[j]);
+  if (horner) a.hpart[(size_t)c * a.t + l] = h;
 }
 
-// Combine chunks: delta by Horner over chunk partials, s by sums, a = s / (m delta).
-__global__ void k_vs_finish(VsArgs a, const uint64_t* __restrict__ mLv, uint64_t* __restrict__ out, size_t ld_out,
-                            int32_t* __restrict__ status) {
+// Combine chunks, part 1 (one lane per row): delta = sum_c m^{lo_c} H_c by
+// Horner over the chunk partials, w = m delta, and its inverse (with Shoup
+// constant) into winv[2t]; a zero w marks the system singular.
+__global__ void k_vs_delta(VsArgs a, const uint64_t* __restrict__ mLv, uint64_t* __restrict__ winv,
+                           int32_t* __restrict__ status) {
   const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= a.t) return;
   const zr_mod M = a.M;
   const uint64_t m = a.mono[l];
   uint64_t delta = a.hpart[l];
   if (a.S > 1) {
-    const uint64_t mL = mLv[l];
+    const uint64_t mL = mLv[l], mLp = zr_shoup_pre(M, mL);
     const uint32_t len_last = a.t - (a.S - 1) * a.L;
     const uint64_t mlast = zr_pow(M, m, len_last);
     for (uint32_t c = 1; c < a.S; ++c) {
-      const uint64_t w = (c + 1 < a.S) ? mL : mlast;
-      delta = zr_add(M, zr_mul(M, delta, w), a.hpart[(size_t)c * a.t + l]);
+      const uint64_t hc = a.hpart[(size_t)c * a.t + l];
+      delta = (c + 1 < a.S) ? zr_add(M, zr_shoup(M, delta, mL, mLp), hc) : zr_add(M, zr_mul(M, delta, mlast), hc);
     }
   }
   const uint64_t w = zr_mul(M, m, delta);
   if (w == 0) {
     atomicExch(status, -3);  // ZR_ESINGULAR
-    for (uint32_t j = 0; j < a.R; ++j) out[(size_t)j * ld_out + l] = 0;
+    winv[l] = 0;
+    winv[a.t + l] = 0;
     return;
   }
-  const uint64_t wi = zr_inv(M, w), wip = zr_shoup_pre(M, wi);
-  for (uint32_t j = 0; j < a.R; ++j) {
-    uint64_t s = a.spart[(size_t)j * a.t + l];
-    for (uint32_t c = 1; c < a.S; ++c) s = zr_add(M, s, a.spart[((size_t)c * a.R + j) * a.t + l]);
-    out[(size_t)j * ld_out + l] = zr_shoup(M, s, wi, wip);
-  }
+  const uint64_t wi = zr_inv(M, w);
+  winv[l] = wi;
+  winv[a.t + l] = zr_shoup_pre(M, wi);
+}
+
+// Combine chunks, part 2 (one lane per row and right-hand side):
+// a^(j)_l = (sum_c s^(j)_{l,c}) / (m_l delta_l).
+__global__ void k_vs_scale(VsArgs a, const uint64_t* __restrict__ winv, uint64_t* __restrict__ out, size_t ld_out) {
+  const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t j = blockIdx.y;
+  if (l >= a.t) return;
+  const zr_mod M = a.M;
+  uint64_t s = 0;
+  for (uint32_t c = 0; c < a.S; ++c) s = zr_add(M, s, a.spart[((size_t)c * a.R + j) * a.t + l]);
+  out[(size_t)j * ld_out + l] = zr_shoup(M, s, winv[l], winv[a.t + l]);
 }
 
 typedef void (*DotsKernel)(VsArgs);
@@ -179,25 +384,23 @@ static DotsKernel dots_ptr() {
   return k_vs_dots<RT>;
 }
 static DotsKernel dots_kernel(uint32_t RT) {
-  switch (RT) {
-    case 2: return dots_ptr<2>();
-    case 4: return dots_ptr<4>();
-    case 6: return dots_ptr<6>();
-    case 8: return dots_ptr<8>();
-    case 10: return dots_ptr<10>();
-    case 12: return dots_ptr<12>();
-    case 14: return dots_ptr<14>();
-    case 16: return dots_ptr<16>();
-    case 18: return dots_ptr<18>();
-    case 20: return dots_ptr<20>();
-    case 22: return dots_ptr<22>();
-    case 24: return dots_ptr<24>();
-    case 26: return dots_ptr<26>();
-    case 28: return dots_ptr<28>();
-    case 30: return dots_ptr<30>();
-    case 32: return dots_ptr<32>();
-    default: return nullptr;
+  static const DotsKernel table[kMaxRT + 1] = {
+      nullptr,        dots_ptr<1>(),  dots_ptr<2>(),  dots_ptr<3>(),  dots_ptr<4>(),  dots_ptr<5>(),
+      dots_ptr<6>(),  dots_ptr<7>(),  dots_ptr<8>(),  dots_ptr<9>(),  dots_ptr<10>(), dots_ptr<11>(),
+      dots_ptr<12>(), dots_ptr<13>(), dots_ptr<14>(), dots_ptr<15>(), dots_ptr<16>(), dots_ptr<17>(),
+      dots_ptr<18>(), dots_ptr<19>(), dots_ptr<20>()};
+  return RT >= 1 && RT <= kMaxRT ? table[RT] : nullptr;
+}
+
+static uint32_t dots_waves_per_cu(uint32_t RT) {
+  static int cache[kMaxRT + 1] = {0};
+  if (RT < 1 || RT > kMaxRT) return 8;
+  if (!cache[RT]) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, dots_kernel(RT), 64, 0) != hipSuccess || nb <= 0) nb = 8;
+    cache[RT] = nb;
   }
+  return (uint32_t)cache[RT];
 }
 
 hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, const uint64_t* Mc, const uint64_t* rhs,
@@ -205,7 +408,7 @@ hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, co
   if (P.t == 0) return hipSuccess;
   const size_t t = P.t, S = P.S;
   uint64_t* VT = work;
-  uint64_t* mono_p = VT + t * P.ldv;
+  uint64_t* mono_p = VT + P.ntile * t * (P.ldv / 2);
   uint64_t* Bc = mono_p + t;
   uint64_t* qstart = Bc + S * t;
   uint64_t* mL = qstart + S * t;
@@ -227,10 +430,10 @@ hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, co
   a.spart = spart;
   a.hpart = hpart;
   {
-    const size_t total = std::max<size_t>(t * P.ldv, t);
+    const size_t total = std::max<size_t>(P.ntile * t * P.ldv, t);  // 32-bit words
     TimedLaunch tl("vs_pack", s);
-    hipLaunchKernelGGL(k_pack, dim3(cdiv(total, 256)), dim3(256), 0, s, P.t, P.R, P.ldv, rhs, ld_rhs, VT, mono,
-                       mono_p, M);
+    hipLaunchKernelGGL(k_pack, dim3(cdiv(total, 256)), dim3(256), 0, s, P.t, P.R, P.RT, P.ntile, P.ldv, rhs, ld_rhs,
+                       Mc, (uint32_t*)VT, mono, mono_p, M);
   }
   if (S > 1) {
     {
@@ -250,7 +453,9 @@ hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, co
   }
   {
     TimedLaunch tl("vs_finish", s);
-    hipLaunchKernelGGL(k_vs_finish, dim3(cdiv(t, 256)), dim3(256), 0, s, a, mL, out, ld_out, status);
+    uint64_t* winv = hpart + S * t;
+    hipLaunchKernelGGL(k_vs_delta, dim3(cdiv(t, 256)), dim3(256), 0, s, a, mL, winv, status);
+    hipLaunchKernelGGL(k_vs_scale, dim3(cdiv(t, 256), P.R), dim3(256), 0, s, a, winv, out, ld_out);
   }
   return hipGetLastError();
 }
@@ -289,6 +494,68 @@ __global__ void k_master_level(zr_mod M, uint32_t t, uint32_t half, const uint64
   nxt[g] = zr_acc_reduce(M, acc);
 }
 
+// Large levels (factors of degree >= 32): a wave owns 64 consecutive output
+// coefficients of one product and one chunk of the convolution index i; the
+// factor L_i is wave-uniform (scalar load), R_{k-i} is a coalesced vector load.
+// Chunk partial sums go to part[ic][g]; k_master_sum adds them and the two
+// terms contributed by the leading ones.
+__global__ void __launch_bounds__(64) k_master_conv(zr_mod M, uint32_t t, uint32_t half, uint32_t IC,
+                                                    const uint64_t* __restrict__ cur, uint64_t* __restrict__ part) {
+  const uint32_t g0 = blockIdx.x * 64;
+  const uint32_t g = g0 + threadIdx.x;
+  const uint32_t ic = blockIdx.y;
+  const uint32_t a = (g0 / (2 * half)) * (2 * half);  // one product per wave since 2*half >= 64
+  const uint32_t n1 = std::min(half, t - a);
+  const uint32_t n2 = std::min(half, t - a - n1);
+  const uint32_t k0 = g0 - a;
+  const uint32_t k = g - a;
+  const uint64_t* __restrict__ Lc = cur + a;
+  const uint64_t* __restrict__ Rc = cur + a + n1;
+  ColAcc acc;
+  col_zero(acc);
+  if (n2 > 0) {
+    // i range of the wave within this chunk
+    uint32_t ilo = ic * IC;
+    uint32_t ihi = std::min(ilo + IC, n1);  // exclusive
+    const uint32_t wlo = k0 + 1 > n2 ? k0 + 1 - n2 : 0;
+    const uint32_t whi = std::min(k0 + 64, n1);  // exclusive: i <= k0+63
+    ilo = std::max(ilo, wlo);
+    ihi = std::min(ihi, whi);
+    for (uint32_t i = ilo; i < ihi; ++i) {
+      const uint64_t Li = Lc[i];
+      const bool ok = g < t && i <= k && k - i < n2;
+      const uint64_t Rv = ok ? Rc[k - i] : 0;
+      col_mac(acc, (uint32_t)Rv, (uint32_t)(Rv >> 32), (uint32_t)Li, (uint32_t)(Li >> 32));
+    }
+  }
+  if (g < t) part[(size_t)ic * t + g] = col_reduce(M, acc);
+}
+
+__global__ void k_master_sum(zr_mod M, uint32_t t, uint32_t half, uint32_t nic, const uint64_t* __restrict__ cur,
+                             const uint64_t* __restrict__ part, uint64_t* __restrict__ nxt) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= t) return;
+  const uint32_t a = (g / (2 * half)) * (2 * half);
+  const uint32_t n1 = std::min(half, t - a);
+  const uint32_t n2 = std::min(half, t - a - n1);
+  const uint32_t k = g - a;
+  uint64_t s = 0;
+  for (uint32_t ic = 0; ic < nic; ++ic) s = zr_add(M, s, part[(size_t)ic * t + g]);
+  if (k >= n1) s = zr_add(M, s, cur[a + n1 + (k - n1)]);
+  if (k >= n2) s = zr_add(M, s, cur[a + (k - n2)]);
+  nxt[g] = s;
+}
+
+size_t master_tmp_words(uint32_t t) {
+  // t for the ping-pong level array plus chunk partials of the large levels
+  uint32_t nic_max = 1;
+  for (uint32_t half = 32; half < t; half *= 2) {
+    const uint32_t IC = std::max<uint32_t>(256, cdiv(half, 32));
+    nic_max = std::max(nic_max, cdiv(half, IC));
+  }
+  return (size_t)t + (size_t)nic_max * t + 64;
+}
+
 hipError_t master_poly(const zr_mod& M, uint32_t t, const uint64_t* mono, uint64_t* Mc, uint64_t* tmp,
                        hipStream_t s) {
   if (t == 0) return hipSuccess;
@@ -297,66 +564,75 @@ hipError_t master_poly(const zr_mod& M, uint32_t t, const uint64_t* mono, uint64
   uint32_t levels = 0;
   for (uint32_t half = 1; half < t; half *= 2) ++levels;
   uint64_t* bufs[2] = {Mc, tmp};
+  uint64_t* part = tmp + t;
   uint64_t* cur = bufs[levels % 2];
   hipLaunchKernelGGL(k_master_leaf, dim3(cdiv(t, 256)), dim3(256), 0, s, M, t, mono, cur);
   uint32_t lev = 0;
   for (uint32_t half = 1; half < t; half *= 2, ++lev) {
     uint64_t* nxt = bufs[(levels - lev - 1) % 2];
-    hipLaunchKernelGGL(k_master_level, dim3(cdiv(t, 128)), dim3(128), 0, s, M, t, half, cur, nxt);
+    if (half < 32) {
+      hipLaunchKernelGGL(k_master_level, dim3(cdiv(t, 128)), dim3(128), 0, s, M, t, half, cur, nxt);
+    } else {
+      const uint32_t IC = std::max<uint32_t>(256, cdiv(half, 32));
+      const uint32_t nic = cdiv(half, IC);
+      hipLaunchKernelGGL(k_master_conv, dim3(cdiv(t, 64), nic), dim3(64), 0, s, M, t, half, IC, cur, part);
+      hipLaunchKernelGGL(k_master_sum, dim3(cdiv(t, 256)), dim3(256), 0, s, M, t, half, nic, cur, part, nxt);
+    }
     cur = nxt;
   }
   return hipGetLastError();
 }
 
 // ============================================================================
-// Newton lift (eq. 1): per term, values at nodes x_0..x_{D} -> divided
-// differences -> monomial coefficients.  Node constants are uniform (Shoup
-// multipliers shared by all lanes); per-lane arrays live in LDS.
+// Newton lift (eq. 1).  Interpolating values a_0..a_D at fixed nodes into
+// monomial coefficients is linear: g = W a with W the inverse of the
+// Vandermonde matrix of the nodes, the same for every term of a stage.  The
+// host builds W by running Newton's divided differences and nested expansion
+// on unit vectors; here each lane owns one term and DB output coefficients,
+// and the products are the carry-free 64x64-bit sums of the solve.
+// Wl: [i][d][3] 22-bit limbs of W[d][i].
 // ============================================================================
 
-constexpr int kNewtonBlock = 64;
+constexpr int kNewtonDB = 8;
 
-__global__ void __launch_bounds__(kNewtonBlock) k_newton(zr_mod M, uint32_t t, uint32_t D1,
-                                                         const uint64_t* __restrict__ vals,
-                                                         const uint64_t* __restrict__ consts,
-                                                         uint64_t* __restrict__ g, uint32_t* __restrict__ cnt) {
-  extern __shared__ uint64_t sh[];
+__global__ void __launch_bounds__(64) k_newton_mat(zr_mod M, uint32_t t, uint32_t D1,
+                                                   const uint64_t* __restrict__ vals,
+                                                   const uint32_t* __restrict__ Wl, uint64_t* __restrict__ g) {
+  const uint32_t l0 = blockIdx.x * 64 + threadIdx.x;
+  const bool live = l0 < t;
+  const uint32_t l = live ? l0 : t - 1;
+  const uint32_t d0 = blockIdx.y * kNewtonDB;
+  Acc6 acc[kNewtonDB];
+#pragma unroll
+  for (int e = 0; e < kNewtonDB; ++e) acc6_zero(acc[e]);
+  for (uint32_t i = 0; i < D1; ++i) {
+    const uint64_t v = vals[(size_t)i * t + l];
+    const uint32_t v0 = (uint32_t)v, v1 = (uint32_t)(v >> 32);
+    const uint32_t* __restrict__ w = Wl + ((size_t)i * D1 + d0) * 3;
+#pragma unroll
+    for (int e = 0; e < kNewtonDB; ++e)
+      if (d0 + e < D1) acc6_mac(acc[e], v0, v1, w[3 * e], w[3 * e + 1], w[3 * e + 2]);
+  }
+  if (!live) return;
+#pragma unroll
+  for (int e = 0; e < kNewtonDB; ++e)
+    if (d0 + e < D1) g[(size_t)(d0 + e) * t + l] = acc6_reduce(M, acc[e]);
+}
+
+__global__ void k_count_nz(uint32_t t, uint32_t D1, const uint64_t* __restrict__ g, uint32_t* __restrict__ cnt) {
   const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= t) return;
-  uint64_t* c = sh + threadIdx.x;  // c[i] at c[i * kNewtonBlock]
-  const uint64_t* x = consts;
-  const uint64_t* xp = consts + D1;
-  const uint64_t* invd = consts + 2 * D1;
-  const uint64_t* invdp = invd + (size_t)D1 * D1;
-  for (uint32_t i = 0; i < D1; ++i) c[i * kNewtonBlock] = vals[(size_t)i * t + l];
-  for (uint32_t j = 1; j < D1; ++j)
-    for (uint32_t i = D1 - 1; i >= j; --i) {
-      const uint64_t d = zr_sub(M, c[i * kNewtonBlock], c[(i - 1) * kNewtonBlock]);
-      c[i * kNewtonBlock] = zr_shoup(M, d, invd[j * D1 + i], invdp[j * D1 + i]);
-    }
-  // expand the nested form from the inside; position q holds the coefficient
-  // of z^(q-i) of the partial polynomial after step i
-  for (uint32_t i = D1 - 1; i-- > 0;)
-    for (uint32_t q = i; q + 1 < D1; ++q) {
-      const uint64_t u = zr_shoup(M, c[(q + 1) * kNewtonBlock], x[i], xp[i]);
-      c[q * kNewtonBlock] = zr_sub(M, c[q * kNewtonBlock], u);
-    }
   uint32_t n = 0;
-  for (uint32_t i = 0; i < D1; ++i) {
-    const uint64_t v = c[i * kNewtonBlock];
-    g[(size_t)i * t + l] = v;
-    n += v != 0;
-  }
+  for (uint32_t d = 0; d < D1; ++d) n += g[(size_t)d * t + l] != 0;
   cnt[l] = n;
 }
 
-hipError_t newton_lift(const zr_mod& M, uint32_t t, uint32_t D1, const uint64_t* vals, const uint64_t* consts,
+hipError_t newton_lift(const zr_mod& M, uint32_t t, uint32_t D1, const uint64_t* vals, const uint32_t* Wl,
                        uint64_t* g, uint32_t* cnt, hipStream_t s) {
   if (t == 0) return hipSuccess;
   TimedLaunch tl("newton", s);
-  const size_t shmem = (size_t)D1 * kNewtonBlock * sizeof(uint64_t);
-  hipLaunchKernelGGL(k_newton, dim3(cdiv(t, kNewtonBlock)), dim3(kNewtonBlock), shmem, s, M, t, D1, vals, consts, g,
-                     cnt);
+  hipLaunchKernelGGL(k_newton_mat, dim3(cdiv(t, 64), cdiv(D1, kNewtonDB)), dim3(64), 0, s, M, t, D1, vals, Wl, g);
+  hipLaunchKernelGGL(k_count_nz, dim3(cdiv(t, 256)), dim3(256), 0, s, t, D1, g, cnt);
   return hipGetLastError();
 }
 
@@ -555,7 +831,18 @@ struct TimingState {
     hipEvent_t e0, e1;
   };
   std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;  // recycled events
   std::unordered_map<std::string, std::pair<uint64_t, double>> totals;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
   void resolve() {
     for (auto& p : pending) {
       (void)hipEventSynchronize(p.e1);
@@ -564,8 +851,8 @@ struct TimingState {
       auto& e = totals[p.name];
       e.first += 1;
       e.second += ms;
-      (void)hipEventDestroy(p.e0);
-      (void)hipEventDestroy(p.e1);
+      pool.push_back(p.e0);
+      pool.push_back(p.e1);
     }
     pending.clear();
   }
@@ -575,8 +862,11 @@ static TimingState g_timing;
 TimedLaunch::TimedLaunch(const char* n, hipStream_t st) : name(n), s(st), e0(nullptr), e1(nullptr), on(false) {
   if (!g_timing.on) return;
   on = true;
-  (void)hipEventCreate(&e0);
-  (void)hipEventCreate(&e1);
+  {
+    std::lock_guard<std::mutex> g(g_timing.mu);
+    e0 = g_timing.get();
+    e1 = g_timing.get();
+  }
   (void)hipEventRecord(e0, s);
 }
 

@@ -20,7 +20,7 @@ struct VsolvePlan {
   uint32_t RT, ntile;  // right-hand sides per tile (even), number of tiles
   uint32_t ldv;        // row stride of the packed right-hand sides = RT*ntile
 };
-VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t target_waves);
+VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus);
 
 // Workspace (device, uint64 elements) needed by vsolve for a plan.
 size_t vsolve_workspace_words(const VsolvePlan& P);
@@ -34,13 +34,16 @@ hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, co
                   int32_t* status, hipStream_t s);
 
 // Master polynomial M(z) = prod_l (z - m_l): lower coefficients into Mc[t];
-// tmp is a [t] scratch array.  Product tree, ceil(log2 t) levels.
+// tmp is a scratch array of master_tmp_words(t).  Product tree, ceil(log2 t) levels.
+size_t master_tmp_words(uint32_t t);
 hipError_t master_poly(const zr_mod& M, uint32_t t, const uint64_t* mono, uint64_t* Mc, uint64_t* tmp,
                        hipStream_t s);
 
 // ---- Newton lift (eq. 1) and skeleton expansion ------------------------------
-// consts: x[D1], xp[D1], invd[D1*D1], invdp[D1*D1] (invd[j*D1+i] = 1/(x_i - x_{i-j})).
-hipError_t newton_lift(const zr_mod& M, uint32_t t, uint32_t D1, const uint64_t* vals, const uint64_t* consts,
+// g[d][l] = sum_i W[d][i] vals[i][l] with W the inverse Vandermonde matrix of
+// the stage's nodes; Wl holds W as 22-bit limbs laid out [i][d][3].  cnt[l]
+// receives the number of nonzero g[.][l].
+hipError_t newton_lift(const zr_mod& M, uint32_t t, uint32_t D1, const uint64_t* vals, const uint32_t* Wl,
                        uint64_t* g, uint32_t* cnt, hipStream_t s);
 
 // Exclusive scan of cnt[n] into off[n+1] (off[n] = total); tmp needs scan_tmp_words(n).

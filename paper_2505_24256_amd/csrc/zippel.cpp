@@ -218,24 +218,100 @@ std::vector<uint64_t> Params::node_list(uint32_t v, uint32_t count) const {
   return X;
 }
 
-// Newton constants for nodes X[0..D1): x, x', 1/(x_i - x_{i-j}) and Shoup constants.
-std::vector<uint64_t> newton_consts(const zr_mod& M, const std::vector<uint64_t>& X) {
+// Matrix of Newton interpolation at nodes X[0..D1): the interpolant of values
+// a_i is sum_i a_i L_i(z) with the Lagrange basis L_i = Q_i / Q_i(x_i),
+// Q_i = prod_{j != i} (z - x_j) = MX(z) / (z - x_i), MX = prod_j (z - x_j); so
+// W[d][i] = coefficient d of L_i.  Q_i comes from MX by synthetic division, the
+// D1 denominators are inverted together (one inversion and 3 D1 products).
+// Returned as 22-bit limbs laid out [i][d][3] for the lift kernel.
+static std::vector<uint32_t> newton_matrix_limbs_uncached(const zr_mod& M, const std::vector<uint64_t>& X) {
   const size_t D1 = X.size();
-  std::vector<uint64_t> c(2 * D1 + 2 * D1 * D1, 0);
-  for (size_t i = 0; i < D1; ++i) {
-    c[i] = X[i];
-    c[D1 + i] = zr_shoup_pre(M, X[i]);
+  std::vector<uint64_t> MX(D1 + 1, 0);
+  MX[0] = 1 % M.p;
+  for (size_t j = 0; j < D1; ++j) {
+    MX[j + 1] = MX[j];
+    for (size_t r = j; r >= 1; --r) MX[r] = zr_sub(M, MX[r - 1], zr_mul(M, X[j], MX[r]));
+    MX[0] = zr_neg(M, zr_mul(M, X[j], MX[0]));
   }
-  uint64_t* invd = c.data() + 2 * D1;
-  uint64_t* invdp = invd + D1 * D1;
-  for (size_t j = 1; j < D1; ++j)
-    for (size_t i = j; i < D1; ++i) {
-      const uint64_t d = zr_sub(M, X[i], X[i - j]);
-      const uint64_t iv = zr_inv(M, d);
-      invd[j * D1 + i] = iv;
-      invdp[j * D1 + i] = zr_shoup_pre(M, iv);
+  std::vector<uint64_t> Q(D1 * D1), den(D1), pre(D1 + 1);
+  for (size_t i = 0; i < D1; ++i) {
+    uint64_t* q = &Q[i * D1];
+    q[D1 - 1] = MX[D1];
+    for (size_t r = D1 - 1; r >= 1; --r) q[r - 1] = zr_add(M, MX[r], zr_mul(M, X[i], q[r]));
+    uint64_t h = 0;
+    for (size_t r = D1; r-- > 0;) h = zr_add(M, zr_mul(M, h, X[i]), q[r]);
+    den[i] = h;
+  }
+  // batch inversion of the denominators (nonzero: the nodes are distinct)
+  pre[0] = 1 % M.p;
+  for (size_t i = 0; i < D1; ++i) pre[i + 1] = zr_mul(M, pre[i], den[i]);
+  uint64_t inv_all = zr_inv(M, pre[D1]);
+  std::vector<uint64_t> inv(D1);
+  for (size_t i = D1; i-- > 0;) {
+    inv[i] = zr_mul(M, inv_all, pre[i]);
+    inv_all = zr_mul(M, inv_all, den[i]);
+  }
+  std::vector<uint32_t> W(D1 * D1 * 3, 0);
+  for (size_t i = 0; i < D1; ++i)
+    for (size_t d = 0; d < D1; ++d) {
+      const uint64_t c = zr_mul(M, Q[i * D1 + d], inv[i]);
+      uint32_t* w = &W[(i * D1 + d) * 3];
+      w[0] = (uint32_t)(c & 0x3FFFFF);
+      w[1] = (uint32_t)((c >> 22) & 0x3FFFFF);
+      w[2] = (uint32_t)(c >> 44);
     }
-  return c;
+  return W;
+}
+
+std::vector<uint32_t> newton_matrix_limbs(const zr_mod& M, const std::vector<uint64_t>& X) {
+  // the same node lists recur across reconstructions that share a schedule
+  static std::mutex mu;
+  static std::vector<std::pair<std::vector<uint64_t>, std::vector<uint32_t>>> cache;
+  std::vector<uint64_t> key(X);
+  key.push_back(M.p);
+  {
+    std::lock_guard<std::mutex> g(mu);
+    for (auto& e : cache)
+      if (e.first == key) return e.second;
+  }
+  std::vector<uint32_t> W = newton_matrix_limbs_uncached(M, X);
+  std::lock_guard<std::mutex> g(mu);
+  if (cache.size() >= 64) cache.erase(cache.begin());
+  cache.emplace_back(std::move(key), W);
+  return W;
+}
+
+// Device copies of the per-variable constants a stage needs: the Newton matrix
+// for D1 nodes and the powers y_v^d (with Shoup constants) for d < D1.
+StageConsts::StageConsts(const Params& P, DevArena& A, const std::vector<uint32_t>& D1s, hipStream_t s) {
+  const uint32_t n = (uint32_t)D1s.size();
+  woff.resize(n);
+  yoff.resize(n);
+  size_t words = 0;  // in 32-bit units, 8-byte aligned pieces
+  std::vector<std::vector<uint32_t>> Ws(n);
+  for (uint32_t v = 0; v < n; ++v) {
+    if (!D1s[v]) continue;
+    Ws[v] = newton_matrix_limbs(P.M, P.node_list(v, D1s[v]));
+    woff[v] = words;
+    words += (Ws[v].size() + 1) & ~(size_t)1;
+    yoff[v] = words;
+    words += 4 * (size_t)D1s[v];
+  }
+  std::vector<uint32_t> host(std::max<size_t>(words, 2), 0);
+  for (uint32_t v = 0; v < n; ++v) {
+    if (!D1s[v]) continue;
+    std::copy(Ws[v].begin(), Ws[v].end(), host.begin() + woff[v]);
+    uint64_t* yp = (uint64_t*)(host.data() + yoff[v]);
+    uint64_t acc = 1 % P.p;
+    for (uint32_t d = 0; d < D1s[v]; ++d) {
+      yp[d] = acc;
+      yp[D1s[v] + d] = zr_shoup_pre(P.M, acc);
+      acc = zr_mul(P.M, acc, P.y[v]);
+    }
+  }
+  base = A.alloc<uint32_t>(host.size());
+  h2d(base, host.data(), host.size() * 4, s);
+  check(hipStreamSynchronize(s));
 }
 
 // ---------------------------------------------------------------------------
@@ -285,48 +361,41 @@ void Skeleton::alloc(DevArena& A, uint32_t nv, uint32_t n) {
 }
 
 // vals [D1][t] (row 0 = coefficients at the anchor) -> new skeleton in `out`
-// (allocated from `keep`).  Returns the new size.
+// (allocated from `keep`).  One host synchronisation: the new size.
 uint32_t lift_stage(const Params& P, uint32_t kvar, const Skeleton& S, const uint64_t* d_vals, uint32_t D1,
-                    const std::vector<uint64_t>& X, DevArena& keep, Skeleton& out, hipStream_t s,
-                    int32_t* d_status, int32_t* h_status_out) {
+                    const uint32_t* d_W, const uint64_t* d_ypow, DevArena& keep, Skeleton& out, hipStream_t s,
+                    int32_t* d_status) {
   DevArena A(s);
   const uint32_t t = S.t;
-  std::vector<uint64_t> nc = newton_consts(P.M, X);
-  uint64_t* d_nc = A.alloc<uint64_t>(nc.size());
-  h2d(d_nc, nc.data(), nc.size() * 8, s);
   uint64_t* g = A.alloc<uint64_t>((size_t)D1 * std::max<uint32_t>(t, 1));
   uint32_t* cnt = A.alloc<uint32_t>(std::max<uint32_t>(t, 1));
   uint32_t* off = A.alloc<uint32_t>((size_t)t + 1);
   uint32_t* tmp = A.alloc<uint32_t>(scan_tmp_words(t));
-  check(newton_lift(P.M, t, D1, d_vals, d_nc, g, cnt, s));
+  check(newton_lift(P.M, t, D1, d_vals, d_W, g, cnt, s));
   count_newton(t, D1);
   if (t == 0) check(fill_i32((int32_t*)off, 0, 1, s));
   else check(exclusive_scan(t, cnt, off, tmp, s));
-  struct {
-    uint32_t total;
-    int32_t status;
-  } h;
-  check(hipMemcpyAsync(&h.total, off + t, 4, hipMemcpyDeviceToHost, s));
-  check(hipMemcpyAsync(&h.status, d_status, 4, hipMemcpyDeviceToHost, s));
+  int32_t* h = host_scratch();
+  check(hipMemcpyAsync(&h[0], off + t, 4, hipMemcpyDeviceToHost, s));
+  check(hipMemcpyAsync(&h[1], d_status, 4, hipMemcpyDeviceToHost, s));
   check(hipStreamSynchronize(s));
-  if (h_status_out) *h_status_out = h.status;
-  if (h.status != 0) throw Error(h.status);
-  // powers of y_k for the monomial values of the next stage
-  std::vector<uint64_t> yp(2 * D1);
-  uint64_t acc = 1 % P.p;
-  for (uint32_t d = 0; d < D1; ++d) {
-    yp[d] = acc;
-    yp[D1 + d] = zr_shoup_pre(P.M, acc);
-    acc = zr_mul(P.M, acc, P.y[kvar]);
+  const uint32_t total = (uint32_t)h[0];
+  if (h[1] != 0) throw Error(h[1]);
+  out.alloc(keep, P.nvars, total);
+  check(expand(P.M, t, D1, kvar, P.nvars, S.exps, S.mono, g, off, d_ypow, d_ypow + D1, out.exps, out.coef, out.mono,
+               std::max<uint32_t>(total, 1), s));
+  return total;
+}
+
+// Pinned host words for the per-stage size read-back.
+int32_t* host_scratch() {
+  static thread_local int32_t* buf = nullptr;
+  if (!buf) {
+    void* p = nullptr;
+    if (hipHostMalloc(&p, 64, hipHostMallocDefault) != hipSuccess) throw Error(ZR_ENOMEM);
+    buf = (int32_t*)p;
   }
-  uint64_t* d_yp = A.alloc<uint64_t>(2 * D1);
-  h2d(d_yp, yp.data(), yp.size() * 8, s);
-  out.alloc(keep, P.nvars, h.total);
-  check(expand(P.M, t, D1, kvar, P.nvars, S.exps, S.mono, g, off, d_yp, d_yp + D1, out.exps, out.coef, out.mono,
-               std::max<uint32_t>(h.total, 1), s));
-  // keep host inputs alive until the enqueued copies have run
-  check(hipStreamSynchronize(s));
-  return h.total;
+  return buf;
 }
 
 // One polynomial Zippel stage k >= 2 (0-based kvar = k-1) for a given skeleton
@@ -336,23 +405,21 @@ void solve_stage(const Params& P, const Skeleton& S, uint64_t* vals, uint32_t R,
   if (t == 0 || R == 0) return;
   DevArena A(s);
   uint64_t* Mc = A.alloc<uint64_t>(t);
-  uint64_t* tmp = A.alloc<uint64_t>(t);
+  uint64_t* tmp = A.alloc<uint64_t>(master_tmp_words(t));
   check(master_poly(P.M, t, S.mono, Mc, tmp, s));
-  VsolvePlan plan = vsolve_plan(t, R, target_waves());
+  VsolvePlan plan = vsolve_plan(t, R, device_cus());
   uint64_t* work = A.alloc<uint64_t>(vsolve_workspace_words(plan));
   check(vsolve(P.M, plan, S.mono, Mc, vals + t, t, vals + t, t, work, d_status, s));
   count_solve(t, R);
 }
 
-uint32_t target_waves() {
+uint32_t device_cus() {
   static uint32_t cached = 0;
   if (cached) return cached;
   int dev = 0, cus = 256;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const char* env = getenv("ZR_TARGET_WAVES_PER_CU");
-  const uint32_t per = env ? (uint32_t)atoi(env) : 8;
-  cached = (uint32_t)cus * std::max<uint32_t>(per, 1);
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  cached = (uint32_t)std::max(cus, 1);
   return cached;
 }
 
@@ -379,39 +446,6 @@ void download(const Skeleton& S, hipStream_t s, zr_poly* out) {
     for (uint32_t v = 0; v < S.nvars; ++v) out->exps[(size_t)l * S.nvars + v] = soa[(size_t)v * S.t + l];
 }
 
-// Value of a device skeleton at an explicit point (host result).
-uint64_t eval_at(const Params& P, const Skeleton& S, const uint64_t* pt, const std::vector<uint32_t>& maxdeg,
-                 hipStream_t s) {
-  DevArena A(s);
-  uint32_t ld = 1;
-  for (uint32_t v = 0; v < P.nvars; ++v) ld = std::max(ld, maxdeg[v] + 1);
-  std::vector<uint64_t> tab((size_t)P.nvars * ld, 0);
-  for (uint32_t v = 0; v < P.nvars; ++v) {
-    uint64_t acc = 1 % P.p;
-    for (uint32_t d = 0; d <= maxdeg[v]; ++d) {
-      tab[(size_t)v * ld + d] = acc;
-      acc = zr_mul(P.M, acc, pt[v]);
-    }
-  }
-  uint64_t* d_tab = A.alloc<uint64_t>(tab.size());
-  uint64_t* d_res = A.alloc<uint64_t>(1);
-  h2d(d_tab, tab.data(), tab.size() * 8, s);
-  if (S.t == 0) check(fill_u64(d_res, 0, 1, s));
-  else check(poly_eval_point(P.M, S.t, P.nvars, S.exps, S.t, S.coef, d_tab, ld, d_res, s));
-  uint64_t r = 0;
-  d2h_sync(&r, d_res, 8, s);
-  return r;
-}
-
-uint64_t bb_at(const Params& P, zr_blackbox_fn bb, void* ctx, const uint64_t* pt, hipStream_t s) {
-  DevArena A(s);
-  uint64_t* d = A.alloc<uint64_t>(1);
-  call_bb(bb, ctx, P, P.nvars, 1, pt, pt + (P.nvars - 1), 1, d, s);
-  uint64_t r = 0;
-  d2h_sync(&r, d, 8, s);
-  return r;
-}
-
 // ---------------------------------------------------------------------------
 // polynomial Zippel
 
@@ -422,17 +456,16 @@ static void reconstruct_poly(const zr_params* params, zr_blackbox_fn bb, void* c
   std::vector<std::unique_ptr<DevArena>> arenas;
   int32_t* d_status = keep.alloc<int32_t>(1);
   check(fill_i32(d_status, 0, 1, s));
+  std::vector<uint32_t> D1s(P.nvars);
+  for (uint32_t v = 0; v < P.nvars; ++v) D1s[v] = v < P.last ? P.deg[v] + 1 : 0;
+  StageConsts K(P, keep, D1s, s);
   // stage 1: Newton in x_1 from D_1 + 1 samples
   Skeleton root;
   root.alloc(keep, P.nvars, 1);
   check(fill_u64(root.mono, 1 % P.p, 1, s));
   check(fill_u64(root.coef, 1 % P.p, 1, s));
-  {
-    std::vector<uint16_t> z(P.nvars, 0);
-    h2d(root.exps, z.data(), z.size() * 2, s);
-    check(hipStreamSynchronize(s));
-  }
-  uint32_t D1 = P.deg[0] + 1;
+  check(fill_u64((uint64_t*)root.exps, 0, (P.nvars * 2 + 7) / 8, s));
+  uint32_t D1 = D1s[0];
   std::vector<uint64_t> X = P.node_list(0, D1);
   Skeleton cur;
   {
@@ -440,42 +473,74 @@ static void reconstruct_poly(const zr_params* params, zr_blackbox_fn bb, void* c
     uint64_t* vals = A.alloc<uint64_t>(D1);
     call_bb(bb, ctx, P, 1, 1, P.y.data(), X.data(), D1, vals, s);
     DevArena* kp = new DevArena(s);
-    lift_stage(P, 0, root, vals, D1, X, *kp, cur, s, d_status, nullptr);
     arenas.emplace_back(kp);
+    lift_stage(P, 0, root, vals, D1, K.W(0), K.ypow(0), *kp, cur, s, d_status);
   }
   g_counters.stages = 1;
   for (uint32_t k = 2; k <= P.last; ++k) {
     const uint32_t kvar = k - 1;
     const uint32_t R = P.deg[kvar];
-    D1 = R + 1;
+    D1 = D1s[kvar];
     X = P.node_list(kvar, D1);
     const uint32_t t = cur.t;
     Skeleton nxt;
     DevArena* kp = new DevArena(s);
+    arenas.emplace_back(kp);
     {
       DevArena A(s);
       uint64_t* vals = A.alloc<uint64_t>((size_t)D1 * std::max<uint32_t>(t, 1));
       check(copy_u64(vals, cur.coef, t, s));
       call_bb(bb, ctx, P, k, t, P.y.data(), X.data() + 1, R, vals + t, s);
       solve_stage(P, cur, vals, R, s, d_status);
-      lift_stage(P, kvar, cur, vals, D1, X, *kp, nxt, s, d_status, nullptr);
+      lift_stage(P, kvar, cur, vals, D1, K.W(kvar), K.ypow(kvar), *kp, nxt, s, d_status);
     }
     // the previous skeleton's arena can go once the new one is built
-    arenas.front().reset();
     arenas.erase(arenas.begin());
-    arenas.emplace_back(kp);
     cur = nxt;
     g_counters.stages = k;
   }
-  if (P.last == P.nvars && P.nprobes) {
-    for (uint32_t q = 0; q < P.nprobes; ++q) {
-      const uint64_t* pt = P.probes.data() + (size_t)q * P.nvars;
-      const uint64_t want = bb_at(P, bb, ctx, pt, s);
-      const uint64_t got = eval_at(P, cur, pt, P.deg, s);
-      if (want != got) throw Error(ZR_EPROBE);
+  if (P.last == P.nvars && P.nprobes) check_probes(P, bb, ctx, cur, nullptr, s);
+  download(cur, s, out);
+}
+
+// Compare the black box with the reconstruction (num / den when den != NULL)
+// at the probe points: all black-box calls and evaluations are enqueued, then
+// one read-back.
+void check_probes(const Params& P, zr_blackbox_fn bb, void* ctx, const Skeleton& N, const Skeleton* D,
+                  hipStream_t s) {
+  DevArena A(s);
+  const uint32_t np = P.nprobes, nv = P.nvars;
+  uint32_t ld = 1;
+  for (uint32_t v = 0; v < nv; ++v) ld = std::max(ld, std::max(P.deg[v], D ? P.deg_den[v] : 0u) + 1);
+  std::vector<uint64_t> tab((size_t)np * nv * ld, 0);
+  for (uint32_t q = 0; q < np; ++q)
+    for (uint32_t v = 0; v < nv; ++v) {
+      uint64_t acc = 1 % P.p;
+      for (uint32_t d = 0; d < ld; ++d) {
+        tab[((size_t)q * nv + v) * ld + d] = acc;
+        acc = zr_mul(P.M, acc, P.probes[(size_t)q * nv + v]);
+      }
+    }
+  uint64_t* d_tab = A.alloc<uint64_t>(tab.size());
+  uint64_t* d_res = A.alloc<uint64_t>(3 * (size_t)np);
+  h2d(d_tab, tab.data(), tab.size() * 8, s);
+  for (uint32_t q = 0; q < np; ++q) {
+    const uint64_t* pt = P.probes.data() + (size_t)q * nv;
+    call_bb(bb, ctx, P, nv, 1, pt, pt + (nv - 1), 1, d_res + q, s);
+    const uint64_t* tq = d_tab + (size_t)q * nv * ld;
+    if (N.t) check(poly_eval_point(P.M, N.t, nv, N.exps, N.t, N.coef, tq, ld, d_res + np + q, s));
+    else check(fill_u64(d_res + np + q, 0, 1, s));
+    if (D) {
+      if (D->t) check(poly_eval_point(P.M, D->t, nv, D->exps, D->t, D->coef, tq, ld, d_res + 2 * np + q, s));
+      else check(fill_u64(d_res + 2 * np + q, 0, 1, s));
     }
   }
-  download(cur, s, out);
+  std::vector<uint64_t> r(3 * (size_t)np);
+  d2h_sync(r.data(), d_res, r.size() * 8, s);
+  for (uint32_t q = 0; q < np; ++q) {
+    const uint64_t f = r[q], nvl = r[np + q];
+    if (D ? nvl != zr_mul(P.M, f, r[2 * np + q]) : nvl != f) throw Error(ZR_EPROBE);
+  }
 }
 
 }  // namespace zr
