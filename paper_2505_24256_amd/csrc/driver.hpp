@@ -22,10 +22,12 @@ void check(hipError_t e);
 void h2d(void* d, const void* h, size_t bytes, hipStream_t s);
 void d2h_sync(void* h, const void* d, size_t bytes, hipStream_t s);
 
-// Stream-ordered device allocations released (stream-ordered) on destruction.
+// Device workspace from the library's stream-ordered block cache; released to
+// the cache (for later work on the same stream) on destruction.
 struct DevArena {
   hipStream_t s;
-  std::vector<void*> ptrs;
+  int dev = 0;
+  std::vector<std::pair<void*, size_t>> blocks;
   explicit DevArena(hipStream_t st);
   ~DevArena();
   DevArena(const DevArena&) = delete;

@@ -495,12 +495,16 @@ __global__ void k_master_level(zr_mod M, uint32_t t, uint32_t half, const uint64
 }
 
 // Large levels (factors of degree >= 32): a wave owns 64 consecutive output
-// coefficients of one product and one chunk of the convolution index i; the
-// factor L_i is wave-uniform (scalar load), R_{k-i} is a coalesced vector load.
-// Chunk partial sums go to part[ic][g]; k_master_sum adds them and the two
-// terms contributed by the leading ones.
+// coefficients of one product and one chunk [i0, i1) of the convolution index.
+// The factor L_i is wave-uniform (scalar load, split into 22-bit limbs); the
+// window of R needed by the wave, R_{k-i} for its k and i, is staged once in
+// LDS.  Chunk partial sums go to part[ic][g]; k_master_sum adds them and the
+// two terms contributed by the leading ones.
+constexpr uint32_t kConvIC = 512;
+
 __global__ void __launch_bounds__(64) k_master_conv(zr_mod M, uint32_t t, uint32_t half, uint32_t IC,
                                                     const uint64_t* __restrict__ cur, uint64_t* __restrict__ part) {
+  __shared__ uint64_t win[64 + kConvIC];
   const uint32_t g0 = blockIdx.x * 64;
   const uint32_t g = g0 + threadIdx.x;
   const uint32_t ic = blockIdx.y;
@@ -511,24 +515,40 @@ __global__ void __launch_bounds__(64) k_master_conv(zr_mod M, uint32_t t, uint32
   const uint32_t k = g - a;
   const uint64_t* __restrict__ Lc = cur + a;
   const uint64_t* __restrict__ Rc = cur + a + n1;
-  ColAcc acc;
-  col_zero(acc);
+  Acc6 acc;
+  acc6_zero(acc);
+  uint32_t ilo = ic * IC, ihi = std::min(ilo + IC, n1);
   if (n2 > 0) {
-    // i range of the wave within this chunk
-    uint32_t ilo = ic * IC;
-    uint32_t ihi = std::min(ilo + IC, n1);  // exclusive
     const uint32_t wlo = k0 + 1 > n2 ? k0 + 1 - n2 : 0;
-    const uint32_t whi = std::min(k0 + 64, n1);  // exclusive: i <= k0+63
+    const uint32_t whi = std::min(k0 + 64, n1);
     ilo = std::max(ilo, wlo);
     ihi = std::min(ihi, whi);
+  } else {
+    ihi = ilo;
+  }
+  if (ilo < ihi) {
+    // window: R index j = k - i for k in [k0, k0+63], i in [ilo, ihi): j in [k0 - ihi + 1, k0 + 63 - ilo]
+    const int64_t jbase = (int64_t)k0 - (int64_t)ihi + 1;
+    const uint32_t wlen = 63 + (ihi - ilo);
+    for (uint32_t x = threadIdx.x; x < wlen; x += 64) {
+      const int64_t j = jbase + x;
+      win[x] = (j >= 0 && j < (int64_t)n2) ? Rc[j] : 0;
+    }
+    __syncthreads();
+    uint32_t since = 0;
     for (uint32_t i = ilo; i < ihi; ++i) {
       const uint64_t Li = Lc[i];
-      const bool ok = g < t && i <= k && k - i < n2;
-      const uint64_t Rv = ok ? Rc[k - i] : 0;
-      col_mac(acc, (uint32_t)Rv, (uint32_t)(Rv >> 32), (uint32_t)Li, (uint32_t)(Li >> 32));
+      // lane k reads R_{k-i} at window index k - i - jbase (in range for every lane)
+      const uint64_t Rv = win[(int64_t)k - (int64_t)i - jbase];
+      acc6_mac(acc, (uint32_t)Rv, (uint32_t)(Rv >> 32), (uint32_t)(Li & 0x3FFFFF), (uint32_t)((Li >> 22) & 0x3FFFFF),
+               (uint32_t)(Li >> 44));
+      if (++since == kFold) {
+        acc6_fold(acc);
+        since = 0;
+      }
     }
   }
-  if (g < t) part[(size_t)ic * t + g] = col_reduce(M, acc);
+  if (g < t) part[(size_t)ic * t + g] = acc6_reduce(M, acc);
 }
 
 __global__ void k_master_sum(zr_mod M, uint32_t t, uint32_t half, uint32_t nic, const uint64_t* __restrict__ cur,
@@ -549,10 +569,7 @@ __global__ void k_master_sum(zr_mod M, uint32_t t, uint32_t half, uint32_t nic, 
 size_t master_tmp_words(uint32_t t) {
   // t for the ping-pong level array plus chunk partials of the large levels
   uint32_t nic_max = 1;
-  for (uint32_t half = 32; half < t; half *= 2) {
-    const uint32_t IC = std::max<uint32_t>(256, cdiv(half, 32));
-    nic_max = std::max(nic_max, cdiv(half, IC));
-  }
+  for (uint32_t half = 32; half < t; half *= 2) nic_max = std::max(nic_max, cdiv(half, kConvIC));
   return (size_t)t + (size_t)nic_max * t + 64;
 }
 
@@ -573,7 +590,7 @@ hipError_t master_poly(const zr_mod& M, uint32_t t, const uint64_t* mono, uint64
     if (half < 32) {
       hipLaunchKernelGGL(k_master_level, dim3(cdiv(t, 128)), dim3(128), 0, s, M, t, half, cur, nxt);
     } else {
-      const uint32_t IC = std::max<uint32_t>(256, cdiv(half, 32));
+      const uint32_t IC = kConvIC;
       const uint32_t nic = cdiv(half, IC);
       hipLaunchKernelGGL(k_master_conv, dim3(cdiv(t, 64), nic), dim3(64), 0, s, M, t, half, IC, cur, part);
       hipLaunchKernelGGL(k_master_sum, dim3(cdiv(t, 256)), dim3(256), 0, s, M, t, half, nic, cur, part, nxt);
@@ -605,13 +622,20 @@ __global__ void __launch_bounds__(64) k_newton_mat(zr_mod M, uint32_t t, uint32_
   Acc6 acc[kNewtonDB];
 #pragma unroll
   for (int e = 0; e < kNewtonDB; ++e) acc6_zero(acc[e]);
-  for (uint32_t i = 0; i < D1; ++i) {
-    const uint64_t v = vals[(size_t)i * t + l];
-    const uint32_t v0 = (uint32_t)v, v1 = (uint32_t)(v >> 32);
-    const uint32_t* __restrict__ w = Wl + ((size_t)i * D1 + d0) * 3;
+  for (uint32_t i0 = 0; i0 < D1; i0 += 8) {
+    uint64_t vv[8];
 #pragma unroll
-    for (int e = 0; e < kNewtonDB; ++e)
-      if (d0 + e < D1) acc6_mac(acc[e], v0, v1, w[3 * e], w[3 * e + 1], w[3 * e + 2]);
+    for (int u = 0; u < 8; ++u) vv[u] = i0 + u < D1 ? vals[(size_t)(i0 + u) * t + l] : 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint32_t i = i0 + u;
+      if (i >= D1) break;
+      const uint32_t v0 = (uint32_t)vv[u], v1 = (uint32_t)(vv[u] >> 32);
+      const uint32_t* __restrict__ w = Wl + ((size_t)i * D1 + d0) * 3;
+#pragma unroll
+      for (int e = 0; e < kNewtonDB; ++e)
+        if (d0 + e < D1) acc6_mac(acc[e], v0, v1, w[3 * e], w[3 * e + 1], w[3 * e + 2]);
+    }
   }
   if (!live) return;
 #pragma unroll
@@ -728,18 +752,17 @@ __global__ void k_expand(zr_mod M, uint32_t t, uint32_t D1, uint32_t kvar, uint3
                          uint16_t* __restrict__ exps_new, uint64_t* __restrict__ coef_new,
                          uint64_t* __restrict__ mono_new, uint32_t ld_new) {
   const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t d = blockIdx.y;
   if (l >= t) return;
+  const uint64_t c = g[(size_t)d * t + l];
+  if (c == 0) return;
+  // rank of (l, d) among the nonzero coefficients of term l
   uint32_t pos = off[l];
-  const uint64_t m = mono_old[l];
-  for (uint32_t d = 0; d < D1; ++d) {
-    const uint64_t c = g[(size_t)d * t + l];
-    if (c == 0) continue;
-    for (uint32_t v = 0; v < nvars; ++v)
-      exps_new[(size_t)v * ld_new + pos] = v == kvar ? (uint16_t)d : exps_old[(size_t)v * t + l];
-    coef_new[pos] = c;
-    mono_new[pos] = zr_shoup(M, m, ypow[d], ypowp[d]);
-    ++pos;
-  }
+  for (uint32_t e = 0; e < d; ++e) pos += g[(size_t)e * t + l] != 0;
+  for (uint32_t v = 0; v < nvars; ++v)
+    exps_new[(size_t)v * ld_new + pos] = v == kvar ? (uint16_t)d : exps_old[(size_t)v * t + l];
+  coef_new[pos] = c;
+  mono_new[pos] = zr_shoup(M, mono_old[l], ypow[d], ypowp[d]);
 }
 
 hipError_t expand(const zr_mod& M, uint32_t t, uint32_t D1, uint32_t kvar, uint32_t nvars, const uint16_t* exps_old,
@@ -748,8 +771,8 @@ hipError_t expand(const zr_mod& M, uint32_t t, uint32_t D1, uint32_t kvar, uint3
                   hipStream_t s) {
   if (t == 0) return hipSuccess;
   TimedLaunch tl("expand", s);
-  hipLaunchKernelGGL(k_expand, dim3(cdiv(t, 256)), dim3(256), 0, s, M, t, D1, kvar, nvars, exps_old, mono_old, g, off,
-                     ypow, ypowp, exps_new, coef_new, mono_new, ld_new);
+  hipLaunchKernelGGL(k_expand, dim3(cdiv(t, 256), D1), dim3(256), 0, s, M, t, D1, kvar, nvars, exps_old, mono_old, g,
+                     off, ypow, ypowp, exps_new, coef_new, mono_new, ld_new);
   return hipGetLastError();
 }
 
@@ -758,31 +781,47 @@ hipError_t expand(const zr_mod& M, uint32_t t, uint32_t D1, uint32_t kvar, uint3
 // variable; partial sums per thread, wave and block reductions mod p).
 // ============================================================================
 
+__device__ __forceinline__ uint64_t block_sum_mod(const zr_mod& M, uint64_t v, uint64_t* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = zr_add(M, sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  return sh[0];
+}
+
 __global__ void __launch_bounds__(256) k_poly_eval(zr_mod M, uint32_t t, uint32_t nvars,
                                                    const uint16_t* __restrict__ exps, uint32_t ld,
                                                    const uint64_t* __restrict__ coef,
                                                    const uint64_t* __restrict__ tab, uint32_t ldtab,
-                                                   uint64_t* __restrict__ result) {
+                                                   uint64_t* __restrict__ partial) {
   __shared__ uint64_t sh[256];
   uint64_t acc = 0;
-  for (uint32_t l = threadIdx.x; l < t; l += blockDim.x) {
+  for (uint32_t l = blockIdx.x * blockDim.x + threadIdx.x; l < t; l += gridDim.x * blockDim.x) {
     uint64_t v = coef[l];
     for (uint32_t j = 0; j < nvars; ++j) v = zr_mul(M, v, tab[(size_t)j * ldtab + exps[(size_t)j * ld + l]]);
     acc = zr_add(M, acc, v);
   }
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] = zr_add(M, sh[threadIdx.x], sh[threadIdx.x + w]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *result = sh[0];
+  const uint64_t s = block_sum_mod(M, acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) k_sum_mod(zr_mod M, uint32_t n, const uint64_t* __restrict__ partial,
+                                                 uint64_t* __restrict__ result) {
+  __shared__ uint64_t sh[256];
+  uint64_t acc = 0;
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) acc = zr_add(M, acc, partial[i]);
+  const uint64_t s = block_sum_mod(M, acc, sh);
+  if (threadIdx.x == 0) *result = s;
 }
 
 hipError_t poly_eval_point(const zr_mod& M, uint32_t t, uint32_t nvars, const uint16_t* exps, uint32_t ld,
                            const uint64_t* coef, const uint64_t* tab, uint32_t ldtab, uint64_t* result,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_poly_eval, dim3(1), dim3(256), 0, s, M, t, nvars, exps, ld, coef, tab, ldtab, result);
+                           uint64_t* partial, hipStream_t s) {
+  const uint32_t nb = std::max<uint32_t>(1, std::min<uint32_t>(kPolyEvalBlocks, cdiv(t, 256)));
+  hipLaunchKernelGGL(k_poly_eval, dim3(nb), dim3(256), 0, s, M, t, nvars, exps, ld, coef, tab, ldtab, partial);
+  hipLaunchKernelGGL(k_sum_mod, dim3(1), dim3(256), 0, s, M, nb, partial, result);
   return hipGetLastError();
 }
 

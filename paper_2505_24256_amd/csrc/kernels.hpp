@@ -59,10 +59,12 @@ hipError_t expand(const zr_mod& M, uint32_t t, uint32_t D1, uint32_t kvar, uint3
                   uint64_t* mono_new, uint32_t ld_new, hipStream_t s);
 
 // Value of the sparse polynomial at one point: sum_l coef_l prod_v tab[v][e_{l,v}].
-//   tab: [nvars][ldtab] powers of the point's coordinates.
+//   tab: [nvars][ldtab] powers of the point's coordinates; partial: scratch of
+//   kPolyEvalBlocks words.
+constexpr uint32_t kPolyEvalBlocks = 64;
 hipError_t poly_eval_point(const zr_mod& M, uint32_t t, uint32_t nvars, const uint16_t* exps, uint32_t ld,
                            const uint64_t* coef, const uint64_t* tab, uint32_t ldtab, uint64_t* result,
-                           hipStream_t s);
+                           uint64_t* partial, hipStream_t s);
 
 // ---- small helpers -----------------------------------------------------------
 hipError_t fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <stdexcept>
 #include <vector>
@@ -19,39 +20,57 @@
 namespace zr {
 
 // ---------------------------------------------------------------------------
-// device memory: stream-ordered allocations from the device's default pool,
-// which keeps freed memory cached so repeated calls do not reach the driver.
+// device memory: a stream-ordered block cache.  Blocks released by a call on a
+// stream go to that stream's free list and are handed out again only to later
+// work on the same stream, which runs after every earlier user of the block;
+// so neither allocation nor release ever waits for the device.  Blocks are
+// kept until the process ends (sizes are rounded up to powers of two).
 
-static std::mutex g_pool_mu;
-static std::vector<int> g_pool_ready;
-
-static void ensure_pool(int dev) {
-  std::lock_guard<std::mutex> g(g_pool_mu);
-  if (std::find(g_pool_ready.begin(), g_pool_ready.end(), dev) != g_pool_ready.end()) return;
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-    uint64_t thr = UINT64_MAX;
-    hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-  }
-  g_pool_ready.push_back(dev);
+namespace {
+struct BlockCache {
+  std::mutex mu;
+  std::map<std::pair<int, hipStream_t>, std::multimap<size_t, void*>> free;
+};
+BlockCache& block_cache() {
+  static BlockCache* c = new BlockCache();  // never destroyed: blocks live until exit
+  return *c;
 }
-
-DevArena::DevArena(hipStream_t st) : s(st) {
-  int dev = 0;
-  hipGetDevice(&dev);
-  ensure_pool(dev);
+size_t size_class(size_t bytes) {
+  size_t c = 256;
+  while (c < bytes) c <<= 1;
+  return c;
 }
+}  // namespace
+
+DevArena::DevArena(hipStream_t st) : s(st) { (void)hipGetDevice(&dev); }
 
 DevArena::~DevArena() {
-  for (void* p : ptrs) hipFreeAsync(p, s);
+  BlockCache& C = block_cache();
+  std::lock_guard<std::mutex> g(C.mu);
+  auto& fl = C.free[{dev, s}];
+  for (auto& b : blocks) fl.emplace(b.second, b.first);
 }
 
 void* DevArena::raw(size_t bytes) {
+  const size_t cls = size_class(std::max<size_t>(bytes, 256));
+  BlockCache& C = block_cache();
+  {
+    std::lock_guard<std::mutex> g(C.mu);
+    auto& fl = C.free[{dev, s}];
+    auto it = fl.find(cls);
+    if (it != fl.end()) {
+      void* p = it->second;
+      fl.erase(it);
+      blocks.emplace_back(p, cls);
+      return p;
+    }
+  }
   void* p = nullptr;
-  bytes = std::max<size_t>(bytes, 256);
-  bytes = (bytes + 255) & ~(size_t)255;
-  if (hipMallocAsync(&p, bytes, s) != hipSuccess || !p) throw Error(ZR_ENOMEM);
-  ptrs.push_back(p);
+  if (hipMallocAsync(&p, cls, s) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    throw Error(ZR_ENOMEM);
+  }
+  blocks.emplace_back(p, cls);
   return p;
 }
 
@@ -523,15 +542,19 @@ void check_probes(const Params& P, zr_blackbox_fn bb, void* ctx, const Skeleton&
     }
   uint64_t* d_tab = A.alloc<uint64_t>(tab.size());
   uint64_t* d_res = A.alloc<uint64_t>(3 * (size_t)np);
+  uint64_t* d_part = A.alloc<uint64_t>(2 * (size_t)np * kPolyEvalBlocks);
   h2d(d_tab, tab.data(), tab.size() * 8, s);
   for (uint32_t q = 0; q < np; ++q) {
     const uint64_t* pt = P.probes.data() + (size_t)q * nv;
     call_bb(bb, ctx, P, nv, 1, pt, pt + (nv - 1), 1, d_res + q, s);
     const uint64_t* tq = d_tab + (size_t)q * nv * ld;
-    if (N.t) check(poly_eval_point(P.M, N.t, nv, N.exps, N.t, N.coef, tq, ld, d_res + np + q, s));
+    uint64_t* pq = d_part + (size_t)2 * q * kPolyEvalBlocks;
+    if (N.t) check(poly_eval_point(P.M, N.t, nv, N.exps, N.t, N.coef, tq, ld, d_res + np + q, pq, s));
     else check(fill_u64(d_res + np + q, 0, 1, s));
     if (D) {
-      if (D->t) check(poly_eval_point(P.M, D->t, nv, D->exps, D->t, D->coef, tq, ld, d_res + 2 * np + q, s));
+      if (D->t)
+        check(poly_eval_point(P.M, D->t, nv, D->exps, D->t, D->coef, tq, ld, d_res + 2 * np + q,
+                              pq + kPolyEvalBlocks, s));
       else check(fill_u64(d_res + 2 * np + q, 0, 1, s));
     }
   }
