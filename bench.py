@@ -63,6 +63,162 @@ def microbench(zr):
     return out
 
 
+def _progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def batched_vs_plain(zr, synth, args, stream):
+    """Batched workload: independent instances sharing p, n uniform in 3..8,
+    t log-uniform in 10..2*10^4, per-variable degree <= 30.  Samples come from
+    the device black box, recorded once per instance and replayed; the same
+    recordings serve the batched call and the one-at-a-time plain calls."""
+    import torch
+    t0 = time.perf_counter()
+    ws = synth.batch_workload(args.batch_instances)
+    t_gen = time.perf_counter() - t0
+    _progress(f"batch workload generated ({len(ws)} instances, {t_gen:.1f} s); recording")
+    recs = [zr.Recorder(synth.DeviceBlackBox(w.hidden, nthreads=args.cpu_threads)) for w in ws]
+    items = [{"deg": w.deg, "box": r, "sched": w.schedule} for w, r in zip(ws, recs)]
+    p = ws[0].p
+    t0 = time.perf_counter()
+    res = zr.reconstruct_batch(p, items, stream=stream)
+    t_rec = time.perf_counter() - t0
+    exact = all(not isinstance(r, Exception) and np.array_equal(r[0], w.hidden.exps) and
+                np.array_equal(r[1], w.hidden.coefs) for w, r in zip(ws, res))
+    for r in recs:
+        r.replay(True)
+    _progress(f"recorded in {t_rec:.1f} s; autotune")
+    tuned = zr.autotune(p, stream=stream)
+    _progress(f"band choices {tuned}; batched runs")
+    # batched
+    times = []
+    cnt = None
+    for _ in range(max(1, args.batch_steps)):
+        for r in recs:
+            zr.lib().zr_recorder_rewind(r.handle)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        res = zr.reconstruct_batch(p, items, stream=stream)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
+        cnt = zr.last_counters()
+        exact = exact and all(not isinstance(r, Exception) and np.array_equal(r[0], w.hidden.exps) and
+                              np.array_equal(r[1], w.hidden.coefs) for w, r in zip(ws, res))
+    tb = statistics.median(times)
+    _progress(f"batched {times}; plain one at a time")
+    # plain, one at a time, same recordings
+    for r in recs:
+        zr.lib().zr_recorder_rewind(r.handle)
+    lat = []
+    mul_plain = 0
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for w, r in zip(ws, recs):
+        t1 = time.perf_counter()
+        e, c = zr.reconstruct(p, w.deg, r, sched=w.schedule, stream=stream)
+        lat.append(time.perf_counter() - t1)
+        mul_plain += zr.last_counters()["mulmods"]
+        exact = exact and bool(np.array_equal(e, w.hidden.exps) and np.array_equal(c, w.hidden.coefs))
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - ts
+    n = len(ws)
+    return {
+        "workload": f"{n} independent polynomial reconstructions, n uniform in 3..8, t log-uniform in 10..2*10^4, "
+                    "per-variable degree<=30, shared 63-bit prime",
+        "instances": n, "terms_total": int(sum(w.hidden.nterms for w in ws)),
+        "batched": {"reconstructions_per_s": round(n / tb, 2), "mulmod_per_s": round(cnt["mulmods"] / tb, 1),
+                    "seconds": round(tb, 3), "runs": len(times)},
+        "plain": {"reconstructions_per_s": round(n / tp, 2), "mulmod_per_s": round(mul_plain / tp, 1),
+                  "seconds": round(tp, 3), "latency_ms": {"p50": round(statistics.median(lat) * 1e3, 3),
+                                                         "p99": round(float(np.percentile(lat, 99)) * 1e3, 3)}},
+        "speedup": round(tp / tb, 3), "mulmods": cnt["mulmods"], "bit_exact": bool(exact),
+        "band_choices": tuned, "setup_seconds": {"generate": round(t_gen, 1), "record": round(t_rec, 1)},
+    }
+
+
+def served(zr, synth, args, stream):
+    """Served balanced Zippel: rational requests P/Q, n = 5, total degree <= 20,
+    t_N and t_D log-uniform in 10..5*10^3, Q(0) = 1, arriving as a Poisson
+    process at a fixed rate; admitted by device footprint, advanced in
+    continuous batches.  Each request's samples are recorded once (its run
+    alone), then replayed both for the one-at-a-time timing and for serving."""
+    import math
+    import torch
+    g = synth.SplitMix64(55)
+    ws = []
+    for i in range(args.serve_requests):
+        def logu():
+            u = g.next() / 2.0 ** 64
+            return int(round(math.exp(math.log(10) + u * (math.log(5000) - math.log(10)))))
+        ws.append(synth.rational_workload(5, 20, logu(), logu(), 50_000 + i))
+    recs = [zr.Recorder(zr.HostBlackBox(synth.BlackBox(w.num, w.den, nthreads=args.cpu_threads).eval, 5))
+            for w in ws]
+    alone = []
+    for w, r in zip(ws, recs):
+        alone.append(zr.balanced_reconstruct(w.p, w.deg_num, w.deg_den, r, sched=w.schedule, stream=stream))
+        r.replay(True)
+    _progress(f"served: {len(ws)} requests recorded")
+    # one at a time
+    lat1 = []
+    for w, r in zip(ws, recs):
+        zr.lib().zr_recorder_rewind(r.handle)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        zr.balanced_reconstruct(w.p, w.deg_num, w.deg_den, r, sched=w.schedule, stream=stream)
+        lat1.append(time.perf_counter() - t1)
+    for r in recs:
+        zr.lib().zr_recorder_rewind(r.handle)
+    # Poisson arrivals
+    rate = args.serve_rate
+    arr, t = [], 0.0
+    for _ in ws:
+        t += -math.log(1.0 - g.next() / 2.0 ** 64) / rate
+        arr.append(t)
+    srv = zr.Server(ws[0].p, hbm_budget=args.serve_budget_gib << 30, max_active=args.serve_slots, stream=stream)
+    ids, sub, fin, res = {}, 0, {}, {}
+    t0 = time.perf_counter()
+    while len(fin) < len(ws):
+        now = time.perf_counter() - t0
+        while sub < len(ws) and arr[sub] <= now:
+            w = ws[sub]
+            rid = srv.submit(w.deg_num, recs[sub], sched=w.schedule, deg_den=w.deg_den,
+                             expected_terms=max(w.num.nterms, w.den.nterms))
+            ids[rid] = sub
+            sub += 1
+        st = srv.stats()
+        if st["active"] == 0 and st["pending"] == 0:
+            if sub < len(ws):
+                time.sleep(max(0.0, arr[sub] - (time.perf_counter() - t0)))
+            continue
+        srv.step()
+        tn = time.perf_counter() - t0
+        for rid, i in list(ids.items()):
+            if i in fin:
+                continue
+            r = srv.poll(rid)
+            if r is not None:
+                fin[i] = tn
+                res[i] = r
+    total = max(fin.values()) - arr[0]
+    lat = [fin[i] - arr[i] for i in range(len(ws))]
+    same = all(res[i][0] == zr.ZR_OK and np.array_equal(res[i][1][0], alone[i][0][0]) and
+               np.array_equal(res[i][1][1], alone[i][0][1]) and np.array_equal(res[i][2][0], alone[i][1][0]) and
+               np.array_equal(res[i][2][1], alone[i][1][1]) for i in range(len(ws)))
+    st = srv.stats()
+    srv.close()
+    return {
+        "workload": f"{len(ws)} rational requests P/Q, n=5, total degree<=20, t_N and t_D log-uniform in 10..5*10^3, "
+                    f"Q(0)=1, Poisson arrivals at {rate} requests/s",
+        "served": {"requests_per_s": round(len(ws) / total, 2), "latency_ms": {
+            "p50": round(statistics.median(lat) * 1e3, 2), "p99": round(float(np.percentile(lat, 99)) * 1e3, 2)},
+            "steps": st["steps"], "peak_active": st["peak_active"], "peak_footprint_bytes": st["peak_footprint"]},
+        "one_at_a_time": {"requests_per_s": round(len(ws) / sum(lat1), 2), "latency_ms": {
+            "p50": round(statistics.median(lat1) * 1e3, 2), "p99": round(float(np.percentile(lat1, 99)) * 1e3, 2)}},
+        "identical_to_alone": bool(same),
+        "slots": args.serve_slots, "budget_gib": args.serve_budget_gib,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +227,14 @@ def main():
     ap.add_argument("--microbench", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=16)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain measurement")
+    ap.add_argument("--batch-instances", type=int, default=4096)
+    ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-form measurement")
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-rate", type=float, default=100.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-budget-gib", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; the reconstruction of independent instances would "
@@ -153,6 +317,14 @@ def main():
                          "samples served from the host cache; unsigned __int128 products reduced with %",
                "seconds": round(tcpu, 2), "matches_gpu": same}
 
+    batch = None
+    _progress("plain configuration measured")
+    if not args.no_batch:
+        batch = batched_vs_plain(zr, synth, args, stream)
+    serve = None
+    if not args.no_serve:
+        serve = served(zr, synth, args, stream)
+
     out = {
         "metric": "mulmod/s (algorithmic modular products per second, whole reconstruction)",
         "value": round(value, 1),
@@ -178,6 +350,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,
+        "batch": batch,
+        "serve": serve,
     }
     print(json.dumps(out), flush=True)
 

@@ -158,6 +158,81 @@ zr_status vandermonde_solve_batch(size_t nsys, uint64_t p, const uint64_t* d_sys
                                   const uint64_t* h_rhs_off, const uint64_t* d_rhs, uint64_t* d_out,
                                   int32_t* d_status, hipStream_t stream);
 
+/* Batched polynomial Zippel (§1): n independent reconstructions advanced stage
+ * by stage together, so that each stage's master polynomials, transposed
+ * Vandermonde solves (one persistent work-queue pass over all systems),
+ * Newton lifts and expansions run as one launch sequence for the whole batch.
+ *   params[n]  one parameter set per instance; every valid instance must use
+ *              the same prime (ZR_EINVAL for the whole call otherwise)
+ *   bb, ctx[n] the black box, called with ctx[i] for instance i (ctx may be
+ *              NULL: then every call gets NULL)
+ *   out[n]     results (library-owned, zr_poly_free each); empty for failed instances
+ *   status[n]  per-instance ZR_OK or that instance's error; one instance's
+ *              failure does not stop the others
+ * Returns ZR_OK when the batch ran, whatever the per-instance statuses. */
+zr_status zippel_reconstruct_batch(uint32_t n, const zr_params* params, zr_blackbox_fn bb, void* const* ctx,
+                                   hipStream_t stream, zr_poly* out, int32_t* status);
+
+/* Size bands of the batched solve, by system size t: [1,64), [64,256),
+ * [256,1024), [1024,4096), [4096,inf).  Per band: whether small systems share
+ * wavefronts (lane = (system, row)), and the shortest chunk of the synthetic
+ * division range when a system is split across wavefronts. */
+typedef struct {
+  uint32_t packed;
+  uint32_t min_chunk;
+} zr_band_choice;
+#define ZR_NBANDS 5
+
+/* Measure the candidates of every band on the current device (synthetic
+ * systems mod p, about a second) and keep the fastest for later batched calls
+ * of this process.  table[ZR_NBANDS] receives the choices (may be NULL). */
+zr_status zr_autotune(uint64_t p, hipStream_t stream, zr_band_choice* table);
+/* Current choices (defaults until zr_autotune ran); returns 1 if tuned. */
+int zr_tuning_get(zr_band_choice* table);
+/* Override the choices (tests and experiments). */
+zr_status zr_tuning_set(const zr_band_choice* table);
+
+/* Served form.  Reconstruction requests arrive over time (the coefficients of a
+ * modular reduction stream out one by one, Introduction); the server admits
+ * them first come, first served while a slot is free and the sum of the
+ * admitted requests' estimated device footprints stays within hbm_budget bytes
+ * (a request above the budget still runs when nothing else is active).  Each
+ * zr_server_step advances every active request by one stage, batching the
+ * stage's Vandermonde solves, Newton matrices and lifts of all of them into one
+ * launch sequence, so requests admitted at a step boundary share the device
+ * with those already running (continuous batching).  Skeletons stay on the
+ * device between steps.  A result is bit-identical to the same request run
+ * alone through zippel_reconstruct / zippel_balanced_reconstruct.
+ * One server is driven from one host thread; all its device work is on `stream`. */
+typedef struct zr_server zr_server;
+
+typedef struct {
+  uint64_t submitted, admitted, completed, failed, steps;
+  uint64_t footprint, peak_footprint;  /* bytes of admitted requests (estimates) */
+  uint64_t active, pending, peak_active;
+} zr_server_stats;
+
+zr_status zr_server_create(zr_server** srv, uint64_t p, uint64_t hbm_budget, uint32_t max_active,
+                           hipStream_t stream);
+void zr_server_destroy(zr_server* srv);
+/* Queue a request: polynomial (balanced = 0) or rational (balanced = 1) with
+ * the parameters of zippel_reconstruct / zippel_balanced_reconstruct (copied;
+ * params may be released on return).  expected_terms sizes the footprint
+ * estimate (0: the degree bounds' monomial count).  The black box is called
+ * with ctx from zr_server_step.  *id receives the request's handle. */
+zr_status zr_server_submit(zr_server* srv, const zr_params* params, int balanced, uint64_t expected_terms,
+                           zr_blackbox_fn bb, void* ctx, uint64_t* id);
+/* Admit what fits, advance every active request by one stage, retire the
+ * finished ones.  Outputs (may be NULL): requests active after the step,
+ * still pending, and finished in this step. */
+zr_status zr_server_step(zr_server* srv, uint32_t* n_active, uint32_t* n_pending, uint32_t* n_finished);
+/* Result of a request: returns 1 while it is pending or active, 0 once finished
+ * (then *status, *num and *den (den empty for polynomials) are filled, the
+ * caller owns the polynomials and the id is forgotten), ZR_EINVAL for an
+ * unknown id.  num or den NULL discards that output. */
+int zr_server_poll(zr_server* srv, uint64_t id, int32_t* status, zr_poly* num, zr_poly* den);
+zr_status zr_server_get_stats(zr_server* srv, zr_server_stats* stats);
+
 /* ---- helpers for callers and black boxes ---------------------------------- */
 
 /* Synchronous copies between host and device memory on `stream`. */

@@ -26,7 +26,9 @@ EXPORTS = [
     "zippel_balanced_reconstruct", "vandermonde_solve_batch", "zr_copy_h2d", "zr_copy_d2h", "zr_copy_d2d",
     "zr_recorder_create", "zr_recorder_destroy", "zr_recorder_rewind", "zr_recorder_set_replay",
     "zr_recorder_blackbox", "zr_timing_enable", "zr_timing_reset", "zr_timing_get", "zr_last_counters",
-    "zr_microbench",
+    "zr_microbench", "zippel_reconstruct_batch", "zr_autotune", "zr_tuning_get", "zr_tuning_set",
+    "zr_server_create", "zr_server_destroy", "zr_server_submit", "zr_server_step", "zr_server_poll",
+    "zr_server_get_stats",
 ]
 MB_KINDS = {"mad_u64_u32": 0, "mul_lo_u32": 1, "mul_hi_u32": 2, "add_u32": 3, "mac192": 4, "shoup": 5, "copy": 6}
 
@@ -55,6 +57,18 @@ class ZrParams(ctypes.Structure):
                 ("deg_den", ctypes.c_void_p), ("seed", ctypes.c_uint64), ("y", ctypes.c_void_p),
                 ("anchor", ctypes.c_void_p), ("nodes", ctypes.c_void_p), ("nnodes", ctypes.c_void_p),
                 ("nprobes", ctypes.c_uint32), ("probes", ctypes.c_void_p), ("last_stage", ctypes.c_uint32)]
+
+
+class ZrBandChoice(ctypes.Structure):
+    _fields_ = [("packed", ctypes.c_uint32), ("min_chunk", ctypes.c_uint32)]
+
+
+NBANDS = 5
+
+
+class ZrServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "admitted", "completed", "failed", "steps", "footprint",
+                                               "peak_footprint", "active", "pending", "peak_active")]
 
 
 class ZrCounters(ctypes.Structure):
@@ -87,6 +101,18 @@ def lib():
         L.zippel_balanced_reconstruct.argtypes = [ctypes.POINTER(ZrParams), vp, vp, vp, ctypes.POINTER(ZrPoly),
                                                   ctypes.POINTER(ZrPoly)]
         L.vandermonde_solve_batch.argtypes = [sz, u64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.zippel_reconstruct_batch.argtypes = [u32, ctypes.POINTER(ZrParams), vp, vp, vp, ctypes.POINTER(ZrPoly),
+                                               vp]
+        L.zr_autotune.argtypes = [u64, vp, ctypes.POINTER(ZrBandChoice)]
+        L.zr_server_create.argtypes = [ctypes.POINTER(vp), u64, u64, u32, vp]
+        L.zr_server_destroy.argtypes = [vp]
+        L.zr_server_destroy.restype = None
+        L.zr_server_submit.argtypes = [vp, ctypes.POINTER(ZrParams), i32, u64, vp, vp, ctypes.POINTER(u64)]
+        L.zr_server_step.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32)]
+        L.zr_server_poll.argtypes = [vp, u64, ctypes.POINTER(i32), ctypes.POINTER(ZrPoly), ctypes.POINTER(ZrPoly)]
+        L.zr_server_get_stats.argtypes = [vp, ctypes.POINTER(ZrServerStats)]
+        L.zr_tuning_get.argtypes = [ctypes.POINTER(ZrBandChoice)]
+        L.zr_tuning_set.argtypes = [ctypes.POINTER(ZrBandChoice)]
         for n in ("zr_copy_h2d", "zr_copy_d2h", "zr_copy_d2d"):
             getattr(L, n).argtypes = [vp, vp, sz, vp]
         L.zr_recorder_create.argtypes = [ctypes.POINTER(vp), vp, vp]
@@ -195,10 +221,10 @@ class HostBlackBox:
 class Recorder:
     """Record a black box's outputs once on the device, then replay them."""
 
-    def __init__(self, inner: HostBlackBox):
+    def __init__(self, inner):
         self.inner = inner
         h = ctypes.c_void_p()
-        st = lib().zr_recorder_create(ctypes.byref(h), inner.fn_ptr, None)
+        st = lib().zr_recorder_create(ctypes.byref(h), inner.fn_ptr, inner.ctx)
         if st != ZR_OK:
             raise ZippelError(st, "zr_recorder_create")
         self.handle = h
@@ -269,9 +295,10 @@ class _ParamsHolder:
 
 
 def _box_args(box):
-    if isinstance(box, (HostBlackBox, Recorder)):
+    """Any object with ``fn_ptr`` (a zr_blackbox_fn) and ``ctx`` attributes."""
+    if hasattr(box, "fn_ptr") and hasattr(box, "ctx"):
         return box.fn_ptr, box.ctx
-    raise TypeError("black box must be a HostBlackBox or Recorder")
+    raise TypeError("black box must expose fn_ptr and ctx (HostBlackBox, Recorder, ...)")
 
 
 def reconstruct(p: int, deg: Sequence[int], box, sched=None, seed: int = 0, nprobes: Optional[int] = None,
@@ -298,6 +325,146 @@ def balanced_reconstruct(p: int, deg_num: Sequence[int], deg_den: Sequence[int],
     if st != ZR_OK:
         raise ZippelError(st, "zippel_balanced_reconstruct")
     return _take(on, len(deg_num)), _take(od, len(deg_num))
+
+
+class _Dispatch:
+    """One zr_blackbox_fn for a batch whose boxes have different callbacks:
+    ctx carries the instance index."""
+
+    def __init__(self, boxes):
+        self.fns = [(BLACKBOX_FN(ctypes.cast(b.fn_ptr, ctypes.c_void_p).value), b.ctx) for b in boxes]
+        self._cb = BLACKBOX_FN(self._call)
+
+    def _call(self, ctx, pts, d_vals, stream):
+        fn, c = self.fns[ctx or 0]
+        return fn(c, pts, d_vals, stream)
+
+
+def reconstruct_batch(p: int, items: Sequence[dict], stream=None):
+    """Batched polynomial Zippel on the GPU (zippel_reconstruct_batch).  Each
+    item is a dict with keys deg, box and optionally sched, seed, nprobes,
+    last_stage.  Returns a list of (exps, coefs) or ZippelError per instance."""
+    n = len(items)
+    holders = [_ParamsHolder(p, it["deg"], None, it.get("sched"), it.get("seed", 0), it.get("nprobes"),
+                             it.get("last_stage", 0)) for it in items]
+    params = (ZrParams * max(n, 1))(*[h.s for h in holders])
+    boxes = [it["box"] for it in items]
+    fptrs = {ctypes.cast(b.fn_ptr, ctypes.c_void_p).value for b in boxes}
+    if len(fptrs) == 1:
+        fn = boxes[0].fn_ptr
+        ctxs = (ctypes.c_void_p * max(n, 1))(*[b.ctx for b in boxes])
+        disp = None
+    else:
+        disp = _Dispatch(boxes)
+        fn = ctypes.cast(disp._cb, ctypes.c_void_p)
+        ctxs = (ctypes.c_void_p * max(n, 1))(*range(n))
+    outs = (ZrPoly * max(n, 1))()
+    status = np.zeros(max(n, 1), np.int32)
+    st = lib().zippel_reconstruct_batch(n, params, fn, ctxs, _stream(stream), outs, status.ctypes.data)
+    if st != ZR_OK:
+        raise ZippelError(st, "zippel_reconstruct_batch")
+    res = []
+    for i in range(n):
+        if status[i] != ZR_OK:
+            res.append(ZippelError(int(status[i]), f"instance {i}"))
+        else:
+            res.append(_take(outs[i], len(items[i]["deg"])))
+    del disp
+    return res
+
+
+def autotune(p: int, stream=None):
+    """Measure the per-band choices of the batched solve on this device; returns them."""
+    tab = (ZrBandChoice * NBANDS)()
+    st = lib().zr_autotune(p, _stream(stream), tab)
+    if st != ZR_OK:
+        raise ZippelError(st, "zr_autotune")
+    return [(t.packed, t.min_chunk) for t in tab]
+
+
+def tuning_get():
+    tab = (ZrBandChoice * NBANDS)()
+    tuned = lib().zr_tuning_get(tab)
+    return bool(tuned), [(t.packed, t.min_chunk) for t in tab]
+
+
+def tuning_set(choices):
+    tab = (ZrBandChoice * NBANDS)(*[ZrBandChoice(int(a), int(b)) for a, b in choices])
+    st = lib().zr_tuning_set(tab)
+    if st != ZR_OK:
+        raise ZippelError(st, "zr_tuning_set")
+
+
+class Server:
+    """Request loop with continuous batching (zr_server_*).  submit() queues a
+    request (polynomial, or balanced when deg_den is given); step() admits what
+    fits and advances every active request by one stage; poll() returns the
+    result once finished."""
+
+    def __init__(self, p: int, hbm_budget: int = 8 << 30, max_active: int = 256, stream=None):
+        self.p = p
+        h = ctypes.c_void_p()
+        st = lib().zr_server_create(ctypes.byref(h), p, hbm_budget, max_active, _stream(stream))
+        if st != ZR_OK:
+            raise ZippelError(st, "zr_server_create")
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, deg, box, sched=None, seed: int = 0, nprobes: Optional[int] = None, deg_den=None,
+               expected_terms: int = 0, last_stage: int = 0) -> int:
+        h = _ParamsHolder(self.p, deg, deg_den, sched, seed, nprobes, last_stage)
+        fn, ctx = _box_args(box)
+        rid = ctypes.c_uint64()
+        st = lib().zr_server_submit(self.handle, ctypes.byref(h.s), 1 if deg_den is not None else 0, expected_terms,
+                                    fn, ctx, ctypes.byref(rid))
+        if st != ZR_OK:
+            raise ZippelError(st, "zr_server_submit")
+        self._keep[rid.value] = (box, len(deg), deg_den is not None)  # the box must outlive the request
+        return rid.value
+
+    def step(self):
+        a, p, f = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        st = lib().zr_server_step(self.handle, ctypes.byref(a), ctypes.byref(p), ctypes.byref(f))
+        if st != ZR_OK:
+            raise ZippelError(st, "zr_server_step")
+        return a.value, p.value, f.value
+
+    def poll(self, rid: int):
+        """None while pending or active; else (status, num, den) with num/den as
+        (exps, coefs) (den None for polynomial requests, both None on failure)."""
+        status = ctypes.c_int32()
+        num, den = ZrPoly(), ZrPoly()
+        r = lib().zr_server_poll(self.handle, rid, ctypes.byref(status), ctypes.byref(num), ctypes.byref(den))
+        if r == 1:
+            return None
+        if r != 0:
+            raise ZippelError(r, "zr_server_poll")
+        _, nv, bal = self._keep.pop(rid)
+        if status.value != ZR_OK:
+            lib().zr_poly_free(ctypes.byref(num))
+            lib().zr_poly_free(ctypes.byref(den))
+            return status.value, None, None
+        n = _take(num, nv)
+        d = _take(den, nv) if bal else None
+        if not bal:
+            lib().zr_poly_free(ctypes.byref(den))
+        return status.value, n, d
+
+    def stats(self):
+        s = ZrServerStats()
+        lib().zr_server_get_stats(self.handle, ctypes.byref(s))
+        return {n: getattr(s, n) for n, _ in ZrServerStats._fields_}
+
+    def close(self):
+        if self.handle:
+            lib().zr_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
 
 
 def vandermonde_solve_batch(p: int, systems: List[Tuple[np.ndarray, np.ndarray]], stream=None):

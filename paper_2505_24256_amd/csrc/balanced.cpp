@@ -32,7 +32,7 @@ static std::vector<int32_t> d2h_i32(const int32_t* d, size_t n, hipStream_t s) {
 }
 
 // Build a univariate skeleton (in variable 0) from host coefficients c[0..deg].
-static void host_skeleton(const Params& P, const std::vector<uint64_t>& c, DevArena& keep, Skeleton& S,
+void host_skeleton(const Params& P, const std::vector<uint64_t>& c, DevArena& keep, Skeleton& S,
                           hipStream_t s) {
   std::vector<uint32_t> idx;
   for (uint32_t r = 0; r < c.size(); ++r)
@@ -57,7 +57,7 @@ static void host_skeleton(const Params& P, const std::vector<uint64_t>& c, DevAr
 // Combine the per-slice statuses and degrees like the definition: the most
 // negative slice status first, then the slices must agree on (deg A, deg B)
 // and respect the bounds.
-static void check_slices(const std::vector<int32_t>& st, const std::vector<int32_t>& dA,
+void check_slices(const std::vector<int32_t>& st, const std::vector<int32_t>& dA,
                          const std::vector<int32_t>& dB, uint32_t bn, uint32_t bd, int32_t& rhoN, int32_t& rhoD) {
   int32_t worst = 0;
   for (int32_t v : st) worst = std::min(worst, v);
@@ -73,6 +73,55 @@ static void check_slices(const std::vector<int32_t>& st, const std::vector<int32
   if (rhoN > (int32_t)bn || rhoD > (int32_t)bd) throw Error(ZR_EDEGEN);
 }
 
+// Stage 1: Thiele in x_1 from the anchor and the first nodes (eq. 2); the
+// numerator and denominator become univariate skeletons in `keep`.
+void balanced_stage1(const Params& P, zr_blackbox_fn bb, void* ctx, DevArena& keep, Skeleton& SN, Skeleton& SD,
+                     hipStream_t s) {
+  const uint32_t n1 = P.nnodes[0] + 1;
+  std::vector<uint64_t> X = P.node_list(0, n1);
+  DevArena A(s);
+  uint64_t* F = A.alloc<uint64_t>(n1);
+  uint64_t* dX = A.alloc<uint64_t>(n1);
+  uint64_t* dA = A.alloc<uint64_t>(n1 + 1);
+  uint64_t* dB = A.alloc<uint64_t>(n1 + 1);
+  int32_t* dg = A.alloc<int32_t>(3);
+  uint64_t* scr = A.alloc<uint64_t>(3 * (size_t)n1 + 2);
+  h2d(dX, X.data(), n1 * 8, s);
+  call_bb(bb, ctx, P, 1, 1, P.y.data(), X.data(), n1, F, s);
+  check(thiele_slices(P.M, 1, n1, dX, F, dA, dB, dg, dg + 1, dg + 2, scr, s));
+  std::vector<int32_t> g = d2h_i32(dg, 3, s);
+  int32_t rn, rd;
+  check_slices({g[2]}, {g[0]}, {g[1]}, P.deg[0], P.deg_den[0], rn, rd);
+  std::vector<uint64_t> ca(rn + 1), cb(rd + 1);
+  d2h_sync(ca.data(), dA, (rn + 1) * 8, s);
+  d2h_sync(cb.data(), dB, (rd + 1) * 8, s);
+  host_skeleton(P, ca, keep, SN, s);
+  host_skeleton(P, cb, keep, SD, s);
+}
+
+// After the last stage: scale so that D(0) = 1 (ZR_ENORM if D has no constant
+// term), check the probes, download.
+void balanced_finish(const Params& P, zr_blackbox_fn bb, void* ctx, Skeleton& SN, Skeleton& SD, hipStream_t s,
+                     zr_poly* num, zr_poly* den) {
+  if (P.last == P.nvars) {
+    uint64_t c0 = 0;
+    if (SD.t) {
+      std::vector<uint16_t> e0(P.nvars);
+      for (uint32_t v = 0; v < P.nvars; ++v) d2h_sync(&e0[v], SD.exps + (size_t)v * SD.t, 2, s);
+      bool zero = true;
+      for (uint16_t e : e0) zero &= e == 0;
+      if (zero) d2h_sync(&c0, SD.coef, 8, s);
+    }
+    if (c0 == 0) throw Error(ZR_ENORM);
+    const uint64_t ci = zr_inv(P.M, c0);
+    check(scale_u64(P.M, SN.coef, SN.t, ci, s));
+    check(scale_u64(P.M, SD.coef, SD.t, ci, s));
+    if (P.nprobes) check_probes(P, bb, ctx, SN, &SD, s);
+  }
+  download(SN, s, num);
+  download(SD, s, den);
+}
+
 static void reconstruct_balanced(const zr_params* params, zr_blackbox_fn bb, void* ctx, hipStream_t s, zr_poly* num,
                                  zr_poly* den) {
   Params P(params, true);
@@ -82,30 +131,10 @@ static void reconstruct_balanced(const zr_params* params, zr_blackbox_fn bb, voi
   check(fill_i32(d_status, 0, 1, s));
   std::vector<std::unique_ptr<DevArena>> arenas;
   Skeleton SN, SD;
-  // ---- stage 1 -----------------------------------------------------------
   {
-    const uint32_t n1 = P.nnodes[0] + 1;
-    std::vector<uint64_t> X = P.node_list(0, n1);
-    DevArena A(s);
-    uint64_t* F = A.alloc<uint64_t>(n1);
-    uint64_t* dX = A.alloc<uint64_t>(n1);
-    uint64_t* dA = A.alloc<uint64_t>(n1 + 1);
-    uint64_t* dB = A.alloc<uint64_t>(n1 + 1);
-    int32_t* dg = A.alloc<int32_t>(3);
-    uint64_t* scr = A.alloc<uint64_t>(3 * (size_t)n1 + 2);
-    h2d(dX, X.data(), n1 * 8, s);
-    call_bb(bb, ctx, P, 1, 1, P.y.data(), X.data(), n1, F, s);
-    check(thiele_slices(P.M, 1, n1, dX, F, dA, dB, dg, dg + 1, dg + 2, scr, s));
-    std::vector<int32_t> g = d2h_i32(dg, 3, s);
-    int32_t rn, rd;
-    check_slices({g[2]}, {g[0]}, {g[1]}, P.deg[0], P.deg_den[0], rn, rd);
-    std::vector<uint64_t> ca(rn + 1), cb(rd + 1);
-    d2h_sync(ca.data(), dA, (rn + 1) * 8, s);
-    d2h_sync(cb.data(), dB, (rd + 1) * 8, s);
     auto* kp = new DevArena(s);
     arenas.emplace_back(kp);
-    host_skeleton(P, ca, *kp, SN, s);
-    host_skeleton(P, cb, *kp, SD, s);
+    balanced_stage1(P, bb, ctx, *kp, SN, SD, s);
   }
   counters().stages = 1;
   // ---- stages k >= 2 ---------------------------------------------------------
@@ -166,24 +195,7 @@ static void reconstruct_balanced(const zr_params* params, zr_blackbox_fn bb, voi
     SD = nD;
     counters().stages = k;
   }
-  // ---- normalisation: D(0) = 1 ----------------------------------------------
-  if (P.last == P.nvars) {
-    uint64_t c0 = 0;
-    if (SD.t) {
-      std::vector<uint16_t> e0(P.nvars);
-      for (uint32_t v = 0; v < P.nvars; ++v) d2h_sync(&e0[v], SD.exps + (size_t)v * SD.t, 2, s);
-      bool zero = true;
-      for (uint16_t e : e0) zero &= e == 0;
-      if (zero) d2h_sync(&c0, SD.coef, 8, s);
-    }
-    if (c0 == 0) throw Error(ZR_ENORM);
-    const uint64_t ci = zr_inv(P.M, c0);
-    check(scale_u64(P.M, SN.coef, SN.t, ci, s));
-    check(scale_u64(P.M, SD.coef, SD.t, ci, s));
-    if (P.nprobes) check_probes(P, bb, ctx, SN, &SD, s);
-  }
-  download(SN, s, num);
-  download(SD, s, den);
+  balanced_finish(P, bb, ctx, SN, SD, s, num, den);
 }
 
 }  // namespace zr

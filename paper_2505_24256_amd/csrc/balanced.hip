@@ -251,6 +251,18 @@ hipError_t balance_rhs(const zr_mod& M, uint32_t T, uint32_t nk, const uint64_t*
   return hipGetLastError();
 }
 
+// *out = code when any st[i] is nonzero (every writer stores the same value)
+__global__ void k_fold_status(const int32_t* __restrict__ st, uint32_t T, int32_t* __restrict__ out, int32_t code) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < T && st[i] != 0) *out = code;
+}
+
+hipError_t fold_status(const int32_t* st, uint32_t T, int32_t* out, int32_t code, hipStream_t s) {
+  if (T == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fold_status, dim3(cdiv(T, 256)), dim3(256), 0, s, st, T, out, code);
+  return hipGetLastError();
+}
+
 __global__ void k_scale(zr_mod M, uint64_t* v, size_t n, uint64_t c, uint64_t cp) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) v[i] = zr_shoup(M, v[i], c, cp);

@@ -91,4 +91,13 @@ void check_probes(const Params& P, zr_blackbox_fn bb, void* ctx, const Skeleton&
 void solve_stage(const Params& P, const Skeleton& S, uint64_t* vals, uint32_t R, hipStream_t s, int32_t* d_status);
 void download(const Skeleton& S, hipStream_t s, zr_poly* out);
 
+// balanced path pieces shared with the server
+void check_slices(const std::vector<int32_t>& st, const std::vector<int32_t>& dA, const std::vector<int32_t>& dB,
+                  uint32_t bn, uint32_t bd, int32_t& rhoN, int32_t& rhoD);
+void host_skeleton(const Params& P, const std::vector<uint64_t>& c, DevArena& keep, Skeleton& S, hipStream_t s);
+void balanced_stage1(const Params& P, zr_blackbox_fn bb, void* ctx, DevArena& keep, Skeleton& SN, Skeleton& SD,
+                     hipStream_t s);
+void balanced_finish(const Params& P, zr_blackbox_fn bb, void* ctx, Skeleton& SN, Skeleton& SD, hipStream_t s,
+                     zr_poly* num, zr_poly* den);
+
 }  // namespace zr

@@ -91,6 +91,9 @@ hipError_t balance_rhs(const zr_mod& M, uint32_t T, uint32_t nk, const uint64_t*
                        const uint64_t* dprev, uint32_t tN, int32_t rhoN, uint64_t* vN, size_t ldN, uint32_t tD,
                        int32_t rhoD, uint64_t* vD, size_t ldD, int32_t* st, hipStream_t s);
 
+// *out = code when any of st[0..T) is nonzero (out left alone otherwise).
+hipError_t fold_status(const int32_t* st, uint32_t T, int32_t* out, int32_t code, hipStream_t s);
+
 // Scale every coefficient by c (in place).
 hipError_t scale_u64(const zr_mod& M, uint64_t* v, size_t n, uint64_t c, hipStream_t s);
 

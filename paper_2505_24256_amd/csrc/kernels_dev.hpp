@@ -1,0 +1,504 @@
+// Device bodies of the polynomial-path kernels, shared by the one-system
+// launches (kernels.hip) and the batched, work-list launches (batch.hip).
+// Each body handles one block's worth of work given its block coordinates, so
+// that the same arithmetic runs whether the coordinates come from the launch
+// grid or from a work list.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "field.hpp"
+
+namespace zr {
+
+__host__ __device__ static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+// ---- transposed Vandermonde solve ----------------------------------------------
+
+// Right-hand sides per tile: a tile of 20 leaves room for the chain state
+// within 256 VGPRs.
+constexpr uint32_t kMaxRT = 20;
+
+struct VsArgs {
+  zr_mod M;
+  uint32_t t, L, S, R, ldv;
+  const uint64_t* mono;
+  const uint64_t* mono_p;
+  const uint64_t* Mc;
+  const uint64_t* VT;
+  const uint64_t* qstart;
+  uint64_t* Bc;
+  uint64_t* spart;
+  uint64_t* hpart;
+};
+
+__device__ __forceinline__ void chunk_range(uint32_t t, uint32_t L, uint32_t c, uint32_t& lo, uint32_t& hi) {
+  hi = t - c * L;
+  lo = hi > L ? hi - L : 0;
+}
+
+// Packed right-hand sides, word idx of [ntile][t][ldv] (32-bit words): for
+// jj < RT the value v = v^(tile*RT + jj)_{r+1} as three limbs v & (2^22-1),
+// (v >> 22) & (2^22-1), v >> 44 at words 3jj..3jj+2; M_r at words 3RT, 3RT+1;
+// zero padding.
+__device__ __forceinline__ uint32_t pack_word(size_t idx, uint32_t t, uint32_t R, uint32_t RT, uint32_t ldv,
+                                              const uint64_t* __restrict__ rhs, size_t ld_rhs,
+                                              const uint64_t* __restrict__ Mc) {
+  const uint32_t w = (uint32_t)(idx % ldv);
+  const size_t rest = idx / ldv;
+  const uint32_t r = (uint32_t)(rest % t), tile = (uint32_t)(rest / t);
+  uint32_t out = 0;
+  if (w < 3 * RT) {
+    const uint32_t jj = w / 3, limb = w % 3;
+    const uint32_t j = tile * RT + jj;
+    const uint64_t v = j < R ? rhs[(size_t)j * ld_rhs + r] : 0;
+    out = (uint32_t)((v >> (22 * limb)) & (limb < 2 ? 0x3FFFFFu : 0xFFFFFFFFu));
+  } else if (w == 3 * RT) {
+    out = (uint32_t)Mc[r];
+  } else if (w == 3 * RT + 1) {
+    out = (uint32_t)(Mc[r] >> 32);
+  }
+  return out;
+}
+
+// Pass 1 for row l, chunk c < S-1: chain only, from 0: B_c = sum_r M_r m^(r-lo).
+__device__ __forceinline__ void vs_chain_body(const VsArgs& a, uint32_t l, uint32_t c) {
+  uint32_t lo, hi;
+  chunk_range(a.t, a.L, c, lo, hi);
+  const uint64_t m = a.mono[l], mp = a.mono_p[l];
+  uint64_t x = 0;
+  // M_r for r = hi-1 down to lo, eight at a time, the next eight fetched ahead
+  uint32_t r = hi;
+  uint64_t cur[8], nxt[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) cur[u] = r >= (uint32_t)u + 1 + lo ? a.Mc[r - 1 - u] : 0;
+  while (r > lo) {
+    const uint32_t rn = r > lo + 8 ? r - 8 : lo;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) nxt[u] = rn >= (uint32_t)u + 1 + lo ? a.Mc[rn - 1 - u] : 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (r - u > lo) x = zr_add(a.M, zr_shoup(a.M, x, m, mp), cur[u]);
+    r = rn;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) cur[u] = nxt[u];
+  }
+  a.Bc[(size_t)c * a.t + l] = x;
+}
+
+// Per-row scan over chunks: qstart[0] = 1, qstart[c] = m^L qstart[c-1] + B_{c-1}.
+__device__ __forceinline__ void vs_scan_body(const VsArgs& a, uint32_t l, uint64_t* __restrict__ qstart,
+                                             uint64_t* __restrict__ mL_out) {
+  const uint64_t m = a.mono[l];
+  const uint64_t mL = zr_pow(a.M, m, a.L), mLp = zr_shoup_pre(a.M, mL);
+  mL_out[l] = mL;
+  uint64_t q = 1 % a.M.p;
+  qstart[l] = q;
+  for (uint32_t c = 1; c < a.S; ++c) {
+    q = zr_add(a.M, zr_shoup(a.M, q, mL, mLp), a.Bc[(size_t)(c - 1) * a.t + l]);
+    qstart[(size_t)c * a.t + l] = q;
+  }
+}
+
+// Carry-free exact dot products.  q = q0 + q1 2^32 (32-bit halves, per lane)
+// and v = v0 + v1 2^22 + v2 2^44 (22-bit limbs, packed once per system), so
+//   q v = q0 v0 + q0 v1 2^22 + q1 v0 2^32 + q0 v2 2^44 + q1 v1 2^54 + q1 v2 2^76,
+// six 32x32 products below 2^54, each summed by one v_mad_u64_u32 into its own
+// 64-bit column.  A column absorbs 1024 such products; every kFold steps the
+// bits above each column's range are moved into the column of matching weight
+// (exact shifts and adds), so chunks of any length stay exact.
+struct Acc6 {
+  uint64_t w0, w22, w32, w44, w54, w76;
+};
+constexpr uint32_t kFold = 512;
+
+__device__ __forceinline__ void acc6_zero(Acc6& a) {
+  a.w0 = a.w22 = a.w32 = a.w44 = a.w54 = a.w76 = 0;
+}
+
+__device__ __forceinline__ void acc6_mac(Acc6& a, uint32_t q0, uint32_t q1, uint32_t v0, uint32_t v1, uint32_t v2) {
+  a.w0 += (uint64_t)q0 * v0;
+  a.w22 += (uint64_t)q0 * v1;
+  a.w44 += (uint64_t)q0 * v2;
+  a.w32 += (uint64_t)q1 * v0;
+  a.w54 += (uint64_t)q1 * v1;
+  a.w76 += (uint64_t)q1 * v2;
+}
+
+// Move everything above bit 54 of each weight-0..44 column into w54, and
+// everything above bit 22 of w54 into w76.
+__device__ __forceinline__ void acc6_fold(Acc6& a) {
+  a.w54 += (a.w0 >> 54) + (a.w22 >> 32) + (a.w32 >> 22) + (a.w44 >> 10);
+  a.w0 &= (1ull << 54) - 1;
+  a.w22 &= (1ull << 32) - 1;
+  a.w32 &= (1ull << 22) - 1;
+  a.w44 &= (1ull << 10) - 1;
+  a.w76 += a.w54 >> 22;
+  a.w54 &= (1ull << 22) - 1;
+}
+
+// add x * 2^s (x < 2^64, s < 128) to the 192-bit (w[0], w[1], w[2])
+__device__ __forceinline__ void add_shift192(uint64_t w[3], uint64_t x, uint32_t s) {
+  const uint32_t o = s >> 6, b = s & 63;
+  const zr_u128 v = ((zr_u128)x) << b;
+  const uint64_t lo = (uint64_t)v, hi = (uint64_t)(v >> 64);
+  if (o == 0) {
+    zr_u128 t = (zr_u128)w[0] + lo;
+    w[0] = (uint64_t)t;
+    t = (zr_u128)w[1] + hi + (uint64_t)(t >> 64);
+    w[1] = (uint64_t)t;
+    w[2] += (uint64_t)(t >> 64);
+  } else {
+    zr_u128 t = (zr_u128)w[1] + lo;
+    w[1] = (uint64_t)t;
+    w[2] += hi + (uint64_t)(t >> 64);
+  }
+}
+
+__device__ __forceinline__ uint64_t acc6_reduce(const zr_mod& M, const Acc6& a) {
+  uint64_t w[3] = {0, 0, 0};
+  add_shift192(w, a.w0, 0);
+  add_shift192(w, a.w22, 22);
+  add_shift192(w, a.w32, 32);
+  add_shift192(w, a.w44, 44);
+  add_shift192(w, a.w54, 54);
+  add_shift192(w, a.w76, 76);
+  uint64_t r = zr_mod128(M, 0, w[2]);
+  r = zr_mod128(M, r, w[1]);
+  return zr_mod128(M, r, w[0]);
+}
+
+
+// Pass 2 for 64 rows (one wave, lane = row): chain + Horner + RT right-hand-side
+// dot products over one chunk.  Packed row r of a tile is identical for all
+// lanes: each 64-byte group of it is one scalar load, issued for step r-1 as
+// soon as step r has consumed the group, so its latency hides behind the
+// remaining work.
+struct alignas(64) VGroup {
+  uint32_t w[16];
+};
+
+template <int RT>
+__device__ __forceinline__ void vs_dots_body(const VsArgs& a, uint32_t rb, uint32_t c, uint32_t tile) {
+  constexpr int LDV = (3 * RT + 2 + 15) & ~15;
+  constexpr int G = LDV / 16;
+  const uint32_t l0 = rb * 64 + (threadIdx.x & 63);
+  const bool live = l0 < a.t;
+  const uint32_t l = live ? l0 : a.t - 1;
+  uint32_t lo, hi;
+  chunk_range(a.t, a.L, c, lo, hi);
+  const zr_mod M = a.M;
+  const uint64_t m = a.mono[l], mp = a.mono_p[l];
+  uint64_t q = a.qstart ? a.qstart[(size_t)c * a.t + l] : 1 % M.p;
+  uint64_t h = 0;
+  Acc6 acc[RT];
+#pragma unroll
+  for (int j = 0; j < RT; ++j) acc6_zero(acc[j]);
+  const VGroup* __restrict__ rows = (const VGroup*)((const uint32_t*)a.VT + (size_t)tile * a.t * LDV);
+  const bool horner = tile == 0;
+  uint32_t r = hi - 1;
+  uint32_t since = 0;
+  VGroup buf[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) buf[g] = rows[(size_t)r * G + g];
+  for (;;) {
+    const uint32_t rn = r > lo ? r - 1 : r;
+    const uint32_t q0 = (uint32_t)q, q1 = (uint32_t)(q >> 32);
+    uint32_t mlo = 0, mhi = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+#pragma unroll
+      for (int jj = 0; jj < RT; ++jj) {
+        if (3 * jj / 16 == g) {
+          // the three limbs of value jj may straddle two groups
+          const int w0 = 3 * jj, w1 = 3 * jj + 1, w2 = 3 * jj + 2;
+          const uint32_t v0 = buf[w0 / 16].w[w0 % 16];
+          const uint32_t v1 = buf[w1 / 16].w[w1 % 16];
+          const uint32_t v2 = buf[w2 / 16].w[w2 % 16];
+          acc6_mac(acc[jj], q0, q1, v0, v1, v2);
+        }
+      }
+      if ((3 * RT) / 16 == g) mlo = buf[g].w[(3 * RT) % 16];
+      if ((3 * RT + 1) / 16 == g) mhi = buf[g].w[(3 * RT + 1) % 16];
+      // every later read of this step lies in groups > g (a value's limbs
+      // only extend forward), so group g can be refilled for step r-1 now
+      buf[g] = rows[(size_t)rn * G + g];
+    }
+    const uint64_t Mr = ((uint64_t)mhi << 32) | mlo;
+    if (horner) h = zr_add(M, zr_shoup(M, h, m, mp), q);
+    q = zr_add(M, zr_shoup(M, q, m, mp), Mr);
+    if (++since == kFold) {
+#pragma unroll
+      for (int j = 0; j < RT; ++j) acc6_fold(acc[j]);
+      since = 0;
+    }
+    if (r == lo) break;
+    r = rn;
+  }
+  if (live) {
+    const uint32_t j0 = tile * RT;
+#pragma unroll
+    for (int j = 0; j < RT; ++j)
+      if (j0 + j < a.R) a.spart[((size_t)c * a.R + j0 + j) * a.t + l] = acc6_reduce(M, acc[j]);
+    if (horner) a.hpart[(size_t)c * a.t + l] = h;
+  }
+}
+
+// Combine chunks, part 1 for row l: delta = sum_c m^{lo_c} H_c by Horner over
+// the chunk partials, w = m delta, and its inverse (with Shoup constant) into
+// winv[2t]; a zero w marks the system singular.
+__device__ __forceinline__ void vs_delta_body(const VsArgs& a, uint32_t l, const uint64_t* __restrict__ mLv,
+                                              uint64_t* __restrict__ winv, int32_t* __restrict__ status) {
+  const zr_mod M = a.M;
+  const uint64_t m = a.mono[l];
+  uint64_t delta = a.hpart[l];
+  if (a.S > 1) {
+    const uint64_t mL = mLv[l], mLp = zr_shoup_pre(M, mL);
+    const uint32_t len_last = a.t - (a.S - 1) * a.L;
+    const uint64_t mlast = zr_pow(M, m, len_last);
+    for (uint32_t c = 1; c < a.S; ++c) {
+      const uint64_t hc = a.hpart[(size_t)c * a.t + l];
+      delta = (c + 1 < a.S) ? zr_add(M, zr_shoup(M, delta, mL, mLp), hc) : zr_add(M, zr_mul(M, delta, mlast), hc);
+    }
+  }
+  const uint64_t w = zr_mul(M, m, delta);
+  if (w == 0) {
+    atomicExch(status, -3);  // ZR_ESINGULAR
+    winv[l] = 0;
+    winv[a.t + l] = 0;
+    return;
+  }
+  const uint64_t wi = zr_inv(M, w);
+  winv[l] = wi;
+  winv[a.t + l] = zr_shoup_pre(M, wi);
+}
+
+// Combine chunks, part 2 for row l and right-hand side j:
+// a^(j)_l = (sum_c s^(j)_{l,c}) / (m_l delta_l).
+__device__ __forceinline__ void vs_scale_body(const VsArgs& a, uint32_t l, uint32_t j, const uint64_t* __restrict__ winv,
+                                              uint64_t* __restrict__ out, size_t ld_out) {
+  const zr_mod M = a.M;
+  uint64_t s = 0;
+  for (uint32_t c = 0; c < a.S; ++c) s = zr_add(M, s, a.spart[((size_t)c * a.R + j) * a.t + l]);
+  out[(size_t)j * ld_out + l] = zr_shoup(M, s, winv[l], winv[a.t + l]);
+}
+
+// ---- master polynomial (product tree) -------------------------------------------
+
+__device__ __forceinline__ uint4 limbs22(uint64_t v) {
+  return make_uint4((uint32_t)(v & 0x3FFFFF), (uint32_t)((v >> 22) & 0x3FFFFF), (uint32_t)(v >> 44), 0u);
+}
+
+// Bottom levels (factors of degree < 64) in LDS for leaves [b, b+64) of a
+// system of t leaves: pairwise products level by level; node boundaries
+// (multiples of 2h) coincide with those of the whole tree, including the
+// ragged end.  Writes the non-leading coefficients and their limbs.
+// buf: 2 x 64 words of LDS.
+__device__ __forceinline__ void master_small_body(const zr_mod& M, uint32_t t, uint32_t b,
+                                                  const uint64_t* __restrict__ mono, uint64_t* __restrict__ out,
+                                                  uint4* __restrict__ limbs, uint64_t* buf) {
+  const uint32_t k = threadIdx.x & 63;
+  const uint32_t n = std::min<uint32_t>(64, t - b);
+  uint64_t* cur = buf;
+  uint64_t* nxt = buf + 64;
+  if (k < n) cur[k] = zr_neg(M, mono[b + k] % M.p);
+  __syncthreads();
+  for (uint32_t half = 1; half < 64 && half < t; half *= 2) {
+    if (k < n) {
+      const uint32_t a = (k / (2 * half)) * (2 * half);
+      const uint32_t n1 = std::min(half, n - a);
+      const uint32_t n2 = std::min(half, n - a - n1);
+      const uint32_t kk = k - a;
+      const uint64_t* Lc = cur + a;
+      const uint64_t* Rc = cur + a + n1;
+      zr_acc192 acc;
+      zr_acc_zero(acc);
+      if (n2 > 0) {
+        const uint32_t ilo = kk + 1 > n2 ? kk + 1 - n2 : 0;
+        const uint32_t ihi = std::min(kk, n1 - 1);
+        for (uint32_t i = ilo; i <= ihi; ++i) zr_acc_mac(acc, Lc[i], Rc[kk - i]);
+      }
+      if (kk >= n1) zr_acc_mac(acc, 1, Rc[kk - n1]);
+      if (kk >= n2) zr_acc_mac(acc, 1, Lc[kk - n2]);
+      nxt[k] = zr_acc_reduce(M, acc);
+    }
+    __syncthreads();
+    uint64_t* tswap = cur;
+    cur = nxt;
+    nxt = tswap;
+  }
+  if (k < n) {
+    out[b + k] = cur[k];
+    limbs[b + k] = limbs22(cur[k]);
+  }
+}
+
+// Large levels (factors of degree >= 64): a wave owns 64 consecutive output
+// coefficients g0.. of one product and one chunk ic of the convolution index.
+// The factor L_i is wave-uniform: the level's coefficients carry their 22-bit
+// limbs (four 32-bit words per value) so that eight of them arrive with two
+// 64-byte scalar loads.  The window of R needed by the wave, R_{k-i} for its k
+// and i, is staged once in LDS (win: 64 + kConvIC + 8 words).  With one chunk
+// per product the wave finishes the coefficient (adding the terms of the
+// leading ones) and writes it with its limbs; otherwise chunk partial sums go
+// to part[ic][g] and master_sum_body finishes them.
+constexpr uint32_t kConvIC = 512;
+
+struct alignas(16) L8 {
+  uint4 v[8];
+};
+
+__device__ __forceinline__ uint64_t master_linear_terms(const zr_mod& M, uint64_t s, const uint64_t* cur, uint32_t a,
+                                                        uint32_t n1, uint32_t n2, uint32_t k) {
+  if (k >= n1) s = zr_add(M, s, cur[a + n1 + (k - n1)]);
+  if (k >= n2) s = zr_add(M, s, cur[a + (k - n2)]);
+  return s;
+}
+
+__device__ __forceinline__ void master_conv_body(const zr_mod& M, uint32_t t, uint32_t half, uint32_t nic,
+                                                 uint32_t g0, uint32_t ic, const uint64_t* __restrict__ cur,
+                                                 const uint4* __restrict__ limbs, uint64_t* __restrict__ part,
+                                                 size_t ld_part, uint64_t* __restrict__ nxt,
+                                                 uint4* __restrict__ limbs_nxt, uint64_t* win) {
+  const uint32_t g = g0 + (threadIdx.x & 63);
+  const uint32_t a = (g0 / (2 * half)) * (2 * half);  // one product per wave since 2*half >= 64
+  const uint32_t n1 = std::min(half, t - a);
+  const uint32_t n2 = std::min(half, t - a - n1);
+  const uint32_t k0 = g0 - a;
+  const uint32_t k = g - a;
+  const uint64_t* __restrict__ Rc = cur + a + n1;
+  Acc6 acc;
+  acc6_zero(acc);
+  uint32_t ilo = ic * kConvIC, ihi = std::min(ilo + kConvIC, n1);
+  if (n2 > 0) {
+    const uint32_t wlo = k0 + 1 > n2 ? k0 + 1 - n2 : 0;
+    const uint32_t whi = std::min(k0 + 64, n1);
+    ilo = std::max(ilo, wlo);
+    ihi = std::min(ihi, whi);
+  } else {
+    ihi = ilo;
+  }
+  if (ilo < ihi) {
+    // round the i range up to whole groups of 8; the extra i are masked
+    const uint32_t ihi8 = ilo + ((ihi - ilo + 7) & ~7u);
+    // window: R index j = k - i for k in [k0, k0+63], i in [ilo, ihi8): j in [k0 - ihi8 + 1, k0 + 63 - ilo]
+    const int64_t jbase = (int64_t)k0 - (int64_t)ihi8 + 1;
+    const uint32_t wlen = 63 + (ihi8 - ilo);
+    for (uint32_t x = threadIdx.x & 63; x < wlen; x += 64) {
+      const int64_t j = jbase + x;
+      win[x] = (j >= 0 && j < (int64_t)n2) ? Rc[j] : 0;
+    }
+    __syncthreads();
+    const uint4* __restrict__ Lg = limbs + a;
+    const uint64_t* __restrict__ wk = win + ((int64_t)k - jbase);
+    L8 L = *(const L8*)(Lg + ilo);
+    for (uint32_t i = ilo; i < ihi8; i += 8) {
+      // fetch the next group of eight coefficients while this one is used
+      const uint32_t in8 = i + 8 < ihi8 ? i + 8 : i;
+      const L8 Ln = *(const L8*)(Lg + in8);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const uint64_t Rv = wk[-(int64_t)(i + u)];
+        const bool in = i + u < ihi;
+        acc6_mac(acc, (uint32_t)Rv, (uint32_t)(Rv >> 32), in ? L.v[u].x : 0u, in ? L.v[u].y : 0u, in ? L.v[u].z : 0u);
+      }
+      L = Ln;
+    }
+  }
+  if (g >= t) return;
+  const uint64_t s = acc6_reduce(M, acc);
+  if (nic == 1) {
+    const uint64_t v = master_linear_terms(M, s, cur, a, n1, n2, k);
+    nxt[g] = v;
+    limbs_nxt[g] = limbs22(v);
+  } else {
+    part[(size_t)ic * ld_part + g] = s;
+  }
+}
+
+__device__ __forceinline__ void master_sum_body(const zr_mod& M, uint32_t t, uint32_t half, uint32_t nic, uint32_t g,
+                                                const uint64_t* __restrict__ cur, const uint64_t* __restrict__ part,
+                                                size_t ld_part, uint64_t* __restrict__ nxt,
+                                                uint4* __restrict__ limbs_nxt) {
+  const uint32_t a = (g / (2 * half)) * (2 * half);
+  const uint32_t n1 = std::min(half, t - a);
+  const uint32_t n2 = std::min(half, t - a - n1);
+  uint64_t s = 0;
+  for (uint32_t ic = 0; ic < nic; ++ic) s = zr_add(M, s, part[(size_t)ic * ld_part + g]);
+  const uint64_t v = master_linear_terms(M, s, cur, a, n1, n2, g - a);
+  nxt[g] = v;
+  limbs_nxt[g] = limbs22(v);
+}
+
+// ---- Newton lift (eq. 1) ----------------------------------------------------------
+// g[d][l] = sum_i W[d][i] vals[i][l] for the 64 terms of row block rb and the
+// kNewtonDB coefficients d0..; Wl holds W as limbs [i][d][3].
+constexpr int kNewtonDB = 8;
+
+__device__ __forceinline__ void newton_body(const zr_mod& M, uint32_t t, uint32_t D1, uint32_t rb, uint32_t d0,
+                                            const uint64_t* __restrict__ vals, const uint32_t* __restrict__ Wl,
+                                            uint64_t* __restrict__ g) {
+  const uint32_t l0 = rb * 64 + (threadIdx.x & 63);
+  const bool live = l0 < t;
+  const uint32_t l = live ? l0 : t - 1;
+  Acc6 acc[kNewtonDB];
+#pragma unroll
+  for (int e = 0; e < kNewtonDB; ++e) acc6_zero(acc[e]);
+  // the kNewtonDB x 3 limbs of W[d0..][i] for the next i are fetched ahead
+  uint32_t wc[3 * kNewtonDB], wn[3 * kNewtonDB];
+#pragma unroll
+  for (int e = 0; e < 3 * kNewtonDB; ++e) wc[e] = Wl[(size_t)d0 * 3 + e];
+  for (uint32_t i0 = 0; i0 < D1; i0 += 8) {
+    uint64_t vv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) vv[u] = i0 + u < D1 ? vals[(size_t)(i0 + u) * t + l] : 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint32_t i = i0 + u;
+      if (i >= D1) break;
+      const uint32_t inext = i + 1 < D1 ? i + 1 : i;
+#pragma unroll
+      for (int e = 0; e < 3 * kNewtonDB; ++e) wn[e] = Wl[((size_t)inext * D1 + d0) * 3 + e];
+      const uint32_t v0 = (uint32_t)vv[u], v1 = (uint32_t)(vv[u] >> 32);
+#pragma unroll
+      for (int e = 0; e < kNewtonDB; ++e)
+        if (d0 + e < D1) acc6_mac(acc[e], v0, v1, wc[3 * e], wc[3 * e + 1], wc[3 * e + 2]);
+#pragma unroll
+      for (int e = 0; e < 3 * kNewtonDB; ++e) wc[e] = wn[e];
+    }
+  }
+  if (!live) return;
+#pragma unroll
+  for (int e = 0; e < kNewtonDB; ++e)
+    if (d0 + e < D1) g[(size_t)(d0 + e) * t + l] = acc6_reduce(M, acc[e]);
+}
+
+__device__ __forceinline__ uint32_t count_nz(uint32_t t, uint32_t D1, const uint64_t* __restrict__ g, uint32_t l) {
+  uint32_t n = 0;
+  for (uint32_t d = 0; d < D1; ++d) n += g[(size_t)d * t + l] != 0;
+  return n;
+}
+
+// ---- skeleton expansion ------------------------------------------------------------
+// Term (e_l, d) of a nonzero g[d][l] goes to position off[l] + (rank of d among
+// the nonzero coefficients of term l): lexicographic order is kept.
+__device__ __forceinline__ void expand_body(const zr_mod& M, uint32_t t, uint32_t kvar, uint32_t nvars, uint32_t l,
+                                            uint32_t d, const uint16_t* __restrict__ exps_old, size_t ld_old,
+                                            const uint64_t* __restrict__ mono_old, const uint64_t* __restrict__ g,
+                                            uint32_t off_l, const uint64_t* __restrict__ ypow,
+                                            const uint64_t* __restrict__ ypowp, uint16_t* __restrict__ exps_new,
+                                            uint64_t* __restrict__ coef_new, uint64_t* __restrict__ mono_new,
+                                            size_t ld_new) {
+  const uint64_t c = g[(size_t)d * t + l];
+  if (c == 0) return;
+  uint32_t pos = off_l;
+  for (uint32_t e = 0; e < d; ++e) pos += g[(size_t)e * t + l] != 0;
+  for (uint32_t v = 0; v < nvars; ++v)
+    exps_new[(size_t)v * ld_new + pos] = v == kvar ? (uint16_t)d : exps_old[(size_t)v * ld_old + l];
+  coef_new[pos] = c;
+  mono_new[pos] = zr_shoup(M, mono_old[l], ypow[d], ypowp[d]);
+}
+
+}  // namespace zr

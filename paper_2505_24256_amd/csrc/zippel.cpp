@@ -312,7 +312,8 @@ StageConsts::StageConsts(const Params& P, DevArena& A, const std::vector<uint32_
     if (!D1s[v]) continue;
     Ws[v] = newton_matrix_limbs(P.M, P.node_list(v, D1s[v]));
     woff[v] = words;
-    words += (Ws[v].size() + 1) & ~(size_t)1;
+    // zero padding: the lift kernel fetches whole groups of limbs ahead of use
+    words += (Ws[v].size() + 3 * 8 + 1) & ~(size_t)1;
     yoff[v] = words;
     words += 4 * (size_t)D1s[v];
   }

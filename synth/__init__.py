@@ -74,30 +74,36 @@ class SplitMix64:
                 return lo + u % n
 
     def uniform_block(self, lo: int, hi: int, count: int) -> np.ndarray:
-        """``count`` draws of ``uniform(lo, hi)``, identical to calling it in a loop."""
+        """``count`` draws of ``uniform(lo, hi)``, identical to calling it in a loop:
+        raw outputs are drawn in bulk, rejected ones skipped in order, and the
+        stream is left just after the last raw output consumed."""
         n = hi - lo
         assert n >= 1
         lim = ((1 << 64) // n) * n
-        out = np.empty(count, dtype=np.uint64)
+        if count <= 0:
+            return np.zeros(0, dtype=np.uint64)
+        if n == (1 << 64):
+            return self.block(count)
+        if lim == (1 << 64):
+            return np.uint64(lo) + self.block(count) % np.uint64(n)
+        rate = lim / float(1 << 64)
+        parts = []
         got = 0
         while got < count:
             need = count - got
-            raw = self.block(need)
-            if lim == (1 << 64):
-                ok = np.ones(need, dtype=bool)
-            else:
-                ok = raw < np.uint64(lim)
-            if ok.all():
-                out[got:] = np.uint64(lo) + raw % np.uint64(n)
+            m = int(need / rate * 1.02) + 64
+            raw = self.block(m)
+            idx = np.flatnonzero(raw < np.uint64(lim))
+            if len(idx) >= need:
+                last = int(idx[need - 1])
+                parts.append(np.uint64(lo) + raw[idx[:need]] % np.uint64(n))
+                # give back the raw outputs after the last one used
+                self.state = (self.state - (m - last - 1) * _GAMMA) & _MASK
                 got = count
             else:
-                # keep the accepted prefix up to the first rejection, re-sync the
-                # stream just after that rejection, and continue
-                first_bad = int(np.argmin(ok))
-                out[got:got + first_bad] = np.uint64(lo) + raw[:first_bad] % np.uint64(n)
-                got += first_bad
-                self.state = (self.state - (need - first_bad - 1) * _GAMMA) & _MASK
-        return out
+                parts.append(np.uint64(lo) + raw[idx] % np.uint64(n))
+                got += len(idx)
+        return np.concatenate(parts)
 
 
 # --------------------------------------------------------------------------
@@ -210,21 +216,27 @@ def random_poly(p: int, nvars: int, deg: Sequence[int] | int, nterms: int, seed:
                 u //= deg[v] + 1
     else:
         # draw candidate rows in bulk; first occurrences in stream order win
-        exps_list = []
-        seen = set()
+        # (rows compared through their mixed-radix index, which fits in 64 bits)
+        radix = np.array([d + 1 for d in deg], dtype=object)
+        assert space < (1 << 63)
+        kept = []
+        seen_keys = np.zeros(0, dtype=np.int64)
         bulk = max(1024, nterms * 2)
-        while len(exps_list) < nterms:
+        total = 0
+        while total < nterms:
             cols = [g.uniform_block(0, deg[v] + 1, bulk) for v in range(nvars)]
             cand = np.stack(cols, axis=1).astype(np.uint16)
-            for row in cand:
-                key = row.tobytes()
-                if key in seen:
-                    continue
-                seen.add(key)
-                exps_list.append(row)
-                if len(exps_list) == nterms:
-                    break
-        exps = np.array(exps_list, dtype=np.uint16).reshape(nterms, nvars)
+            key = np.zeros(bulk, dtype=np.int64)
+            for v in range(nvars):
+                key = key * int(radix[v]) + cand[:, v].astype(np.int64)
+            _, first = np.unique(key, return_index=True)
+            first.sort()
+            first = first[~np.isin(key[first], seen_keys)]
+            first = first[:nterms - total]
+            kept.append(cand[first])
+            seen_keys = np.concatenate([seen_keys, key[first]])
+            total += len(first)
+        exps = np.concatenate(kept).reshape(nterms, nvars)
     coefs = g.uniform_block(1, p, nterms)
     return SparsePoly(p, nvars, exps, coefs).sorted()
 
@@ -369,6 +381,25 @@ def config_workload(idx: int, nprobes: int = 2) -> PolyWorkload:
     return poly_workload(name, n, d, t, idx, 1000 + idx, nprobes)
 
 
+def batch_workload(count: int = 4096, seed: int = 4, tmin: int = 10, tmax: int = 20_000, deg: int = 30,
+                   nmin: int = 3, nmax: int = 8, nprobes: int = 2, p: Optional[int] = None) -> List[PolyWorkload]:
+    """Many independent instances sharing p: n uniform in [nmin, nmax], t
+    log-uniform in [tmin, tmax] (capped by the number of monomials), per-variable
+    degree bound `deg`; instance i uses hidden-polynomial seed seed*10^6 + i and
+    schedule seed seed*10^6 + 500000 + i."""
+    p = make_prime() if p is None else p
+    g = SplitMix64(seed * 7919 + 1)
+    out = []
+    for i in range(count):
+        n = nmin + int(g.uniform(0, nmax - nmin + 1))
+        u = g.next() / 2.0 ** 64
+        t = int(round(math.exp(math.log(tmin) + u * (math.log(tmax) - math.log(tmin)))))
+        t = max(1, min(t, (deg + 1) ** n))
+        out.append(poly_workload(f"b{i}", n, deg, t, seed * 1_000_000 + i, seed * 1_000_000 + 500_000 + i,
+                                 nprobes, p))
+    return out
+
+
 def rational_workload(nvars: int, total_deg: int, tnum: int, tden: int, seed: int,
                       nprobes: int = 2, p: Optional[int] = None,
                       name: str = "rational") -> RationalWorkload:
@@ -411,6 +442,10 @@ def lib_path() -> str:
     return os.path.join(_HERE, "libzsynth.so")
 
 
+def dev_lib_path() -> str:
+    return os.path.join(_HERE, "libzsynth_hip.so")
+
+
 def build(verbose: bool = False) -> str:
     import subprocess
     src = os.path.join(_HERE, "blackbox.c")
@@ -418,6 +453,13 @@ def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11", "-o", out + ".tmp", src]
     subprocess.run(cmd, check=True, capture_output=not verbose)
     os.replace(out + ".tmp", out)
+    dsrc = os.path.join(_HERE, "devbox.hip")
+    dout = dev_lib_path()
+    cmd = ["hipcc", "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument",
+           "-o", dout + ".tmp", dsrc]
+    subprocess.run(cmd, check=True, capture_output=not verbose)
+    os.replace(dout + ".tmp", dout)
     return out
 
 
@@ -431,6 +473,9 @@ def lib():
         L.zs_eval_points.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
                                      ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                      ctypes.c_void_p, ctypes.c_void_p]
+        L.zs_group_stage.restype = ctypes.c_uint64
+        L.zs_group_stage.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         _LIB = L
     return _LIB
 
@@ -495,3 +540,108 @@ class BlackBox:
     @staticmethod
     def c_function_address() -> int:
         return ctypes.cast(lib().zs_eval_points, ctypes.c_void_p).value
+
+
+# --------------------------------------------------------------------------
+# device black box: the same values as BlackBox, computed on the GPU for the
+# structured Zippel points (large workloads); small requests use the host.
+
+class _ZrPoints(ctypes.Structure):
+    # layout of zr_points in include/zippel.h
+    _fields_ = [("nvars", ctypes.c_uint32), ("k", ctypes.c_uint32), ("i_first", ctypes.c_uint64),
+                ("ni", ctypes.c_uint64), ("nj", ctypes.c_uint64), ("y", ctypes.POINTER(ctypes.c_uint64)),
+                ("anchor", ctypes.POINTER(ctypes.c_uint64)), ("xk", ctypes.POINTER(ctypes.c_uint64)),
+                ("p", ctypes.c_uint64)]
+
+
+_BB_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(_ZrPoints), ctypes.c_void_p,
+                          ctypes.c_void_p)
+_DEV = None
+_HIP = None
+
+
+def dev_lib():
+    global _DEV, _HIP
+    if _DEV is None:
+        D = ctypes.CDLL(dev_lib_path())
+        D.zsd_apply.restype = ctypes.c_int
+        D.zsd_apply.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]
+        _DEV = D
+        H = ctypes.CDLL("libamdhip64.so")
+        H.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+        H.hipStreamSynchronize.argtypes = [ctypes.c_void_p]
+        _HIP = H
+    return _DEV, _HIP
+
+
+class DeviceBlackBox:
+    """Black box for a hidden polynomial usable by the GPU reconstruction: the
+    library passes a zr_points descriptor and a device buffer.  Large stage
+    requests are evaluated on the GPU (zsd_apply); small ones on the host."""
+
+    HOST_LIMIT = 1 << 14
+
+    def __init__(self, poly: SparsePoly, nthreads: int = 0):
+        self.host = BlackBox(poly, nthreads=nthreads)
+        self.p = poly.p
+        self.nvars = poly.nvars
+        self.calls = 0
+        self.error = None
+        self._cb = _BB_FN(self._call)
+        self._bufs = {}
+
+    def _dev(self, name, n):
+        import torch
+        buf = self._bufs.get(name)
+        if buf is None or buf.numel() < n:
+            buf = torch.empty(max(n, 1), dtype=torch.int64, device="cuda")
+            self._bufs[name] = buf
+        return buf
+
+    def device_eval(self, k, i_first, ni, y, anchor, xk, d_out: int, stream: int = 0) -> None:
+        """Values at the stage-k points, written [jj][ii] to device memory d_out."""
+        D, H = dev_lib()
+        y = _arr(y, np.uint64)
+        anchor = _arr(anchor, np.uint64)
+        xk = _arr(xk, np.uint64)
+        nj = len(xk)
+        T = self.host.num.nterms
+        Y = np.zeros(max(T, 1), dtype=np.uint64)
+        W = np.zeros(max(T * nj, 1), dtype=np.uint64)
+        ng = lib().zs_group_stage(self.host.ctx(), k, y.ctypes.data, anchor.ctypes.data, nj, xk.ctypes.data,
+                                  Y.ctypes.data, W.ctypes.data)
+        dY = self._dev("Y", ng)
+        dW = self._dev("W", ng * nj)
+        H.hipMemcpyAsync(dY.data_ptr(), Y.ctypes.data, ng * 8, 1, stream)
+        H.hipMemcpyAsync(dW.data_ptr(), W.ctypes.data, ng * nj * 8, 1, stream)
+        st = D.zsd_apply(self.p, ng, dY.data_ptr(), dW.data_ptr(), nj, i_first, ni, d_out, stream)
+        if st != 0:
+            raise RuntimeError(f"zsd_apply failed with {st}")
+        H.hipStreamSynchronize(stream)
+
+    def _call(self, ctx, pts_ptr, d_vals, stream):
+        try:
+            pts = pts_ptr.contents
+            nv, k, ni, nj = pts.nvars, pts.k, pts.ni, pts.nj
+            y = np.ctypeslib.as_array(pts.y, shape=(nv,)).copy()
+            a = np.ctypeslib.as_array(pts.anchor, shape=(nv,)).copy()
+            xk = np.ctypeslib.as_array(pts.xk, shape=(nj,)).copy()
+            _, H = dev_lib()
+            if ni * nj <= self.HOST_LIMIT or k == 1 or nj > 64 or self.host.den is not None:
+                vals = self.host.eval(k, pts.i_first, ni, y, a, xk)
+                H.hipMemcpyAsync(d_vals, vals.ctypes.data, vals.nbytes, 1, stream)
+                H.hipStreamSynchronize(stream)
+            else:
+                self.device_eval(k, pts.i_first, ni, y, a, xk, d_vals, stream)
+            self.calls += 1
+            return 0
+        except BaseException as e:  # noqa: BLE001 - reported through the status code
+            self.error = e
+            return 23
+
+    @property
+    def fn_ptr(self):
+        return ctypes.cast(self._cb, ctypes.c_void_p)
+
+    ctx = None

@@ -123,3 +123,53 @@ int zs_eval_points(const void *ctx, uint32_t nvars, uint32_t k, uint64_t i_first
   free(dv);
   return bad;
 }
+
+/* Stage-k grouping for the device black box: hidden terms sharing their
+ * exponents on x_1..x_{k-1} (contiguous, the polynomial is lex-sorted) form one
+ * group l with monomial value Y_l = prod_{v<k} y_v^e_v and weights
+ * W[l][jj] = sum_{h in l} c_h * xk[jj]^e_{h,k} * prod_{v>k} anchor_v^e_{h,v}.
+ * Y and W need capacity nterms and nterms*nj; returns the number of groups. */
+uint64_t zs_group_stage(const void *ctx, uint32_t k, const uint64_t *y, const uint64_t *anchor, uint64_t nj,
+                        const uint64_t *xk, uint64_t *Y, uint64_t *W) {
+  const zs_box *B = (const zs_box *)ctx;
+  const zs_poly *P = &B->num;
+  const uint64_t p = P->p;
+  const uint32_t n = P->nvars, T = P->nterms;
+  uint64_t ng = 0;
+  uint64_t *start = (uint64_t *)malloc(sizeof(uint64_t) * (T + 1));
+  for (uint32_t h = 0; h < T; ++h) {
+    int same = h > 0;
+    for (uint32_t v = 0; same && v + 1 < k; ++v) same = P->exps[(size_t)h * n + v] == P->exps[(size_t)(h - 1) * n + v];
+    if (!same) start[ng++] = h;
+  }
+  start[ng] = T;
+  uint32_t maxd = 0;
+  for (uint32_t h = 0; h < T; ++h)
+    if (P->exps[(size_t)h * n + (k - 1)] > maxd) maxd = P->exps[(size_t)h * n + (k - 1)];
+  uint64_t *xpow = (uint64_t *)malloc(sizeof(uint64_t) * (maxd + 1) * (nj ? nj : 1));
+  for (uint64_t jj = 0; jj < nj; ++jj) {
+    xpow[jj * (maxd + 1)] = 1 % p;
+    for (uint32_t d = 1; d <= maxd; ++d) xpow[jj * (maxd + 1) + d] = mm(xpow[jj * (maxd + 1) + d - 1], xk[jj], p);
+  }
+#pragma omp parallel for schedule(dynamic, 64) num_threads(B->nthreads > 0 ? B->nthreads : omp_get_max_threads())
+  for (uint64_t g = 0; g < ng; ++g) {
+    const uint16_t *e0 = P->exps + (size_t)start[g] * n;
+    uint64_t yv = 1 % p;
+    for (uint32_t v = 0; v + 1 < k; ++v) yv = mm(yv, pw(y[v], e0[v], p), p);
+    Y[g] = yv;
+    for (uint64_t jj = 0; jj < nj; ++jj) W[g * nj + jj] = 0;
+    for (uint64_t h = start[g]; h < start[g + 1]; ++h) {
+      const uint16_t *e = P->exps + (size_t)h * n;
+      uint64_t a = P->coefs[h] % p;
+      for (uint32_t v = k; v < n; ++v) a = mm(a, pw(anchor[v], e[v], p), p);
+      for (uint64_t jj = 0; jj < nj; ++jj) {
+        uint64_t w = mm(a, xpow[jj * (maxd + 1) + e[k - 1]], p);
+        uint64_t s = W[g * nj + jj] + w;
+        W[g * nj + jj] = s >= p ? s - p : s;
+      }
+    }
+  }
+  free(start);
+  free(xpow);
+  return ng;
+}
