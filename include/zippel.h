@@ -173,6 +173,13 @@ zr_status vandermonde_solve_batch(size_t nsys, uint64_t p, const uint64_t* d_sys
 zr_status zippel_reconstruct_batch(uint32_t n, const zr_params* params, zr_blackbox_fn bb, void* const* ctx,
                                    hipStream_t stream, zr_poly* out, int32_t* status);
 
+/* Graph mode of the batched paths (zippel_reconstruct_batch, the server,
+ * vandermonde_solve_batch): with on != 0 each stage's device-side solve
+ * sequence (master polynomials, packing, chunk chains, the persistent dot-product
+ * pass, scaling) is captured into one hipGraph and launched as a unit.  Off by
+ * default; results are identical either way. */
+void zr_batch_graphs(int on);
+
 /* Size bands of the batched solve, by system size t: [1,64), [64,256),
  * [256,1024), [1024,4096), [4096,inf).  Per band: whether small systems share
  * wavefronts (lane = (system, row)), and the shortest chunk of the synthetic

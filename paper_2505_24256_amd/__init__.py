@@ -28,7 +28,7 @@ EXPORTS = [
     "zr_recorder_blackbox", "zr_timing_enable", "zr_timing_reset", "zr_timing_get", "zr_last_counters",
     "zr_microbench", "zippel_reconstruct_batch", "zr_autotune", "zr_tuning_get", "zr_tuning_set",
     "zr_server_create", "zr_server_destroy", "zr_server_submit", "zr_server_step", "zr_server_poll",
-    "zr_server_get_stats",
+    "zr_server_get_stats", "zr_batch_graphs",
 ]
 MB_KINDS = {"mad_u64_u32": 0, "mul_lo_u32": 1, "mul_hi_u32": 2, "add_u32": 3, "mac192": 4, "shoup": 5, "copy": 6}
 
@@ -104,6 +104,8 @@ def lib():
         L.zippel_reconstruct_batch.argtypes = [u32, ctypes.POINTER(ZrParams), vp, vp, vp, ctypes.POINTER(ZrPoly),
                                                vp]
         L.zr_autotune.argtypes = [u64, vp, ctypes.POINTER(ZrBandChoice)]
+        L.zr_batch_graphs.argtypes = [i32]
+        L.zr_batch_graphs.restype = None
         L.zr_server_create.argtypes = [ctypes.POINTER(vp), u64, u64, u32, vp]
         L.zr_server_destroy.argtypes = [vp]
         L.zr_server_destroy.restype = None
@@ -380,6 +382,11 @@ def autotune(p: int, stream=None):
     if st != ZR_OK:
         raise ZippelError(st, "zr_autotune")
     return [(t.packed, t.min_chunk) for t in tab]
+
+
+def batch_graphs(on: bool):
+    """Capture each stage's batched solve into one hipGraph (zr_batch_graphs)."""
+    lib().zr_batch_graphs(1 if on else 0)
 
 
 def tuning_get():

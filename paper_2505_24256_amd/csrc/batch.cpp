@@ -21,6 +21,8 @@ static void solve_batch(size_t nsys, uint64_t p, const uint64_t* h_sys_off, cons
                         const uint32_t* h_nrhs, const uint64_t* h_rhs_off, const uint64_t* d_rhs, uint64_t* d_out,
                         int32_t* d_status, hipStream_t s) {
   const zr_mod M = zr_mod_make(p);
+  // graphs of earlier asynchronous calls on this stream: destroyed once it is idle
+  if (hipStreamQuery(s) == hipSuccess) release_graphs(s);
   check(fill_i32(d_status, 0, nsys, s));
   if (h_rhs_off[nsys])
     check(hipMemcpyAsync(d_out, d_rhs, h_rhs_off[nsys] * 8, hipMemcpyDeviceToDevice, s));
@@ -341,6 +343,8 @@ zr_status zr_autotune(uint64_t p, hipStream_t stream, zr_band_choice* table) {
   if (table) zr_tuning_get(table);
   return ZR_OK;
 }
+
+void zr_batch_graphs(int on) { set_graphs(on != 0); }
 
 int zr_tuning_get(zr_band_choice* table) {
   const Tuning& T = tuning();

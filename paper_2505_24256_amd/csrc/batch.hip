@@ -182,25 +182,25 @@ __global__ void __launch_bounds__(64) k_b_master_small(zr_mod M, uint32_t n, con
   master_small_body(M, b.t, (blockIdx.x - prefix[s]) * 64, b.mono, b.buf[0], b.limbs[0], buf);
 }
 
-// level with factors of degree `half` (>= 64): reads buffer r, writes r ^ 1
-__global__ void __launch_bounds__(64) k_b_master_conv(zr_mod M, uint32_t half, uint32_t r, uint32_t n,
+// level with factors of degree `half` (>= 64), chunks of IC: reads buffer r, writes r ^ 1
+__global__ void __launch_bounds__(64) k_b_master_conv(zr_mod M, uint32_t half, uint32_t IC, uint32_t r, uint32_t n,
                                                       const uint32_t* __restrict__ prefix,
                                                       const BMaster* __restrict__ sys) {
-  __shared__ uint64_t win[64 + kConvIC + 8];
+  extern __shared__ uint64_t win[];  // 64 + IC + 8 words
   const uint32_t s = seg_find(prefix, n, blockIdx.x);
   const BMaster& b = sys[s];
-  const uint32_t nic = cdiv(half, kConvIC);
+  const uint32_t nic = cdiv(half, IC);
   const uint32_t lb = blockIdx.x - prefix[s], nrb = cdiv(b.t, 64);
-  master_conv_body(M, b.t, half, nic, (lb % nrb) * 64, lb / nrb, b.buf[r], b.limbs[r], b.part, b.t, b.buf[r ^ 1],
+  master_conv_body(M, b.t, half, IC, nic, (lb % nrb) * 64, lb / nrb, b.buf[r], b.limbs[r], b.part, b.t, b.buf[r ^ 1],
                    b.limbs[r ^ 1], win);
 }
 
-__global__ void k_b_master_sum(zr_mod M, uint32_t half, uint32_t r, uint32_t n, const uint32_t* __restrict__ prefix,
-                               const BMaster* __restrict__ sys) {
+__global__ void k_b_master_sum(zr_mod M, uint32_t half, uint32_t nic, uint32_t r, uint32_t n,
+                               const uint32_t* __restrict__ prefix, const BMaster* __restrict__ sys) {
   const uint32_t s = seg_find(prefix, n, blockIdx.x);
   const BMaster& b = sys[s];
   const uint32_t g = (blockIdx.x - prefix[s]) * blockDim.x + threadIdx.x;
-  if (g < b.t) master_sum_body(M, b.t, half, cdiv(half, kConvIC), g, b.buf[r], b.part, b.t, b.buf[r ^ 1], b.limbs[r ^ 1]);
+  if (g < b.t) master_sum_body(M, b.t, half, nic, g, b.buf[r], b.part, b.t, b.buf[r ^ 1], b.limbs[r ^ 1]);
 }
 
 // systems whose last level landed in buf[1]: copy to Mc
@@ -439,6 +439,49 @@ char* Blob::upload(DevArena& A, hipStream_t s) {
   }
 }
 
+// ---- graphs --------------------------------------------------------------------------
+namespace {
+std::mutex g_graph_mu;
+bool g_graphs = false;
+struct Retired {
+  hipStream_t s;
+  hipGraph_t g;
+  hipGraphExec_t ge;
+};
+std::vector<Retired>& retired() {
+  static std::vector<Retired>* v = new std::vector<Retired>();
+  return *v;
+}
+}  // namespace
+
+bool graphs_enabled() {
+  std::lock_guard<std::mutex> l(g_graph_mu);
+  return g_graphs;
+}
+void set_graphs(bool on) {
+  std::lock_guard<std::mutex> l(g_graph_mu);
+  g_graphs = on;
+}
+// a launched graph is destroyed once its stream has been synchronised
+void retire_graph(hipStream_t s, hipGraph_t g, hipGraphExec_t ge) {
+  std::lock_guard<std::mutex> l(g_graph_mu);
+  retired().push_back(Retired{s, g, ge});
+}
+void release_graphs(hipStream_t s) {
+  std::lock_guard<std::mutex> l(g_graph_mu);
+  auto& v = retired();
+  for (size_t i = 0; i < v.size();) {
+    if (v[i].s == s) {
+      (void)hipGraphExecDestroy(v[i].ge);
+      (void)hipGraphDestroy(v[i].g);
+      v[i] = v.back();
+      v.pop_back();
+    } else {
+      ++i;
+    }
+  }
+}
+
 uint32_t band_of(uint32_t t) {
   if (t < 64) return 0;
   if (t < 256) return 1;
@@ -615,14 +658,24 @@ void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs_in, hipStr
   for (uint32_t i = 0; i < n; ++i) plan[i] = bplan(jobs[i].t, jobs[i].R, cap, T);
 
   DevArena A(s);
-  // ---- master polynomials
+  // ---- master polynomials; chunk length of each product-tree level from the
+  // level's total number of row blocks
   std::vector<BMaster> bm(n);
   Segs small, fix;
   uint32_t halfmax = 0;
+  for (uint32_t i = 0; i < n; ++i)
+    for (uint32_t h = 64; h < jobs[i].t; h *= 2) halfmax = std::max(halfmax, h);
+  std::vector<uint32_t> level_ic;
+  for (uint32_t h = 64; h <= halfmax; h *= 2) {
+    uint64_t blocks = 0;
+    for (uint32_t i = 0; i < n; ++i)
+      if (jobs[i].t > h) blocks += cdiv(jobs[i].t, 64);
+    level_ic.push_back(conv_ic(h, blocks));
+  }
   for (uint32_t i = 0; i < n; ++i) {
     const uint32_t t = jobs[i].t;
     uint32_t big = 0;
-    for (uint32_t h = 64; h < t; h *= 2) ++big, halfmax = std::max(halfmax, h);
+    for (uint32_t h = 64; h < t; h *= 2) ++big;
     BMaster& b = bm[i];
     b.t = t;
     b.big = big;
@@ -632,7 +685,7 @@ void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs_in, hipStr
     b.limbs[0] = A.alloc<uint4>(t + 16);
     b.limbs[1] = A.alloc<uint4>(t + 16);
     uint32_t nic_max = 1;
-    for (uint32_t h = 64; h < t; h *= 2) nic_max = std::max(nic_max, cdiv(h, kConvIC));
+    for (uint32_t h = 64, lv = 0; h < t; h *= 2, ++lv) nic_max = std::max(nic_max, cdiv(h, level_ic[lv]));
     b.part = nic_max > 1 ? A.alloc<uint64_t>((size_t)nic_max * t) : nullptr;
     small.add(cdiv(t, 64));
     fix.add(big % 2 ? cdiv(t, 256) : 0);
@@ -688,9 +741,9 @@ void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs_in, hipStr
   }
   // conv levels
   std::vector<Segs> conv, csum;
-  for (uint32_t h = 64; h <= halfmax; h *= 2) {
+  for (uint32_t h = 64, lv = 0; h <= halfmax; h *= 2, ++lv) {
     Segs c, su;
-    const uint32_t nic = cdiv(h, kConvIC);
+    const uint32_t nic = cdiv(h, level_ic[lv]);
     for (uint32_t i = 0; i < n; ++i) {
       const uint32_t t = jobs[i].t;
       c.add(t > h ? (size_t)cdiv(t, 64) * nic : 0);
@@ -760,16 +813,25 @@ void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs_in, hipStr
   const BSolve* d_bs = (const BSolve*)(d + o_bs);
   uint32_t* d_heads = (uint32_t*)(d + o_heads);
 
+  // the device-side sequence below (every input already resident) is recorded
+  // as one graph and launched as one unit when graphs are on
+  std::vector<uint32_t> grid(kMaxRT + 1, 0);  // persistent grid per class, queried before any capture
+  for (uint32_t RT = 1; RT <= kMaxRT; ++RT)
+    if (!items[RT].empty()) grid[RT] = std::min<uint32_t>((uint32_t)items[RT].size(), cus * bdots_waves_per_cu(RT));
+  const bool graph = graphs_enabled();
+  if (graph) check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   {
     TimedLaunch tl("batch_master", s);
     hipLaunchKernelGGL(k_b_master_small, dim3(small.total()), dim3(64), 0, s, M, n, P32(o_small), d_bm);
     uint32_t r = 0;
     for (size_t lv = 0; lv < conv.size(); ++lv, r ^= 1) {
-      const uint32_t h = 64u << lv;
+      const uint32_t h = 64u << lv, IC = level_ic[lv];
       if (conv[lv].total())
-        hipLaunchKernelGGL(k_b_master_conv, dim3(conv[lv].total()), dim3(64), 0, s, M, h, r, n, P32(o_conv[lv]), d_bm);
+        hipLaunchKernelGGL(k_b_master_conv, dim3(conv[lv].total()), dim3(64), (64 + IC + 8) * 8, s, M, h, IC, r, n,
+                           P32(o_conv[lv]), d_bm);
       if (csum[lv].total())
-        hipLaunchKernelGGL(k_b_master_sum, dim3(csum[lv].total()), dim3(256), 0, s, M, h, r, n, P32(o_csum[lv]), d_bm);
+        hipLaunchKernelGGL(k_b_master_sum, dim3(csum[lv].total()), dim3(256), 0, s, M, h, cdiv(h, IC), r, n,
+                           P32(o_csum[lv]), d_bm);
     }
     if (fix.total()) hipLaunchKernelGGL(k_b_master_fix, dim3(fix.total()), dim3(256), 0, s, n, P32(o_fix), d_bm);
   }
@@ -787,8 +849,7 @@ void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs_in, hipStr
     for (uint32_t RT = 1; RT <= kMaxRT; ++RT) {
       if (!items[RT].empty()) {
         const uint32_t ni = (uint32_t)items[RT].size();
-        const uint32_t grid = std::min<uint32_t>(ni, cus * bdots_waves_per_cu(RT));
-        hipLaunchKernelGGL(bdots_kernel(RT), dim3(grid), dim3(64), 0, s, d_bs, (const uint4*)(d + o_items[RT]), ni,
+        hipLaunchKernelGGL(bdots_kernel(RT), dim3(grid[RT]), dim3(64), 0, s, d_bs, (const uint4*)(d + o_items[RT]), ni,
                            d_heads + RT, (const uint64_t*)vt_base, part_base);
       }
       if (!lanes[RT].empty())
@@ -801,6 +862,18 @@ void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs_in, hipStr
     TimedLaunch tl("batch_finish", s);
     hipLaunchKernelGGL(k_b_delta, dim3(rows.total()), dim3(256), 0, s, n, P32(o_rows), d_bs);
     hipLaunchKernelGGL(k_b_scale, dim3(scale.total()), dim3(256), 0, s, n, P32(o_scale), d_bs);
+  }
+  if (graph) {
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (e != hipSuccess || !g) throw Error(ZR_EDEVICE);
+    hipGraphExec_t ge = nullptr;
+    if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      throw Error(ZR_EDEVICE);
+    }
+    check(hipGraphLaunch(ge, s));
+    retire_graph(s, g, ge);
   }
   check(hipGetLastError());
   for (const auto& j : jobs) count_solve(j.t, j.R);
@@ -882,6 +955,7 @@ std::vector<int32_t> batched_lift(const zr_mod& M, const std::vector<LiftJob>& j
   std::vector<int32_t> h(2 * (size_t)n);
   check(hipMemcpyAsync(h.data(), tot, 8 * (size_t)n, hipMemcpyDeviceToHost, s));
   check(hipStreamSynchronize(s));
+  release_graphs(s);
   // the new skeletons share one block of `keep`
   size_t words = 0;
   for (uint32_t i = 0; i < n; ++i) {

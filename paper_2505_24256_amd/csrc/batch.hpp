@@ -37,6 +37,15 @@ Tuning& tuning();
 // fastest; cost: a few hundred milliseconds, once per process.
 void autotune(const zr_mod& M, hipStream_t s);
 
+// Graph mode of batched_solve: its device-side launch sequence is captured
+// into one hipGraph and launched as a unit.  Graphs launched on a stream are
+// destroyed at that stream's next synchronisation by batched_lift
+// (release_graphs).
+bool graphs_enabled();
+void set_graphs(bool on);
+void retire_graph(hipStream_t s, hipGraph_t g, hipGraphExec_t ge);
+void release_graphs(hipStream_t s);
+
 // One system: t unknowns, R right-hand sides in rhs[R][t] (unknowns written
 // back in place), monomial values mono[t].  status: 0 or ZR_ESINGULAR.
 struct SolveJob {

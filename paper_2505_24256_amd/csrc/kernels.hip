@@ -186,12 +186,12 @@ __global__ void __launch_bounds__(64) k_master_small(zr_mod M, uint32_t t, const
   master_small_body(M, t, blockIdx.x * 64, mono, out, limbs, buf);
 }
 
-__global__ void __launch_bounds__(64) k_master_conv(zr_mod M, uint32_t t, uint32_t half, uint32_t nic,
+__global__ void __launch_bounds__(64) k_master_conv(zr_mod M, uint32_t t, uint32_t half, uint32_t IC, uint32_t nic,
                                                     const uint64_t* __restrict__ cur, const uint4* __restrict__ limbs,
                                                     uint64_t* __restrict__ part, uint64_t* __restrict__ nxt,
                                                     uint4* __restrict__ limbs_nxt) {
-  __shared__ uint64_t win[64 + kConvIC + 8];
-  master_conv_body(M, t, half, nic, blockIdx.x * 64, blockIdx.y, cur, limbs, part, t, nxt, limbs_nxt, win);
+  extern __shared__ uint64_t win[];  // 64 + IC + 8 words
+  master_conv_body(M, t, half, IC, nic, blockIdx.x * 64, blockIdx.y, cur, limbs, part, t, nxt, limbs_nxt, win);
 }
 
 __global__ void k_master_sum(zr_mod M, uint32_t t, uint32_t half, uint32_t nic, const uint64_t* __restrict__ cur,
@@ -205,7 +205,7 @@ size_t master_tmp_words(uint32_t t) {
   // t for the ping-pong level array, two limb arrays of t + 16 entries (two
   // words each) and the chunk partials of the largest levels
   uint32_t nic_max = 1;
-  for (uint32_t half = 64; half < t; half *= 2) nic_max = std::max(nic_max, cdiv(half, kConvIC));
+  for (uint32_t half = 64; half < t; half *= 2) nic_max = std::max(nic_max, cdiv(half, conv_ic(half, cdiv(t, 64))));
   return (size_t)t + 1 + 4 * ((size_t)t + 16) + (nic_max > 1 ? (size_t)nic_max * t : 0) + 64;
 }
 
@@ -225,9 +225,10 @@ hipError_t master_poly(const zr_mod& M, uint32_t t, const uint64_t* mono, uint64
   for (uint32_t half = 64; half < t; half *= 2) {
     const uint32_t r = w;
     w ^= 1;
-    const uint32_t nic = cdiv(half, kConvIC);
-    hipLaunchKernelGGL(k_master_conv, dim3(cdiv(t, 64), nic), dim3(64), 0, s, M, t, half, nic, bufs[r], limbs[r],
-                       part, bufs[w], limbs[w]);
+    const uint32_t IC = conv_ic(half, cdiv(t, 64));
+    const uint32_t nic = cdiv(half, IC);
+    hipLaunchKernelGGL(k_master_conv, dim3(cdiv(t, 64), nic), dim3(64), (64 + IC + 8) * 8, s, M, t, half, IC, nic,
+                       bufs[r], limbs[r], part, bufs[w], limbs[w]);
     if (nic > 1)
       hipLaunchKernelGGL(k_master_sum, dim3(cdiv(t, 256)), dim3(256), 0, s, M, t, half, nic, bufs[r], part, bufs[w],
                          limbs[w]);
@@ -497,6 +498,8 @@ static TimingState g_timing;
 
 TimedLaunch::TimedLaunch(const char* n, hipStream_t st) : name(n), s(st), e0(nullptr), e1(nullptr), on(false) {
   if (!g_timing.on) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return;  // not in graphs
   on = true;
   {
     std::lock_guard<std::mutex> g(g_timing.mu);

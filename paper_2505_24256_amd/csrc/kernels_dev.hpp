@@ -340,11 +340,21 @@ __device__ __forceinline__ void master_small_body(const zr_mod& M, uint32_t t, u
 // The factor L_i is wave-uniform: the level's coefficients carry their 22-bit
 // limbs (four 32-bit words per value) so that eight of them arrive with two
 // 64-byte scalar loads.  The window of R needed by the wave, R_{k-i} for its k
-// and i, is staged once in LDS (win: 64 + kConvIC + 8 words).  With one chunk
+// and i, is staged once in LDS (win: 64 + IC + 8 words).  With one chunk
 // per product the wave finishes the coefficient (adding the terms of the
 // leading ones) and writes it with its limbs; otherwise chunk partial sums go
 // to part[ic][g] and master_sum_body finishes them.
-constexpr uint32_t kConvIC = 512;
+// Chunk length IC of the convolution index for a level with factors of degree
+// `half` and `blocks` row blocks in total: short enough that the level has
+// about 2048 waves, so that the small levels are not bound by one wave's serial
+// sum, long enough to keep the partial sums few (64 chunks per product, up to
+// IC = 4096, whose LDS window is 33 KB).
+__host__ __device__ inline uint32_t conv_ic(uint32_t half, uint64_t blocks) {
+  uint32_t ic = 512;
+  while (ic > 64 && blocks * ((half + ic - 1) / ic) < 2048) ic /= 2;
+  while ((half + ic - 1) / ic > 64 && ic < 4096) ic *= 2;
+  return ic;
+}
 
 struct alignas(16) L8 {
   uint4 v[8];
@@ -357,7 +367,7 @@ __device__ __forceinline__ uint64_t master_linear_terms(const zr_mod& M, uint64_
   return s;
 }
 
-__device__ __forceinline__ void master_conv_body(const zr_mod& M, uint32_t t, uint32_t half, uint32_t nic,
+__device__ __forceinline__ void master_conv_body(const zr_mod& M, uint32_t t, uint32_t half, uint32_t IC, uint32_t nic,
                                                  uint32_t g0, uint32_t ic, const uint64_t* __restrict__ cur,
                                                  const uint4* __restrict__ limbs, uint64_t* __restrict__ part,
                                                  size_t ld_part, uint64_t* __restrict__ nxt,
@@ -371,7 +381,7 @@ __device__ __forceinline__ void master_conv_body(const zr_mod& M, uint32_t t, ui
   const uint64_t* __restrict__ Rc = cur + a + n1;
   Acc6 acc;
   acc6_zero(acc);
-  uint32_t ilo = ic * kConvIC, ihi = std::min(ilo + kConvIC, n1);
+  uint32_t ilo = ic * IC, ihi = std::min(ilo + IC, n1);
   if (n2 > 0) {
     const uint32_t wlo = k0 + 1 > n2 ? k0 + 1 - n2 : 0;
     const uint32_t whi = std::min(k0 + 64, n1);

@@ -474,7 +474,7 @@ def lib():
                                      ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                      ctypes.c_void_p, ctypes.c_void_p]
         L.zs_group_stage.restype = ctypes.c_uint64
-        L.zs_group_stage.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
+        L.zs_group_stage.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         _LIB = L
     return _LIB
@@ -566,7 +566,12 @@ def dev_lib():
         D = ctypes.CDLL(dev_lib_path())
         D.zsd_apply.restype = ctypes.c_int
         D.zsd_apply.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
-                                ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]
+                                ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        D.zsd_divide.restype = ctypes.c_int
+        D.zsd_divide.argtypes = [ctypes.c_uint64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.c_void_p]
+        D.zsd_apply_scratch_words.restype = ctypes.c_size_t
+        D.zsd_apply_scratch_words.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64]
         _DEV = D
         H = ctypes.CDLL("libamdhip64.so")
         H.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
@@ -576,14 +581,16 @@ def dev_lib():
 
 
 class DeviceBlackBox:
-    """Black box for a hidden polynomial usable by the GPU reconstruction: the
-    library passes a zr_points descriptor and a device buffer.  Large stage
-    requests are evaluated on the GPU (zsd_apply); small ones on the host."""
+    """Black box for a hidden polynomial (or P/Q) usable by the GPU
+    reconstruction: the library passes a zr_points descriptor and a device
+    buffer.  Large stage requests are evaluated on the GPU (zsd_apply, and
+    zsd_divide for P/Q); small ones on the host."""
 
     HOST_LIMIT = 1 << 14
+    MAX_NJ = 48  # values of x_k per request handled on the device
 
-    def __init__(self, poly: SparsePoly, nthreads: int = 0):
-        self.host = BlackBox(poly, nthreads=nthreads)
+    def __init__(self, poly: SparsePoly, den: Optional[SparsePoly] = None, nthreads: int = 0):
+        self.host = BlackBox(poly, den, nthreads=nthreads)
         self.p = poly.p
         self.nvars = poly.nvars
         self.calls = 0
@@ -599,26 +606,53 @@ class DeviceBlackBox:
             self._bufs[name] = buf
         return buf
 
-    def device_eval(self, k, i_first, ni, y, anchor, xk, d_out: int, stream: int = 0) -> None:
-        """Values at the stage-k points, written [jj][ii] to device memory d_out."""
+    def _apply(self, den, k, i_first, ni, y, anchor, xk, d_out, stream):
         D, H = dev_lib()
-        y = _arr(y, np.uint64)
-        anchor = _arr(anchor, np.uint64)
-        xk = _arr(xk, np.uint64)
         nj = len(xk)
-        T = self.host.num.nterms
+        poly = self.host.den if den else self.host.num
+        T = poly.nterms
         Y = np.zeros(max(T, 1), dtype=np.uint64)
         W = np.zeros(max(T * nj, 1), dtype=np.uint64)
-        ng = lib().zs_group_stage(self.host.ctx(), k, y.ctypes.data, anchor.ctypes.data, nj, xk.ctypes.data,
-                                  Y.ctypes.data, W.ctypes.data)
+        ng = lib().zs_group_stage(self.host.ctx(), 1 if den else 0, k, y.ctypes.data, anchor.ctypes.data, nj,
+                                  xk.ctypes.data, Y.ctypes.data, W.ctypes.data)
         dY = self._dev("Y", ng)
         dW = self._dev("W", ng * nj)
         H.hipMemcpyAsync(dY.data_ptr(), Y.ctypes.data, ng * 8, 1, stream)
         H.hipMemcpyAsync(dW.data_ptr(), W.ctypes.data, ng * nj * 8, 1, stream)
-        st = D.zsd_apply(self.p, ng, dY.data_ptr(), dW.data_ptr(), nj, i_first, ni, d_out, stream)
+        sw = D.zsd_apply_scratch_words(ng, nj, ni)
+        dS = self._dev("S", sw) if sw else None
+        st = D.zsd_apply(self.p, ng, dY.data_ptr(), dW.data_ptr(), nj, i_first, ni, d_out,
+                         dS.data_ptr() if dS is not None else None, stream)
         if st != 0:
             raise RuntimeError(f"zsd_apply failed with {st}")
+        # the host arrays must outlive the asynchronous copies
         H.hipStreamSynchronize(stream)
+
+    def device_eval(self, k, i_first, ni, y, anchor, xk, d_out: int, stream: int = 0) -> None:
+        """Values at the stage-k points, written [jj][ii] to device memory d_out
+        (numerator / denominator for a rational box)."""
+        D, H = dev_lib()
+        y = _arr(y, np.uint64)
+        anchor = _arr(anchor, np.uint64)
+        xk = _arr(xk, np.uint64)
+        if self.host.den is None:
+            self._apply(False, k, i_first, ni, y, anchor, xk, d_out, stream)
+            return
+        n = ni * len(xk)
+        dN = self._dev("N", n)
+        dD = self._dev("D", n)
+        flag = self._dev("F", 1)
+        flag.zero_()
+        import torch
+        torch.cuda.synchronize()
+        self._apply(False, k, i_first, ni, y, anchor, xk, dN.data_ptr(), stream)
+        self._apply(True, k, i_first, ni, y, anchor, xk, dD.data_ptr(), stream)
+        st = D.zsd_divide(self.p, n, dN.data_ptr(), dD.data_ptr(), d_out, flag.data_ptr(), stream)
+        if st != 0:
+            raise RuntimeError(f"zsd_divide failed with {st}")
+        H.hipStreamSynchronize(stream)
+        if int(flag[0].item()) != 0:
+            raise ZeroDivisionError("black box: denominator vanishes at a requested point")
 
     def _call(self, ctx, pts_ptr, d_vals, stream):
         try:
@@ -628,7 +662,7 @@ class DeviceBlackBox:
             a = np.ctypeslib.as_array(pts.anchor, shape=(nv,)).copy()
             xk = np.ctypeslib.as_array(pts.xk, shape=(nj,)).copy()
             _, H = dev_lib()
-            if ni * nj <= self.HOST_LIMIT or k == 1 or nj > 64 or self.host.den is not None:
+            if ni * nj <= self.HOST_LIMIT or k == 1 or nj > self.MAX_NJ:
                 vals = self.host.eval(k, pts.i_first, ni, y, a, xk)
                 H.hipMemcpyAsync(d_vals, vals.ctypes.data, vals.nbytes, 1, stream)
                 H.hipStreamSynchronize(stream)

@@ -128,11 +128,12 @@ int zs_eval_points(const void *ctx, uint32_t nvars, uint32_t k, uint64_t i_first
  * exponents on x_1..x_{k-1} (contiguous, the polynomial is lex-sorted) form one
  * group l with monomial value Y_l = prod_{v<k} y_v^e_v and weights
  * W[l][jj] = sum_{h in l} c_h * xk[jj]^e_{h,k} * prod_{v>k} anchor_v^e_{h,v}.
+ * den != 0 selects the denominator of a rational box.
  * Y and W need capacity nterms and nterms*nj; returns the number of groups. */
-uint64_t zs_group_stage(const void *ctx, uint32_t k, const uint64_t *y, const uint64_t *anchor, uint64_t nj,
+uint64_t zs_group_stage(const void *ctx, int den, uint32_t k, const uint64_t *y, const uint64_t *anchor, uint64_t nj,
                         const uint64_t *xk, uint64_t *Y, uint64_t *W) {
   const zs_box *B = (const zs_box *)ctx;
-  const zs_poly *P = &B->num;
+  const zs_poly *P = den ? &B->den : &B->num;
   const uint64_t p = P->p;
   const uint32_t n = P->nvars, T = P->nterms;
   uint64_t ng = 0;

@@ -123,3 +123,20 @@ def test_batch_recorded_replay_and_autotune(zr):
     for w, a, b in zip(ws, first, again):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
         assert np.array_equal(a[0], w.hidden.exps) and np.array_equal(a[1], w.hidden.coefs)
+
+
+def test_batch_graphs_identical(zr):
+    """Graph mode (each stage's solve captured and launched as one hipGraph)
+    gives the same results as direct launches, on repeated runs."""
+    ws = _mixed(20, 5)
+    zr.batch_graphs(False)
+    base = zr.reconstruct_batch(ws[0].p, _items(zr, ws))
+    try:
+        zr.batch_graphs(True)
+        for rep in range(3):
+            again = zr.reconstruct_batch(ws[0].p, _items(zr, ws))
+            for w, a, b in zip(ws, base, again):
+                assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+                assert np.array_equal(b[0], w.hidden.exps) and np.array_equal(b[1], w.hidden.coefs)
+    finally:
+        zr.batch_graphs(False)
