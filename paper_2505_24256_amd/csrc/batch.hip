@@ -454,6 +454,18 @@ std::vector<Retired>& retired() {
 }
 }  // namespace
 
+// one non-blocking stream per device, default priority, for graph capture
+hipStream_t capture_stream() {
+  static std::mutex mu;
+  static hipStream_t streams[64] = {nullptr};
+  int dev = 0;
+  check(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) throw Error(ZR_EDEVICE);
+  std::lock_guard<std::mutex> l(mu);
+  if (!streams[dev]) check(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
+  return streams[dev];
+}
+
 bool graphs_enabled() {
   std::lock_guard<std::mutex> l(g_graph_mu);
   return g_graphs;
@@ -818,54 +830,57 @@ void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs_in, hipStr
   std::vector<uint32_t> grid(kMaxRT + 1, 0);  // persistent grid per class, queried before any capture
   for (uint32_t RT = 1; RT <= kMaxRT; ++RT)
     if (!items[RT].empty()) grid[RT] = std::min<uint32_t>((uint32_t)items[RT].size(), cus * bdots_waves_per_cu(RT));
+  // (captured on a library stream, since the caller's may be the null stream,
+  // which cannot be captured; the graph is then launched on the caller's)
   const bool graph = graphs_enabled();
-  if (graph) check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  const hipStream_t ls = graph ? capture_stream() : s;
+  if (graph) check(hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal));
   {
-    TimedLaunch tl("batch_master", s);
-    hipLaunchKernelGGL(k_b_master_small, dim3(small.total()), dim3(64), 0, s, M, n, P32(o_small), d_bm);
+    TimedLaunch tl("batch_master", ls);
+    hipLaunchKernelGGL(k_b_master_small, dim3(small.total()), dim3(64), 0, ls, M, n, P32(o_small), d_bm);
     uint32_t r = 0;
     for (size_t lv = 0; lv < conv.size(); ++lv, r ^= 1) {
       const uint32_t h = 64u << lv, IC = level_ic[lv];
       if (conv[lv].total())
-        hipLaunchKernelGGL(k_b_master_conv, dim3(conv[lv].total()), dim3(64), (64 + IC + 8) * 8, s, M, h, IC, r, n,
+        hipLaunchKernelGGL(k_b_master_conv, dim3(conv[lv].total()), dim3(64), (64 + IC + 8) * 8, ls, M, h, IC, r, n,
                            P32(o_conv[lv]), d_bm);
       if (csum[lv].total())
-        hipLaunchKernelGGL(k_b_master_sum, dim3(csum[lv].total()), dim3(256), 0, s, M, h, cdiv(h, IC), r, n,
+        hipLaunchKernelGGL(k_b_master_sum, dim3(csum[lv].total()), dim3(256), 0, ls, M, h, cdiv(h, IC), r, n,
                            P32(o_csum[lv]), d_bm);
     }
-    if (fix.total()) hipLaunchKernelGGL(k_b_master_fix, dim3(fix.total()), dim3(256), 0, s, n, P32(o_fix), d_bm);
+    if (fix.total()) hipLaunchKernelGGL(k_b_master_fix, dim3(fix.total()), dim3(256), 0, ls, n, P32(o_fix), d_bm);
   }
   {
-    TimedLaunch tl("batch_pack", s);
-    hipLaunchKernelGGL(k_b_pack, dim3(pack.total()), dim3(256), 0, s, n, P32(o_pack), d_bs);
+    TimedLaunch tl("batch_pack", ls);
+    hipLaunchKernelGGL(k_b_pack, dim3(pack.total()), dim3(256), 0, ls, n, P32(o_pack), d_bs);
   }
   if (chain.total()) {
-    TimedLaunch tl("batch_chain", s);
-    hipLaunchKernelGGL(k_b_chain, dim3(chain.total()), dim3(256), 0, s, n, P32(o_chain), d_bs);
-    hipLaunchKernelGGL(k_b_scan, dim3(scan.total()), dim3(256), 0, s, n, P32(o_scan), d_bs);
+    TimedLaunch tl("batch_chain", ls);
+    hipLaunchKernelGGL(k_b_chain, dim3(chain.total()), dim3(256), 0, ls, n, P32(o_chain), d_bs);
+    hipLaunchKernelGGL(k_b_scan, dim3(scan.total()), dim3(256), 0, ls, n, P32(o_scan), d_bs);
   }
   {
-    TimedLaunch tl("batch_dots", s);
+    TimedLaunch tl("batch_dots", ls);
     for (uint32_t RT = 1; RT <= kMaxRT; ++RT) {
       if (!items[RT].empty()) {
         const uint32_t ni = (uint32_t)items[RT].size();
-        hipLaunchKernelGGL(bdots_kernel(RT), dim3(grid[RT]), dim3(64), 0, s, d_bs, (const uint4*)(d + o_items[RT]), ni,
+        hipLaunchKernelGGL(bdots_kernel(RT), dim3(grid[RT]), dim3(64), 0, ls, d_bs, (const uint4*)(d + o_items[RT]), ni,
                            d_heads + RT, (const uint64_t*)vt_base, part_base);
       }
       if (!lanes[RT].empty())
         for (uint32_t tile = 0; tile < max_tiles[RT]; ++tile)
-          hipLaunchKernelGGL(bpacked_kernel(RT), dim3((uint32_t)(lanes[RT].size() / 64)), dim3(64), 0, s, d_bs,
+          hipLaunchKernelGGL(bpacked_kernel(RT), dim3((uint32_t)(lanes[RT].size() / 64)), dim3(64), 0, ls, d_bs,
                              (const uint2*)(d + o_lanes[RT]), tile);
     }
   }
   {
-    TimedLaunch tl("batch_finish", s);
-    hipLaunchKernelGGL(k_b_delta, dim3(rows.total()), dim3(256), 0, s, n, P32(o_rows), d_bs);
-    hipLaunchKernelGGL(k_b_scale, dim3(scale.total()), dim3(256), 0, s, n, P32(o_scale), d_bs);
+    TimedLaunch tl("batch_finish", ls);
+    hipLaunchKernelGGL(k_b_delta, dim3(rows.total()), dim3(256), 0, ls, n, P32(o_rows), d_bs);
+    hipLaunchKernelGGL(k_b_scale, dim3(scale.total()), dim3(256), 0, ls, n, P32(o_scale), d_bs);
   }
   if (graph) {
     hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(s, &g);
+    const hipError_t e = hipStreamEndCapture(ls, &g);
     if (e != hipSuccess || !g) throw Error(ZR_EDEVICE);
     hipGraphExec_t ge = nullptr;
     if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {

@@ -42,6 +42,7 @@ void autotune(const zr_mod& M, hipStream_t s);
 // destroyed at that stream's next synchronisation by batched_lift
 // (release_graphs).
 bool graphs_enabled();
+hipStream_t capture_stream();
 void set_graphs(bool on);
 void retire_graph(hipStream_t s, hipGraph_t g, hipGraphExec_t ge);
 void release_graphs(hipStream_t s);

@@ -2,6 +2,7 @@
 // transposed Vandermonde solve, Newton lift, skeleton expansion, probes.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdlib.h>
 
 #include <algorithm>
 #include <mutex>
@@ -27,6 +28,17 @@ namespace zr {
 // ============================================================================
 
 static uint32_t dots_waves_per_cu(uint32_t RT);
+static uint32_t dots_pc_blocks_per_cu(uint32_t RT, uint32_t ntile);
+
+// The producer/consumer pass is the default for several tiles; ZR_DOTS_PC=0 in
+// the environment selects one wave per tile instead (same results).
+static bool dots_pc_enabled() {
+  static const bool on = [] {
+    const char* e = getenv("ZR_DOTS_PC");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
 
 // Chunking: enough (row block, chunk, tile) waves for about four rounds of the
 // device's resident wave slots, so the tail of the launch stays short, with
@@ -35,12 +47,27 @@ VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
   VsolvePlan P;
   P.t = t;
   P.R = R;
-  P.ntile = R == 0 ? 1 : cdiv(R, kMaxRT);
-  P.RT = R == 0 ? 1 : cdiv(R, P.ntile);
-  P.ldv = (3 * P.RT + 2 + 15) & ~15u;  // 32-bit words per packed row: 3 limbs per value + M_r, 64-byte groups
-  const uint32_t slots = std::max<uint32_t>(1, num_cus) * dots_waves_per_cu(P.RT);
   const uint32_t row_blocks = std::max<uint32_t>(1, cdiv(t, 64));
-  uint32_t S = std::max<uint32_t>(1, cdiv(4ull * slots, (uint64_t)row_blocks * P.ntile));
+  // Above kPcMinR right-hand sides the chain runs once per row block in a
+  // producer wave (k_vs_dots_pc) and consumer waves take tiles of at most
+  // kPcRT; the unit of the launch is then a workgroup of 1 + ntile waves.
+  P.pc = (R > kPcMinR && cdiv(R, kPcRT) <= kPcMaxTiles && dots_pc_enabled()) ? 1 : 0;
+  if (P.pc) {
+    P.ntile = cdiv(R, kPcRT);
+    P.RT = cdiv(R, P.ntile);
+  } else {
+    P.ntile = R == 0 ? 1 : cdiv(R, kMaxRT);
+    P.RT = R == 0 ? 1 : cdiv(R, P.ntile);
+  }
+  P.ldv = (3 * P.RT + 2 + 15) & ~15u;  // 32-bit words per packed row: 3 limbs per value + M_r, 64-byte groups
+  uint32_t S;
+  if (P.pc) {
+    const uint32_t slots = std::max<uint32_t>(1, num_cus) * dots_pc_blocks_per_cu(P.RT, P.ntile);
+    S = std::max<uint32_t>(1, cdiv(4ull * slots, (uint64_t)row_blocks));
+  } else {
+    const uint32_t slots = std::max<uint32_t>(1, num_cus) * dots_waves_per_cu(P.RT);
+    S = std::max<uint32_t>(1, cdiv(4ull * slots, (uint64_t)row_blocks * P.ntile));
+  }
   S = std::min<uint32_t>(S, std::max<uint32_t>(1, t / 128));
   S = std::min<uint32_t>(S, 256);
   P.L = std::max<uint32_t>(1, cdiv(t, S));
@@ -81,6 +108,13 @@ __global__ void __launch_bounds__(64) k_vs_dots(VsArgs a) {
   vs_dots_body<RT>(a, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
+// producer + one consumer wave per tile (64 * (1 + ntile) threads)
+template <int RT>
+__global__ void __launch_bounds__(64 * (1 + kPcMaxTiles)) k_vs_dots_pc(VsArgs a, uint32_t ntile) {
+  __shared__ uint64_t qbuf[2][kQB][64];
+  vs_dots_pc_body<RT>(a, blockIdx.x, blockIdx.y, ntile, qbuf);
+}
+
 __global__ void k_vs_delta(VsArgs a, const uint64_t* __restrict__ mLv, uint64_t* __restrict__ winv,
                            int32_t* __restrict__ status) {
   const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
@@ -104,6 +138,32 @@ static DotsKernel dots_kernel(uint32_t RT) {
       dots_ptr<12>(), dots_ptr<13>(), dots_ptr<14>(), dots_ptr<15>(), dots_ptr<16>(), dots_ptr<17>(),
       dots_ptr<18>(), dots_ptr<19>(), dots_ptr<20>()};
   return RT >= 1 && RT <= kMaxRT ? table[RT] : nullptr;
+}
+
+typedef void (*DotsPcKernel)(VsArgs, uint32_t);
+template <int RT>
+static DotsPcKernel dots_pc_ptr() {
+  return k_vs_dots_pc<RT>;
+}
+static DotsPcKernel dots_pc_kernel(uint32_t RT) {
+  static const DotsPcKernel table[kPcRT + 1] = {
+      nullptr,          dots_pc_ptr<1>(), dots_pc_ptr<2>(), dots_pc_ptr<3>(), dots_pc_ptr<4>(), dots_pc_ptr<5>(),
+      dots_pc_ptr<6>(), dots_pc_ptr<7>(), dots_pc_ptr<8>(), dots_pc_ptr<9>(), dots_pc_ptr<10>()};
+  return RT >= 1 && RT <= kPcRT ? table[RT] : nullptr;
+}
+
+// Workgroups of the producer/consumer pass resident per CU for ntile tiles.
+static uint32_t dots_pc_blocks_per_cu(uint32_t RT, uint32_t ntile) {
+  static int cache[kPcRT + 1][kPcMaxTiles + 1] = {{0}};
+  if (RT < 1 || RT > kPcRT || ntile < 1 || ntile > kPcMaxTiles) return 2;
+  if (!cache[RT][ntile]) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, dots_pc_kernel(RT), 64 * (1 + ntile), 0) != hipSuccess ||
+        nb <= 0)
+      nb = 2;
+    cache[RT][ntile] = nb;
+  }
+  return (uint32_t)cache[RT][ntile];
 }
 
 static uint32_t dots_waves_per_cu(uint32_t RT) {
@@ -159,9 +219,14 @@ hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, co
       hipLaunchKernelGGL(k_vs_scan, dim3(cdiv(t, 256)), dim3(256), 0, s, a, qstart, mL);
     }
   }
-  DotsKernel kd = dots_kernel(P.RT);
-  if (!kd) return hipErrorInvalidValue;
-  {
+  if (P.pc) {
+    DotsPcKernel kp = dots_pc_kernel(P.RT);
+    if (!kp) return hipErrorInvalidValue;
+    TimedLaunch tl("vs_dots", s);
+    hipLaunchKernelGGL(kp, dim3(cdiv(t, 64), P.S), dim3(64 * (1 + P.ntile)), 0, s, a, P.ntile);
+  } else {
+    DotsKernel kd = dots_kernel(P.RT);
+    if (!kd) return hipErrorInvalidValue;
     TimedLaunch tl("vs_dots", s);
     hipLaunchKernelGGL(kd, dim3(cdiv(t, 64), P.S, P.ntile), dim3(64), 0, s, a);
   }

@@ -18,7 +18,8 @@ struct VsolvePlan {
   uint32_t t, R;
   uint32_t L, S;       // chunk length and count
   uint32_t RT, ntile;  // right-hand sides per tile (even), number of tiles
-  uint32_t ldv;        // row stride of the packed right-hand sides = RT*ntile
+  uint32_t ldv;        // row stride (32-bit words) of one packed row of a tile
+  uint32_t pc;         // 1: producer/consumer pass (chain once per row block, one wave per tile)
 };
 VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus);
 

@@ -80,7 +80,7 @@ __device__ __forceinline__ void vs_chain_body(const VsArgs& a, uint32_t l, uint3
     for (int u = 0; u < 8; ++u) nxt[u] = rn >= (uint32_t)u + 1 + lo ? a.Mc[rn - 1 - u] : 0;
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (r - u > lo) x = zr_add(a.M, zr_shoup(a.M, x, m, mp), cur[u]);
+      if (r > lo + (uint32_t)u) x = zr_add(a.M, zr_shoup(a.M, x, m, mp), cur[u]);
     r = rn;
 #pragma unroll
     for (int u = 0; u < 8; ++u) cur[u] = nxt[u];
@@ -243,6 +243,140 @@ __device__ __forceinline__ void vs_dots_body(const VsArgs& a, uint32_t rb, uint3
     for (int j = 0; j < RT; ++j)
       if (j0 + j < a.R) a.spart[((size_t)c * a.R + j0 + j) * a.t + l] = acc6_reduce(M, acc[j]);
     if (horner) a.hpart[(size_t)c * a.t + l] = h;
+  }
+}
+
+// Producer/consumer form of pass 2 for systems with several right-hand-side
+// tiles: wave 0 of the workgroup runs the chain and Horner once and publishes
+// q_{l,r} through LDS in blocks of kQB steps (double buffered); wave 1 + tile
+// accumulates that tile's RT dot products.  Compared with one wave per tile,
+// the chain is computed once instead of ntile times and the consumer waves
+// hold no chain state, which leaves room for RT = 20 at two waves per SIMD.
+constexpr uint32_t kQB = 16;
+constexpr uint32_t kPcMinR = 10;     // more right-hand sides than this: producer/consumer pass
+constexpr uint32_t kPcRT = 10;       // right-hand sides per consumer wave (at most)
+constexpr uint32_t kPcMaxTiles = 6;  // consumer waves per workgroup (at most)
+
+// Read-only data that every lane of a wave reads at the same address, seen
+// through the constant address space: the loads stay scalar even after the
+// workgroup barriers (which otherwise count as possible writers).
+template <class T>
+using const_as = const __attribute__((address_space(4))) T*;
+
+// 64-byte group of a packed row as one vector (one scalar load)
+typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
+
+// One consumer step: q (already in registers) times row r held in cur; row
+// r - 1 is requested into nxt and the next step's q into qn before the
+// products, so that both have a whole step to arrive.
+template <int RT, int G>
+__device__ __forceinline__ void vs_pc_step(Acc6 (&acc)[RT], const u32x16 (&cur)[G], u32x16 (&nxt)[G], uint64_t& q,
+                                           const uint64_t* qnext, const_as<u32x16> rows, uint32_t& r, uint32_t lo,
+                                           uint32_t& since) {
+  const uint32_t rn = r > lo ? r - 1 : r;
+#pragma unroll
+  for (int g = 0; g < G; ++g) nxt[g] = rows[(size_t)rn * G + g];
+  const uint64_t qn = qnext ? *qnext : 0;
+  const uint32_t q0 = (uint32_t)q, q1 = (uint32_t)(q >> 32);
+#pragma unroll
+  for (int jj = 0; jj < RT; ++jj) {
+    const int w0 = 3 * jj, w1 = 3 * jj + 1, w2 = 3 * jj + 2;
+    acc6_mac(acc[jj], q0, q1, cur[w0 / 16][w0 % 16], cur[w1 / 16][w1 % 16], cur[w2 / 16][w2 % 16]);
+  }
+  if (++since == kFold) {
+#pragma unroll
+    for (int j = 0; j < RT; ++j) acc6_fold(acc[j]);
+    since = 0;
+  }
+  q = qn;
+  r = rn;
+}
+
+template <int RT>
+__device__ __forceinline__ void vs_dots_pc_body(const VsArgs& a, uint32_t rb, uint32_t c, uint32_t ntile,
+                                                uint64_t (*qbuf)[kQB][64]) {
+  constexpr int LDV = (3 * RT + 2 + 15) & ~15;
+  constexpr int G = LDV / 16;
+  // the wave index is uniform within a wave: say so, so that each role's code
+  // is compiled as uniform control flow (scalar loads, scalar loop counters)
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const uint32_t l0 = rb * 64 + lane;
+  const bool live = l0 < a.t;
+  const uint32_t l = live ? l0 : a.t - 1;
+  uint32_t lo, hi;
+  chunk_range(a.t, a.L, c, lo, hi);
+  const uint32_t nb = (hi - lo + kQB - 1) / kQB;
+  const zr_mod M = a.M;
+  if (wave == 0) {
+    // producer: q and Horner; M_r read eight at a time, the next eight in flight
+    const uint64_t m = a.mono[l], mp = a.mono_p[l];
+    uint64_t q = a.qstart ? a.qstart[(size_t)c * a.t + l] : 1 % M.p;
+    uint64_t h = 0;
+    const_as<uint64_t> Mc = (const_as<uint64_t>)a.Mc;
+    uint32_t r = hi;  // the next step is r - 1
+    uint64_t cur[8], nxt[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) cur[u] = r >= (uint32_t)u + 1 + lo ? Mc[r - 1 - u] : 0;
+    for (uint32_t it = 0; it <= nb; ++it) {
+      if (it < nb) {
+#pragma unroll
+        for (uint32_t g8 = 0; g8 < kQB / 8; ++g8) {
+          const uint32_t rn = r > lo + 8 ? r - 8 : lo;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) nxt[u] = rn >= (uint32_t)u + 1 + lo ? Mc[rn - 1 - u] : 0;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (r > lo + (uint32_t)u) {
+              qbuf[it & 1][g8 * 8 + u][lane] = q;
+              h = zr_add(M, zr_shoup(M, h, m, mp), q);
+              q = zr_add(M, zr_shoup(M, q, m, mp), cur[u]);
+            }
+          }
+          r = rn;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) cur[u] = nxt[u];
+        }
+      }
+      __syncthreads();
+    }
+    if (live) a.hpart[(size_t)c * a.t + l] = h;
+    return;
+  }
+  // consumer of tile wave - 1
+  const uint32_t tile = wave - 1;
+  if (tile >= ntile) {
+    for (uint32_t it = 0; it <= nb; ++it) __syncthreads();
+    return;
+  }
+  Acc6 acc[RT];
+#pragma unroll
+  for (int j = 0; j < RT; ++j) acc6_zero(acc[j]);
+  const_as<u32x16> rows = (const_as<u32x16>)((const uint32_t*)a.VT + (size_t)tile * a.t * LDV);
+  // two row buffers: while one feeds the products of step r the other receives
+  // row r-1, so each row's scalar loads have a whole step to arrive
+  uint32_t r = hi - 1;
+  uint32_t since = 0;
+  u32x16 b0[G], b1[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) b0[g] = rows[(size_t)r * G + g];
+  for (uint32_t it = 0; it <= nb; ++it) {
+    if (it >= 1) {
+      const uint32_t b = it - 1;
+      const uint32_t s_end = min(kQB, hi - lo - b * kQB);  // even except in the last block
+      uint64_t q = qbuf[b & 1][0][lane];
+      for (uint32_t s = 0; s < s_end; s += 2) {
+        vs_pc_step<RT, G>(acc, b0, b1, q, s + 1 < s_end ? &qbuf[b & 1][s + 1][lane] : nullptr, rows, r, lo, since);
+        if (s + 1 < s_end)
+          vs_pc_step<RT, G>(acc, b1, b0, q, s + 2 < s_end ? &qbuf[b & 1][s + 2][lane] : nullptr, rows, r, lo, since);
+      }
+    }
+    __syncthreads();
+  }
+  if (live) {
+    const uint32_t j0 = tile * RT;
+#pragma unroll
+    for (int j = 0; j < RT; ++j)
+      if (j0 + j < a.R) a.spart[((size_t)c * a.R + j0 + j) * a.t + l] = acc6_reduce(M, acc[j]);
   }
 }
 

@@ -79,9 +79,18 @@ def test_config3_stage4_is_projection(zr, cfg3):
     assert np.array_equal(e, pe) and np.array_equal(c, pc)
 
 
+class _Timed(synth.DeviceBlackBox):
+    """Device black box that reports each request (progress of long runs)."""
+
+    def device_eval(self, k, i_first, ni, y, anchor, xk, d_out, stream=0):
+        t = time.perf_counter()
+        super().device_eval(k, i_first, ni, y, anchor, xk, d_out, stream)
+        _note(f"black box stage {k}: {ni} x {len(xk)} values in {time.perf_counter() - t:.2f} s")
+
+
 def test_config3_full(zr, cfg3):
     w = cfg3
-    box = synth.DeviceBlackBox(w.hidden, nthreads=16)
+    box = _Timed(w.hidden, nthreads=16)
     t0 = time.perf_counter()
     e, c = zr.reconstruct(w.p, w.deg, box, sched=w.schedule)
     cnt = zr.last_counters()
