@@ -53,6 +53,9 @@ typedef enum {
 } zr_status;
 
 const char* zr_strerror(int status);
+/* Details of the last failure of a library call on this thread (the HIP call
+ * and its error, or the failed allocation); "" when none was recorded. */
+const char* zr_last_error(void);
 
 /* Result polynomial.  Library-owned host memory; release with zr_poly_free. */
 typedef struct {
@@ -172,6 +175,12 @@ zr_status vandermonde_solve_batch(size_t nsys, uint64_t p, const uint64_t* d_sys
  * Returns ZR_OK when the batch ran, whatever the per-instance statuses. */
 zr_status zippel_reconstruct_batch(uint32_t n, const zr_params* params, zr_blackbox_fn bb, void* const* ctx,
                                    hipStream_t stream, zr_poly* out, int32_t* status);
+
+/* Dot-product pass of the one-system solve when the right-hand sides span
+ * several tiles: 0 (default) one wave per tile, each running the synthetic
+ * division chain; 1 a producer wave runs the chain once per row block and
+ * publishes it through LDS to one consumer wave per tile.  Same results. */
+void zr_solve_variant(int producer_consumer);
 
 /* Graph mode of the batched paths (zippel_reconstruct_batch, the server,
  * vandermonde_solve_batch): with on != 0 each stage's device-side solve

@@ -22,13 +22,13 @@ ZR_EPROBE, ZR_ENORM, ZR_ENOMEM, ZR_EDEVICE, ZR_EBLACKBOX = -5, -6, -7, -8, -9
 
 # every symbol include/zippel.h declares
 EXPORTS = [
-    "zr_strerror", "zr_poly_free", "zr_thiele_nodes", "zr_schedule", "zr_is_prime", "zippel_reconstruct",
+    "zr_strerror", "zr_last_error", "zr_poly_free", "zr_thiele_nodes", "zr_schedule", "zr_is_prime", "zippel_reconstruct",
     "zippel_balanced_reconstruct", "vandermonde_solve_batch", "zr_copy_h2d", "zr_copy_d2h", "zr_copy_d2d",
     "zr_recorder_create", "zr_recorder_destroy", "zr_recorder_rewind", "zr_recorder_set_replay",
     "zr_recorder_blackbox", "zr_timing_enable", "zr_timing_reset", "zr_timing_get", "zr_last_counters",
     "zr_microbench", "zippel_reconstruct_batch", "zr_autotune", "zr_tuning_get", "zr_tuning_set",
     "zr_server_create", "zr_server_destroy", "zr_server_submit", "zr_server_step", "zr_server_poll",
-    "zr_server_get_stats", "zr_batch_graphs",
+    "zr_server_get_stats", "zr_batch_graphs", "zr_solve_variant",
 ]
 MB_KINDS = {"mad_u64_u32": 0, "mul_lo_u32": 1, "mul_hi_u32": 2, "add_u32": 3, "mac192": 4, "shoup": 5, "copy": 6}
 
@@ -36,7 +36,8 @@ MB_KINDS = {"mad_u64_u32": 0, "mul_lo_u32": 1, "mul_hi_u32": 2, "add_u32": 3, "m
 class ZippelError(RuntimeError):
     def __init__(self, code: int, what: str = ""):
         msg = lib().zr_strerror(code).decode() if _LIB is not None else str(code)
-        super().__init__(f"{what}: status {code} ({msg})")
+        detail = lib().zr_last_error().decode() if _LIB is not None else ""
+        super().__init__(f"{what}: status {code} ({msg}){'; ' + detail if detail else ''}")
         self.code = code
 
 
@@ -87,9 +88,14 @@ def lib():
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"HIP library not built: {LIB_PATH} (run paper_2505_24256_amd.build.build())")
+        # PyTorch ships its own copy of the HIP runtime; loading it first makes
+        # the library bind to that same copy (one runtime per process)
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         u64, u32, vp, sz, i32 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
         L.zr_strerror.restype = ctypes.c_char_p
+        L.zr_last_error.restype = ctypes.c_char_p
+        L.zr_last_error.argtypes = []
         L.zr_strerror.argtypes = [i32]
         L.zr_poly_free.argtypes = [ctypes.POINTER(ZrPoly)]
         L.zr_poly_free.restype = None
@@ -104,6 +110,8 @@ def lib():
         L.zippel_reconstruct_batch.argtypes = [u32, ctypes.POINTER(ZrParams), vp, vp, vp, ctypes.POINTER(ZrPoly),
                                                vp]
         L.zr_autotune.argtypes = [u64, vp, ctypes.POINTER(ZrBandChoice)]
+        L.zr_solve_variant.argtypes = [i32]
+        L.zr_solve_variant.restype = None
         L.zr_batch_graphs.argtypes = [i32]
         L.zr_batch_graphs.restype = None
         L.zr_server_create.argtypes = [ctypes.POINTER(vp), u64, u64, u32, vp]
@@ -382,6 +390,11 @@ def autotune(p: int, stream=None):
     if st != ZR_OK:
         raise ZippelError(st, "zr_autotune")
     return [(t.packed, t.min_chunk) for t in tab]
+
+
+def solve_variant(producer_consumer: bool):
+    """Select the dot-product pass of the one-system solve (zr_solve_variant)."""
+    lib().zr_solve_variant(1 if producer_consumer else 0)
 
 
 def batch_graphs(on: bool):

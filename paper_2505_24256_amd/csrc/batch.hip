@@ -151,7 +151,7 @@ __global__ void __launch_bounds__(64) k_b_dots_packed(const BSolve* __restrict__
       q = zr_add(M, zr_shoup(M, q, m, mp), Mr);
       if (++since == kFold) {
 #pragma unroll
-        for (int j = 0; j < RT; ++j) acc6_fold(acc[j]);
+        for (int j = 0; j < RT; ++j) acc6_fold(acc[j], M);
         since = 0;
       }
     }
@@ -425,7 +425,7 @@ char* Blob::upload(DevArena& A, hipStream_t s) {
       Staging x;
       x.n = std::max<size_t>(bytes_.size(), 1 << 20);
       void* p = nullptr;
-      if (hipHostMalloc(&p, x.n, hipHostMallocDefault) != hipSuccess) throw Error(ZR_ENOMEM);
+      check(hipHostMalloc(&p, x.n, hipHostMallocDefault));
       x.p = (char*)p;
       check(hipEventCreateWithFlags(&x.done, hipEventDisableTiming));
       staging_pool().push_back(x);

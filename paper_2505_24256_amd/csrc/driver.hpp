@@ -18,7 +18,11 @@ struct Error {
   explicit Error(int c) : code(c) {}
 };
 
-void check(hipError_t e);
+// Throw Error(ZR_ENOMEM / ZR_EDEVICE) for a failed HIP call, recording the
+// call's text and location for zr_last_error().
+void check_at(hipError_t e, const char* what, const char* file, int line);
+#define check(e) ::zr::check_at((e), #e, __FILE__, __LINE__)
+void note_error(const char* fmt, ...);
 void h2d(void* d, const void* h, size_t bytes, hipStream_t s);
 void d2h_sync(void* h, const void* d, size_t bytes, hipStream_t s);
 

@@ -5,6 +5,7 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -30,19 +31,15 @@ namespace zr {
 static uint32_t dots_waves_per_cu(uint32_t RT);
 static uint32_t dots_pc_blocks_per_cu(uint32_t RT, uint32_t ntile);
 
-// The producer/consumer pass is the default for several tiles; ZR_DOTS_PC=0 in
-// the environment selects one wave per tile instead (same results).
-static bool dots_pc_enabled() {
-  static const bool on = [] {
-    const char* e = getenv("ZR_DOTS_PC");
-    return !(e && e[0] == '0');
-  }();
-  return on;
-}
+// Variant of the dot-product pass for several tiles: one wave per tile (the
+// default), or the producer/consumer form (zr_solve_variant(1)).
+static std::atomic<int> g_dots_pc{0};
+static bool dots_pc_enabled() { return g_dots_pc.load() != 0; }
 
-// Chunking: enough (row block, chunk, tile) waves for about four rounds of the
-// device's resident wave slots, so the tail of the launch stays short, with
-// chunks of at least 128 steps.
+// Widest tile of the one-wave-per-tile pass: 16 right-hand sides keep two
+// waves per SIMD (20 would drop to one).
+constexpr uint32_t kPlanRT = 16;
+
 VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
   VsolvePlan P;
   P.t = t;
@@ -56,7 +53,7 @@ VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
     P.ntile = cdiv(R, kPcRT);
     P.RT = cdiv(R, P.ntile);
   } else {
-    P.ntile = R == 0 ? 1 : cdiv(R, kMaxRT);
+    P.ntile = R == 0 ? 1 : cdiv(R, kPlanRT);
     P.RT = R == 0 ? 1 : cdiv(R, P.ntile);
   }
   P.ldv = (3 * P.RT + 2 + 15) & ~15u;  // 32-bit words per packed row: 3 limbs per value + M_r, 64-byte groups
@@ -584,6 +581,8 @@ TimedLaunch::~TimedLaunch() {
 }  // namespace zr
 
 extern "C" {
+void zr_solve_variant(int producer_consumer) { zr::g_dots_pc.store(producer_consumer ? 1 : 0); }
+
 void zr_timing_enable(int on) {
   std::lock_guard<std::mutex> g(zr::g_timing.mu);
   zr::g_timing.on = on != 0;

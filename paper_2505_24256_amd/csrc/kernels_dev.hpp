@@ -106,9 +106,9 @@ __device__ __forceinline__ void vs_scan_body(const VsArgs& a, uint32_t l, uint64
 // and v = v0 + v1 2^22 + v2 2^44 (22-bit limbs, packed once per system), so
 //   q v = q0 v0 + q0 v1 2^22 + q1 v0 2^32 + q0 v2 2^44 + q1 v1 2^54 + q1 v2 2^76,
 // six 32x32 products below 2^54, each summed by one v_mad_u64_u32 into its own
-// 64-bit column.  A column absorbs 1024 such products; every kFold steps the
-// bits above each column's range are moved into the column of matching weight
-// (exact shifts and adds), so chunks of any length stay exact.
+// 64-bit column.  Every kFold steps the bits above each column's range are
+// moved into the column of matching weight (exact shifts and adds) and the top
+// column is reduced mod p, so sums of any length stay exact.
 struct Acc6 {
   uint64_t w0, w22, w32, w44, w54, w76;
 };
@@ -127,9 +127,12 @@ __device__ __forceinline__ void acc6_mac(Acc6& a, uint32_t q0, uint32_t q1, uint
   a.w76 += (uint64_t)q1 * v2;
 }
 
-// Move everything above bit 54 of each weight-0..44 column into w54, and
-// everything above bit 22 of w54 into w76.
-__device__ __forceinline__ void acc6_fold(Acc6& a) {
+// Move everything above bit 54 of each weight-0..44 column into w54,
+// everything above bit 22 of w54 into w76, and reduce w76 mod p (its weight
+// 2^76 is applied mod p at the end, so only its residue matters).  Between two
+// folds each column gains at most kFold products below 2^54, so no column can
+// wrap, however long the sum.
+__device__ __forceinline__ void acc6_fold(Acc6& a, const zr_mod& M) {
   a.w54 += (a.w0 >> 54) + (a.w22 >> 32) + (a.w32 >> 22) + (a.w44 >> 10);
   a.w0 &= (1ull << 54) - 1;
   a.w22 &= (1ull << 32) - 1;
@@ -137,6 +140,7 @@ __device__ __forceinline__ void acc6_fold(Acc6& a) {
   a.w44 &= (1ull << 10) - 1;
   a.w76 += a.w54 >> 22;
   a.w54 &= (1ull << 22) - 1;
+  a.w76 = zr_mod128(M, 0, a.w76);
 }
 
 // add x * 2^s (x < 2^64, s < 128) to the 192-bit (w[0], w[1], w[2])
@@ -231,7 +235,7 @@ __device__ __forceinline__ void vs_dots_body(const VsArgs& a, uint32_t rb, uint3
     q = zr_add(M, zr_shoup(M, q, m, mp), Mr);
     if (++since == kFold) {
 #pragma unroll
-      for (int j = 0; j < RT; ++j) acc6_fold(acc[j]);
+      for (int j = 0; j < RT; ++j) acc6_fold(acc[j], M);
       since = 0;
     }
     if (r == lo) break;
@@ -270,9 +274,9 @@ typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
 // r - 1 is requested into nxt and the next step's q into qn before the
 // products, so that both have a whole step to arrive.
 template <int RT, int G>
-__device__ __forceinline__ void vs_pc_step(Acc6 (&acc)[RT], const u32x16 (&cur)[G], u32x16 (&nxt)[G], uint64_t& q,
-                                           const uint64_t* qnext, const_as<u32x16> rows, uint32_t& r, uint32_t lo,
-                                           uint32_t& since) {
+__device__ __forceinline__ void vs_pc_step(const zr_mod& M, Acc6 (&acc)[RT], const u32x16 (&cur)[G],
+                                           u32x16 (&nxt)[G], uint64_t& q, const uint64_t* qnext,
+                                           const_as<u32x16> rows, uint32_t& r, uint32_t lo, uint32_t& since) {
   const uint32_t rn = r > lo ? r - 1 : r;
 #pragma unroll
   for (int g = 0; g < G; ++g) nxt[g] = rows[(size_t)rn * G + g];
@@ -285,7 +289,7 @@ __device__ __forceinline__ void vs_pc_step(Acc6 (&acc)[RT], const u32x16 (&cur)[
   }
   if (++since == kFold) {
 #pragma unroll
-    for (int j = 0; j < RT; ++j) acc6_fold(acc[j]);
+    for (int j = 0; j < RT; ++j) acc6_fold(acc[j], M);
     since = 0;
   }
   q = qn;
@@ -365,9 +369,11 @@ __device__ __forceinline__ void vs_dots_pc_body(const VsArgs& a, uint32_t rb, ui
       const uint32_t s_end = min(kQB, hi - lo - b * kQB);  // even except in the last block
       uint64_t q = qbuf[b & 1][0][lane];
       for (uint32_t s = 0; s < s_end; s += 2) {
-        vs_pc_step<RT, G>(acc, b0, b1, q, s + 1 < s_end ? &qbuf[b & 1][s + 1][lane] : nullptr, rows, r, lo, since);
+        vs_pc_step<RT, G>(M, acc, b0, b1, q, s + 1 < s_end ? &qbuf[b & 1][s + 1][lane] : nullptr, rows, r, lo,
+                          since);
         if (s + 1 < s_end)
-          vs_pc_step<RT, G>(acc, b1, b0, q, s + 2 < s_end ? &qbuf[b & 1][s + 2][lane] : nullptr, rows, r, lo, since);
+          vs_pc_step<RT, G>(M, acc, b1, b0, q, s + 2 < s_end ? &qbuf[b & 1][s + 2][lane] : nullptr, rows, r, lo,
+                            since);
       }
     }
     __syncthreads();
@@ -538,6 +544,7 @@ __device__ __forceinline__ void master_conv_body(const zr_mod& M, uint32_t t, ui
     const uint4* __restrict__ Lg = limbs + a;
     const uint64_t* __restrict__ wk = win + ((int64_t)k - jbase);
     L8 L = *(const L8*)(Lg + ilo);
+    uint32_t since = 0;
     for (uint32_t i = ilo; i < ihi8; i += 8) {
       // fetch the next group of eight coefficients while this one is used
       const uint32_t in8 = i + 8 < ihi8 ? i + 8 : i;
@@ -549,6 +556,11 @@ __device__ __forceinline__ void master_conv_body(const zr_mod& M, uint32_t t, ui
         acc6_mac(acc, (uint32_t)Rv, (uint32_t)(Rv >> 32), in ? L.v[u].x : 0u, in ? L.v[u].y : 0u, in ? L.v[u].z : 0u);
       }
       L = Ln;
+      since += 8;
+      if (since == kFold) {  // chunks longer than kFold products
+        acc6_fold(acc, M);
+        since = 0;
+      }
     }
   }
   if (g >= t) return;

@@ -2,7 +2,10 @@
 // The host runs the stage loop (one stage per variable, §1) and talks to the
 // black box; every O(t^2) and O(t D^2) step runs in the gfx950 kernels.
 #include <hip/hip_runtime.h>
+#include <stdarg.h>
 #include <stdint.h>
+#include <stdio.h>
+#include <string.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -66,7 +69,9 @@ void* DevArena::raw(size_t bytes) {
     }
   }
   void* p = nullptr;
-  if (hipMallocAsync(&p, cls, s) != hipSuccess || !p) {
+  const hipError_t e = hipMallocAsync(&p, cls, s);
+  if (e != hipSuccess || !p) {
+    note_error("hipMallocAsync(%zu bytes for %zu requested) failed: %s", cls, bytes, hipGetErrorString(e));
     (void)hipGetLastError();
     throw Error(ZR_ENOMEM);
   }
@@ -74,8 +79,19 @@ void* DevArena::raw(size_t bytes) {
   return p;
 }
 
-void check(hipError_t e) {
+static thread_local char g_last_error[512] = "";
+
+void note_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+}
+
+void check_at(hipError_t e, const char* what, const char* file, int line) {
   if (e != hipSuccess) {
+    const char* base = strrchr(file, '/');
+    note_error("%s failed: %s (%s:%d)", what, hipGetErrorString(e), base ? base + 1 : file, line);
     if (e == hipErrorOutOfMemory) throw Error(ZR_ENOMEM);
     throw Error(ZR_EDEVICE);
   }
@@ -412,7 +428,7 @@ int32_t* host_scratch() {
   static thread_local int32_t* buf = nullptr;
   if (!buf) {
     void* p = nullptr;
-    if (hipHostMalloc(&p, 64, hipHostMallocDefault) != hipSuccess) throw Error(ZR_ENOMEM);
+    check(hipHostMalloc(&p, 64, hipHostMallocDefault));
     buf = (int32_t*)p;
   }
   return buf;
@@ -576,6 +592,8 @@ void check_probes(const Params& P, zr_blackbox_fn bb, void* ctx, const Skeleton&
 using namespace zr;
 
 extern "C" {
+
+const char* zr_last_error(void) { return g_last_error; }
 
 const char* zr_strerror(int st) {
   switch (st) {

@@ -563,6 +563,7 @@ _HIP = None
 def dev_lib():
     global _DEV, _HIP
     if _DEV is None:
+        import torch  # noqa: F401  (one HIP runtime per process: PyTorch's, loaded first)
         D = ctypes.CDLL(dev_lib_path())
         D.zsd_apply.restype = ctypes.c_int
         D.zsd_apply.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
