@@ -35,6 +35,21 @@ CU, SIMD, LANES, CLOCK_GHZ = 256, 4, 16, 2.4
 MUL32_PEAK_TOPS = CU * SIMD * LANES * CLOCK_GHZ * 1e9 / 1e12
 MUL32_PER_MULMOD = 4
 
+# HBM bytes per k_vs_dots launch on this workload, from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE scaled by the copy-probe calibration (0.5x read, 1.0x write); see
+# profiles/k_vs_dots_plain_n6_d30_t1e4_hbm_counters.md.  Valid only for the
+# kernel sources those counters were taken on.
+DOTS_TRAFFIC = {"sources_sha16": "814bca904f8597eb", "bytes_per_launch": 82.05e6}
+
+
+def _dots_sources_sha16() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("field.hpp", "kernels_dev.hpp", "kernels.hip"):
+        with open(os.path.join(ROOT, "paper_2505_24256_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 class CachingBox:
     """Host black box (synth) whose answers are kept for re-use."""
@@ -328,7 +343,10 @@ def main():
     achieved = achieved_mulmod_s * MUL32_PER_MULMOD / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(MUL32_PEAK_TOPS, 3),
                 "unit": "TOP/s (32x32-bit multiplies; one 64x64-bit modular product or multiply-accumulate = 4)",
-                "frac": round(achieved / MUL32_PEAK_TOPS, 4), "traffic": None,
+                "frac": round(achieved / MUL32_PEAK_TOPS, 4),
+                "traffic": (DOTS_TRAFFIC["bytes_per_launch"] if _dots_sources_sha16() == DOTS_TRAFFIC["sources_sha16"]
+                            else None),
+                "traffic_unit": "bytes per launch (HBM, rocprofv3 counters, calibrated)",
                 "kernel": "k_vs_dots", "launches_per_step": n_dots // steps if steps else 0,
                 "avg_launch_ms": round(ms_dots / n_dots, 4) if n_dots else None}
 

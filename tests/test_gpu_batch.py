@@ -140,3 +140,27 @@ def test_batch_graphs_identical(zr):
                 assert np.array_equal(b[0], w.hidden.exps) and np.array_equal(b[1], w.hidden.coefs)
     finally:
         zr.batch_graphs(False)
+
+
+def test_long_unsplit_chain_is_exact(zr):
+    """One system of 20000 rows solved without chunking (every row's sum runs
+    over all 20000 steps) and right-hand sides just below p, so that the
+    accumulator columns would wrap without their periodic reduction; rows
+    sampled against the oracle."""
+    import random
+    p = synth.make_prime()
+    t, R = 20_000, 16
+    g = synth.SplitMix64(2024)
+    m = g.uniform_block(1, p, t)
+    assert len(set(int(x) for x in m)) == t
+    rhs = (np.uint64(p - 1) - g.uniform_block(0, 1 << 20, t * R)).reshape(R, t)
+    saved = zr.tuning_get()[1]
+    try:
+        zr.tuning_set([(0, 1 << 30)] * zr.NBANDS)  # never split a system
+        got, status = zr.vandermonde_solve_batch(p, [(m, rhs)])
+    finally:
+        zr.tuning_set(saved)
+    assert status[0] == 0
+    rows = sorted(random.Random(5).sample(range(t), 24) + [0, t - 1])
+    want = oracle.vandermonde_solve_rows(p, m, rhs, rows)
+    assert np.array_equal(got[0][:, rows], want)
