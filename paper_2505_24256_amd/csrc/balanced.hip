@@ -23,12 +23,10 @@ static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b -
 // and scale so that the lowest nonzero coefficient of B is 1.
 // Arrays are SoA [index][T] so that consecutive lanes touch consecutive words.
 // ----------------------------------------------------------------------------
-__global__ void k_thiele(zr_mod M, uint32_t T, uint32_t nk, const uint64_t* __restrict__ X,
-                         const uint64_t* __restrict__ F, uint64_t* __restrict__ A, uint64_t* __restrict__ B,
-                         int32_t* __restrict__ degA, int32_t* __restrict__ degB, int32_t* __restrict__ st,
-                         uint64_t* __restrict__ scratch) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= T) return;
+__device__ void thiele_body(const zr_mod& M, uint32_t T, uint32_t nk, const uint64_t* __restrict__ X,
+                            const uint64_t* __restrict__ F, uint64_t* __restrict__ A, uint64_t* __restrict__ B,
+                            int32_t* __restrict__ degA, int32_t* __restrict__ degB, int32_t* __restrict__ st,
+                            uint64_t* __restrict__ scratch, uint32_t i) {
   uint64_t* phi = scratch;
   uint64_t* b = phi + (size_t)nk * T;
   uint64_t* NA = b + (size_t)nk * T;
@@ -57,16 +55,27 @@ __global__ void k_thiele(zr_mod M, uint32_t T, uint32_t nk, const uint64_t* __re
       P = nP;
     }
     if (ok && P == zr_mul(M, FV(m + 1), Q)) break;
+    // phi_{m+1}(x_j) for j > m, the denominators inverted together
+    // (Montgomery's batch inversion: one inverse and three products each)
     const uint64_t pm = PHI(m), xm = X[m];
+    uint64_t pre = 1 % M.p;
     for (uint32_t j = m + 1; j < nk; ++j) {
       const uint64_t den = zr_sub(M, PHI(j), pm);
       if (den == 0) {
         status = -4;
         break;
       }
-      PHI(j) = zr_mul(M, zr_sub(M, X[j], xm), zr_inv(M, den));
+      NA[(size_t)j * T + i] = pre;  // product of the denominators before j
+      pre = zr_mul(M, pre, den);
     }
     if (status) break;
+    uint64_t inv = zr_inv(M, pre);
+    for (uint32_t j = nk; j-- > m + 1;) {
+      const uint64_t den = zr_sub(M, PHI(j), pm);
+      const uint64_t dinv = zr_mul(M, inv, NA[(size_t)j * T + i]);
+      inv = zr_mul(M, inv, den);
+      PHI(j) = zr_mul(M, zr_sub(M, X[j], xm), dinv);
+    }
     BB(m + 1) = PHI(m + 1);
     ++m;
   }
@@ -125,6 +134,37 @@ __global__ void k_thiele(zr_mod M, uint32_t T, uint32_t nk, const uint64_t* __re
 #undef AA
 #undef BQ
 #undef NN
+}
+
+__global__ void k_thiele(zr_mod M, uint32_t T, uint32_t nk, const uint64_t* __restrict__ X,
+                         const uint64_t* __restrict__ F, uint64_t* __restrict__ A, uint64_t* __restrict__ B,
+                         int32_t* __restrict__ degA, int32_t* __restrict__ degB, int32_t* __restrict__ st,
+                         uint64_t* __restrict__ scratch) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < T) thiele_body(M, T, nk, X, F, A, B, degA, degB, st, scratch, i);
+}
+
+// Slices of many reconstructions in one launch: block b belongs to job
+// seg(b) (largest s with prefix[s] <= b), 64 slices per block.
+__global__ void k_thiele_batch(zr_mod M, uint32_t n, const uint32_t* __restrict__ prefix,
+                               const ThieleJob* __restrict__ jobs) {
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (prefix[mid] <= blockIdx.x) lo = mid;
+    else hi = mid;
+  }
+  const ThieleJob& j = jobs[lo];
+  const uint32_t i = (blockIdx.x - prefix[lo]) * blockDim.x + threadIdx.x;
+  if (i < j.T) thiele_body(M, j.T, j.nk, j.X, j.F, j.A, j.B, j.degA, j.degB, j.st, j.scratch, i);
+}
+
+hipError_t thiele_slices_batch(const zr_mod& M, uint32_t n, const uint32_t* d_prefix, uint32_t total_blocks,
+                               const ThieleJob* d_jobs, hipStream_t s) {
+  if (n == 0 || total_blocks == 0) return hipSuccess;
+  TimedLaunch tl("thiele", s);
+  hipLaunchKernelGGL(k_thiele_batch, dim3(total_blocks), dim3(64), 0, s, M, n, d_prefix, d_jobs);
+  return hipGetLastError();
 }
 
 hipError_t thiele_slices(const zr_mod& M, uint32_t T, uint32_t nk, const uint64_t* X, const uint64_t* F, uint64_t* A,

@@ -79,6 +79,22 @@ hipError_t thiele_slices(const zr_mod& M, uint32_t T, uint32_t nk, const uint64_
                          uint64_t* A, uint64_t* B, int32_t* degA, int32_t* degB, int32_t* st, uint64_t* scratch,
                          hipStream_t s);
 
+// Thiele for the slices of several reconstructions in one launch (64 slices per
+// block; d_prefix[n+1] holds the prefix sums of cdiv(T_j, 64)).
+struct ThieleJob {
+  uint32_t T, nk;
+  const uint64_t* X;
+  const uint64_t* F;
+  uint64_t* A;
+  uint64_t* B;
+  int32_t* degA;
+  int32_t* degB;
+  int32_t* st;
+  uint64_t* scratch;
+};
+hipError_t thiele_slices_batch(const zr_mod& M, uint32_t n, const uint32_t* d_prefix, uint32_t total_blocks,
+                               const ThieleJob* d_jobs, hipStream_t s);
+
 // Transposed Vandermonde apply: out[i] = sum_l a_l m_l^(i+1), i = 0..T-1.
 hipError_t vapply(const zr_mod& M, uint32_t t, const uint64_t* mono, const uint64_t* a, uint32_t T, uint64_t* out,
                   uint64_t* work, size_t work_words, hipStream_t s);

@@ -186,6 +186,8 @@ void advance(Server& S) {
     for (auto& b : bal) xo.push_back(xb.add(b.X));
     char* dxb = xb.upload(A, s);
     size_t hwords = 0;
+    std::vector<ThieleJob> tj;
+    std::vector<uint32_t> tprefix{0};
     for (size_t q = 0; q < bal.size(); ++q) {
       Bal& b = bal[q];
       Request& r = *b.r;
@@ -208,12 +210,21 @@ void advance(Server& S) {
         r.status = e.code;
         continue;
       }
-      check(thiele_slices(M, b.T, b.nk, b.dX, b.F, b.cA, b.cB, b.dgA, b.dgB, b.dst, scr, s));
+      // the slices of every request go through one Thiele launch below
+      tj.push_back(ThieleJob{b.T, b.nk, b.dX, b.F, b.cA, b.cB, b.dgA, b.dgB, b.dst, scr});
+      tprefix.push_back(tprefix.back() + (b.T + 63) / 64);
       const size_t ww = std::max(vapply_work_words(r.SN.t, b.T), vapply_work_words(r.SD.t, b.T));
       uint64_t* wk = A.alloc<uint64_t>(ww);
       check(vapply(M, r.SN.t, r.SN.mono, r.SN.coef, b.T, b.nprev, wk, ww, s));
       check(vapply(M, r.SD.t, r.SD.mono, r.SD.coef, b.T, b.dprev, wk, ww, s));
       counters().mulmods += (uint64_t)b.T * (r.SN.t + r.SD.t);
+    }
+    if (!tj.empty()) {
+      Blob tb;
+      const size_t oj = tb.add(tj), op = tb.add(tprefix);
+      char* dt = tb.upload(A, s);
+      check(thiele_slices_batch(M, (uint32_t)tj.size(), (const uint32_t*)(dt + op), tprefix.back(),
+                                (const ThieleJob*)(dt + oj), s));
     }
     // one read-back of every slice's degrees and status
     if (S.hcap < hwords) {
