@@ -142,6 +142,26 @@ zr_status zippel_reconstruct(const zr_params* params, zr_blackbox_fn bb, void* c
 zr_status zippel_balanced_reconstruct(const zr_params* params, zr_blackbox_fn bb, void* ctx, hipStream_t stream,
                                       zr_poly* num, zr_poly* den);
 
+/* Per-slice Thiele reconstruction (eq. 2), the univariate step of balanced
+ * Zippel (§2.2).  For each of T slices: the shortest continued fraction
+ * b_0 + (x - x_0)/(b_1 + (x - x_1)/(... + (x - x_{m-1})/b_m)) through the
+ * samples at X[0..m] whose value at X[m+1] equals the sample there, written
+ * as A(x)/B(x) and scaled so that the lowest nonzero coefficient of B is 1.
+ *   d_X       device [nk], distinct nodes in [0, p)
+ *   d_F       device [nk][T], each < p: the sample of slice i at X[j] is at [j][i]
+ *   d_A, d_B  device [nk+1][T] outputs: coefficient r of slice i at [r][i]
+ *             (zero above the degree); not written for a failed slice
+ *   d_degA, d_degB, d_status  device [T] int32: the degrees, and ZR_OK,
+ *             ZR_EDEGEN (a vanishing inverse difference before confirmation,
+ *             or B = 0) or ZR_EPROBE (nothing confirmed within the nk samples);
+ *             degrees -1 for a failed slice
+ * nk <= 511 runs one wavefront per slice; longer node lists one lane per
+ * slice with library-allocated scratch.  Asynchronous on `stream`; argument
+ * errors return at once (ZR_EINVAL, ZR_ENOTPRIME). */
+zr_status zr_thiele_slices(uint64_t p, uint32_t T, uint32_t nk, const uint64_t* d_X, const uint64_t* d_F,
+                           uint64_t* d_A, uint64_t* d_B, int32_t* d_degA, int32_t* d_degB, int32_t* d_status,
+                           hipStream_t stream);
+
 /* Batched transposed Vandermonde solve (the O(t^2) step of §1 and §2.2, many
  * systems and right-hand sides at once).  System s has t_s unknowns and R_s
  * right-hand sides; for each right-hand side j it solves

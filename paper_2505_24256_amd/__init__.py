@@ -28,7 +28,7 @@ EXPORTS = [
     "zr_recorder_blackbox", "zr_timing_enable", "zr_timing_reset", "zr_timing_get", "zr_last_counters",
     "zr_microbench", "zippel_reconstruct_batch", "zr_autotune", "zr_tuning_get", "zr_tuning_set",
     "zr_server_create", "zr_server_destroy", "zr_server_submit", "zr_server_step", "zr_server_poll",
-    "zr_server_get_stats", "zr_batch_graphs", "zr_solve_variant",
+    "zr_server_get_stats", "zr_batch_graphs", "zr_solve_variant", "zr_thiele_slices",
 ]
 MB_KINDS = {"mad_u64_u32": 0, "mul_lo_u32": 1, "mul_hi_u32": 2, "add_u32": 3, "mac192": 4, "shoup": 5, "copy": 6}
 
@@ -107,6 +107,7 @@ def lib():
         L.zippel_balanced_reconstruct.argtypes = [ctypes.POINTER(ZrParams), vp, vp, vp, ctypes.POINTER(ZrPoly),
                                                   ctypes.POINTER(ZrPoly)]
         L.vandermonde_solve_batch.argtypes = [sz, u64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.zr_thiele_slices.argtypes = [u64, u32, u32, vp, vp, vp, vp, vp, vp, vp, vp]
         L.zippel_reconstruct_batch.argtypes = [u32, ctypes.POINTER(ZrParams), vp, vp, vp, ctypes.POINTER(ZrPoly),
                                                vp]
         L.zr_autotune.argtypes = [u64, vp, ctypes.POINTER(ZrBandChoice)]
@@ -523,6 +524,33 @@ def vandermonde_solve_batch(p: int, systems: List[Tuple[np.ndarray, np.ndarray]]
     out = d_out.cpu().numpy().view(np.uint64)
     res = [out[int(rhs_off[i]):int(rhs_off[i + 1])].reshape(int(R[i]), int(t[i])) for i in range(nsys)]
     return res, d_status.cpu().numpy()[:nsys]
+
+
+def thiele_slices(p: int, x, f, stream=None):
+    """Per-slice Thiele reconstruction on the GPU (zr_thiele_slices): x [nk]
+    nodes, f [nk][T] samples.  Returns (A [nk+1][T], B [nk+1][T], degA [T],
+    degB [T], status [T]); column i holds slice i, entries of failed slices
+    are unspecified."""
+    import torch
+    x = _u64(x)
+    f = _u64(f).reshape(len(x), -1) if len(x) else np.zeros((0, 0), np.uint64)
+    nk, T = f.shape
+    dev = torch.device("cuda")
+    d_x = torch.from_numpy(np.concatenate([x, np.zeros(1, np.uint64)]).view(np.int64)).to(dev)
+    d_f = torch.from_numpy(np.concatenate([f.reshape(-1), np.zeros(1, np.uint64)]).view(np.int64)).to(dev)
+    d_a = torch.zeros((nk + 1) * max(T, 1), dtype=torch.int64, device=dev)
+    d_b = torch.zeros_like(d_a)
+    d_i = torch.zeros(3 * max(T, 1), dtype=torch.int32, device=dev)
+    st = lib().zr_thiele_slices(p, T, nk, d_x.data_ptr(), d_f.data_ptr(), d_a.data_ptr(), d_b.data_ptr(),
+                                d_i.data_ptr(), d_i.data_ptr() + 4 * max(T, 1), d_i.data_ptr() + 8 * max(T, 1),
+                                _stream(stream))
+    if st != ZR_OK:
+        raise ZippelError(st, "zr_thiele_slices")
+    torch.cuda.synchronize()
+    a = d_a.cpu().numpy().view(np.uint64)[:(nk + 1) * T].reshape(nk + 1, T)
+    b = d_b.cpu().numpy().view(np.uint64)[:(nk + 1) * T].reshape(nk + 1, T)
+    i = d_i.cpu().numpy().reshape(3, max(T, 1))[:, :T]
+    return a, b, i[0], i[1], i[2]
 
 
 # ---------------------------------------------------------------------------

@@ -85,7 +85,8 @@ void balanced_stage1(const Params& P, zr_blackbox_fn bb, void* ctx, DevArena& ke
   uint64_t* dA = A.alloc<uint64_t>(n1 + 1);
   uint64_t* dB = A.alloc<uint64_t>(n1 + 1);
   int32_t* dg = A.alloc<int32_t>(3);
-  uint64_t* scr = A.alloc<uint64_t>(3 * (size_t)n1 + 2);
+  const size_t sw = thiele_scratch_words(1, n1);
+  uint64_t* scr = sw ? A.alloc<uint64_t>(sw) : nullptr;
   h2d(dX, X.data(), n1 * 8, s);
   call_bb(bb, ctx, P, 1, 1, P.y.data(), X.data(), n1, F, s);
   check(thiele_slices(P.M, 1, n1, dX, F, dA, dB, dg, dg + 1, dg + 2, scr, s));
@@ -157,7 +158,8 @@ static void reconstruct_balanced(const zr_params* params, zr_blackbox_fn bb, voi
       int32_t* dgA = A.alloc<int32_t>(std::max<uint32_t>(T, 1));
       int32_t* dgB = A.alloc<int32_t>(std::max<uint32_t>(T, 1));
       int32_t* dst = A.alloc<int32_t>(std::max<uint32_t>(T, 1));
-      uint64_t* scr = A.alloc<uint64_t>((size_t)(3 * nk + 1) * std::max<uint32_t>(T, 1));
+      const size_t sw = thiele_scratch_words(T, nk);
+      uint64_t* scr = sw ? A.alloc<uint64_t>(sw) : nullptr;
       check(thiele_slices(P.M, T, nk, dX, F, cA, cB, dgA, dgB, dst, scr, s));
       int32_t rhoN = 0, rhoD = 0;
       check_slices(d2h_i32(dst, T, s), d2h_i32(dgA, T, s), d2h_i32(dgB, T, s), P.deg[kvar], P.deg_den[kvar], rhoN,
@@ -215,6 +217,28 @@ extern "C" zr_status zippel_balanced_reconstruct(const zr_params* params, zr_bla
   } catch (const std::bad_alloc&) {
     zr_poly_free(num);
     zr_poly_free(den);
+    return ZR_ENOMEM;
+  }
+}
+
+extern "C" zr_status zr_thiele_slices(uint64_t p, uint32_t T, uint32_t nk, const uint64_t* d_X, const uint64_t* d_F,
+                                      uint64_t* d_A, uint64_t* d_B, int32_t* d_degA, int32_t* d_degB,
+                                      int32_t* d_status, hipStream_t stream) {
+  if (T == 0) return ZR_OK;
+  if (p < 3 || p >= ((uint64_t)1 << 63) || nk == 0 || !d_X || !d_F || !d_A || !d_B || !d_degA || !d_degB ||
+      !d_status)
+    return ZR_EINVAL;
+  if (!zr::is_prime_u64(p)) return ZR_ENOTPRIME;
+  try {
+    const zr_mod M = zr_mod_make(p);
+    zr::DevArena A(stream);  // blocks return to a cache ordered on `stream`: no synchronisation
+    const size_t sw = zr::thiele_scratch_words(T, nk);
+    uint64_t* scr = sw ? A.alloc<uint64_t>(sw) : nullptr;
+    check(zr::thiele_slices(M, T, nk, d_X, d_F, d_A, d_B, d_degA, d_degB, d_status, scr, stream));
+    return ZR_OK;
+  } catch (const zr::Error& e) {
+    return (zr_status)e.code;
+  } catch (const std::bad_alloc&) {
     return ZR_ENOMEM;
   }
 }

@@ -144,26 +144,276 @@ __global__ void k_thiele(zr_mod M, uint32_t T, uint32_t nk, const uint64_t* __re
   if (i < T) thiele_body(M, T, nk, X, F, A, B, degA, degB, st, scratch, i);
 }
 
-// Slices of many reconstructions in one launch: block b belongs to job
-// seg(b) (largest s with prefix[s] <= b), 64 slices per block.
-__global__ void k_thiele_batch(zr_mod M, uint32_t n, const uint32_t* __restrict__ prefix,
-                               const ThieleJob* __restrict__ jobs) {
+// ----------------------------------------------------------------------------
+// Thiele, one wavefront per slice (nk <= 64 KPL - 1).  The same continued
+// fraction as thiele_body, computed without per-step inverses: an inverse
+// difference is carried as a fraction N/D,
+//     phi_{m+1}(x_j) = (x_j - x_m) D_j D_m / (N_j D_m - N_m D_j),
+// starting from (f_j, 1).  Every D that is used is nonzero (a zero one is the
+// vanishing denominator that ends the recursion), so replacing b_s by N_s/D_s
+// and clearing the D's scales the confirmation fraction P/Q and the
+// polynomials (A, B) by nonzero constants: no zero test and no ratio changes,
+// and the final normalisation of B removes the constant.  One inverse remains.
+//   1. all recursion steps m = 0..nk-2 at once over the lanes (lane-held
+//      index j = 64 k + lane), up to the first step with a zero denominator;
+//   2. the confirmation test of every candidate m in parallel (lane-held m),
+//      one uniform loop over s = mlast-1..0 with b_s broadcast from its lane;
+//   3. the first confirmed m -> (A, B), lane-held coefficient index r.
+// ----------------------------------------------------------------------------
+constexpr int kThWaves = 4;      // slices (wavefronts) per workgroup
+constexpr int kThMaxKpl = 8;     // values per lane: nk <= 511
+
+// v from lane `src` (uniform) of the wavefront
+__device__ __forceinline__ uint64_t bcast(uint64_t v, uint32_t src) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, (int)src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)src);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Element idx (uniform) of the lane-held array v.  Each lane offers the entry
+// it holds at idx, if any, and the owner lane's offer is broadcast; the group
+// index stays a compile-time constant, so v is never indexed at run time.
+template <int KPL>
+__device__ __forceinline__ uint64_t held(const uint64_t (&v)[KPL], uint32_t idx, uint32_t lane) {
+  uint64_t mine = 0;
+#pragma unroll
+  for (int k = 0; k < KPL; ++k)
+    if (64 * k + lane == idx) mine = v[k];
+  return bcast(mine, idx & 63);
+}
+
+template <int KPL>
+__device__ void thiele_wave(const zr_mod& M, uint32_t T, uint32_t nk, const uint64_t* __restrict__ X,
+                            const uint64_t* __restrict__ F, uint64_t* __restrict__ A, uint64_t* __restrict__ B,
+                            int32_t* __restrict__ degA, int32_t* __restrict__ degB, int32_t* __restrict__ st,
+                            uint32_t i) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t one = 1 % M.p;
+  auto fail = [&](int32_t code) {
+    if (lane == 0) {
+      st[i] = code;
+      degA[i] = -1;
+      degB[i] = -1;
+    }
+  };
+  if (nk < 2) {
+    fail(-5);  // no sample to confirm with
+    return;
+  }
+  uint64_t N[KPL], D[KPL], xv[KPL];
+#pragma unroll
+  for (int k = 0; k < KPL; ++k) {
+    const uint32_t j = 64 * k + lane;
+    const bool in = j < nk;
+    xv[k] = in ? X[j] : 0;
+    N[k] = in ? F[(size_t)j * T + i] : 0;
+    D[k] = one;
+  }
+  // 1. recursion steps m = 64 g + l; zstep = first step with a zero
+  //    denominator (nk: none).  Groups below g hold no index above m.
+  uint32_t zstep = nk;
+  bool stop = false;
+#pragma unroll
+  for (int g = 0; g < KPL; ++g) {
+    for (uint32_t l = 0; l < 64 && !stop; ++l) {
+      const uint32_t m = 64 * g + l;
+      if (m + 1 >= nk) {
+        stop = true;
+        break;
+      }
+      const uint64_t Nm = bcast(N[g], l), Dm = bcast(D[g], l), xm = bcast(xv[g], l);
+      bool zero = false;
+#pragma unroll
+      for (int k = g; k < KPL; ++k) {
+        const uint32_t j = 64 * k + lane;
+        if (j > m && j < nk) {
+          const uint64_t dn = zr_sub(M, zr_mul(M, N[k], Dm), zr_mul(M, Nm, D[k]));
+          N[k] = zr_mul(M, zr_mul(M, zr_sub(M, xv[k], xm), D[k]), Dm);
+          D[k] = dn;
+          zero |= dn == 0;
+        }
+      }
+      if (__ballot(zero)) {
+        zstep = m;
+        stop = true;
+      }
+    }
+  }
+  // 2. candidates m <= mlast (b_0..b_m final), confirmed at node m+1;
+  //    s = 64 g + l runs down from mlast-1, lane-held m updates while m > s
+  const uint32_t mlast = zstep < nk - 2 ? zstep : nk - 2;
+  uint64_t P[KPL], Q[KPL], xc[KPL], fc[KPL];
+  bool ok[KPL];
+#pragma unroll
+  for (int k = 0; k < KPL; ++k) {
+    const uint32_t m = 64 * k + lane;
+    ok[k] = m <= mlast;
+    P[k] = N[k];
+    Q[k] = D[k];
+    xc[k] = ok[k] ? X[m + 1] : 0;
+    fc[k] = ok[k] ? F[(size_t)(m + 1) * T + i] : 0;
+  }
+#pragma unroll
+  for (int g = KPL - 1; g >= 0; --g) {
+    if (64u * g >= mlast) continue;
+    const uint32_t top = mlast - 64u * g < 64u ? mlast - 64u * g : 64u;  // s < mlast
+    for (uint32_t l = top; l-- > 0;) {
+      const uint32_t s = 64 * g + l;
+      const uint64_t Ns = bcast(N[g], l), Ds = bcast(D[g], l), xs = bcast(xv[g], l);
+#pragma unroll
+      for (int k = g; k < KPL; ++k) {
+        const uint32_t m = 64 * k + lane;
+        if (ok[k] && m > s) {
+          if (P[k] == 0) {
+            ok[k] = false;  // a zero tail: the nested fraction divides by zero
+          } else {
+            const uint64_t u = zr_mul(M, zr_sub(M, xc[k], xs), Ds);
+            const uint64_t nP = zr_add(M, zr_mul(M, Ns, P[k]), zr_mul(M, u, Q[k]));
+            Q[k] = zr_mul(M, Ds, P[k]);
+            P[k] = nP;
+          }
+        }
+      }
+    }
+  }
+  uint32_t c = nk;
+#pragma unroll
+  for (int k = 0; k < KPL; ++k) {
+    const uint64_t hit = __ballot(ok[k] && P[k] == zr_mul(M, fc[k], Q[k]));
+    if (hit && c == nk) c = 64 * k + (uint32_t)__builtin_ctzll(hit);
+  }
+  if (c == nk) {
+    fail(zstep < nk ? -4 : -5);
+    return;
+  }
+  // 3. (A, B) <- (N_c, D_c); (A, B) <- (N_s A + (x - x_s) D_s B, D_s A) for
+  //    s = c-1..0; after c - s steps the degree is at most c - s <= c
+  uint64_t Ac[KPL], Bc[KPL];
+  {
+    const uint64_t Nc = held(N, c, lane), Dc = held(D, c, lane);
+#pragma unroll
+    for (int k = 0; k < KPL; ++k) {
+      const bool r0 = k == 0 && lane == 0;
+      Ac[k] = r0 ? Nc : 0;
+      Bc[k] = r0 ? Dc : 0;
+    }
+  }
+#pragma unroll
+  for (int g = KPL - 1; g >= 0; --g) {
+    if (64u * g >= c) continue;
+    const uint32_t top = c - 64u * g < 64u ? c - 64u * g : 64u;  // s < c
+    for (uint32_t l = top; l-- > 0;) {
+      const uint64_t Ns = bcast(N[g], l), Ds = bcast(D[g], l), xs = bcast(xv[g], l);
+      const uint64_t u = zr_mul(M, xs, Ds);
+      uint64_t Bm[KPL];  // coefficient r-1 of B
+#pragma unroll
+      for (int k = 0; k < KPL; ++k) {
+        const uint64_t up = __shfl_up(Bc[k], 1, 64);
+        const uint64_t carry = k > 0 ? bcast(Bc[k > 0 ? k - 1 : 0], 63) : 0;
+        Bm[k] = lane == 0 ? carry : up;
+      }
+#pragma unroll
+      for (int k = 0; k < KPL; ++k) {
+        if (64u * k > c) continue;  // coefficients above the final degree stay 0
+        const uint64_t a =
+            zr_add(M, zr_sub(M, zr_mul(M, Ns, Ac[k]), zr_mul(M, u, Bc[k])), zr_mul(M, Ds, Bm[k]));
+        Bc[k] = zr_mul(M, Ds, Ac[k]);
+        Ac[k] = a;
+      }
+    }
+  }
+  int32_t da = -1, db = -1, low = -1;
+#pragma unroll
+  for (int k = 0; k < KPL; ++k) {
+    const uint64_t nzA = __ballot(Ac[k] != 0), nzB = __ballot(Bc[k] != 0);
+    if (nzA) da = 64 * k + 63 - __builtin_clzll(nzA);
+    if (nzB) db = 64 * k + 63 - __builtin_clzll(nzB);
+    if (nzB && low < 0) low = 64 * k + __builtin_ctzll(nzB);
+  }
+  if (db < 0) {
+    fail(-4);
+    return;
+  }
+  const uint64_t sc = zr_inv(M, held(Bc, (uint32_t)low, lane));
+  const uint32_t cap = nk + 1;
+#pragma unroll
+  for (int k = 0; k < KPL; ++k) {
+    const uint32_t r = 64 * k + lane;
+    if (r < cap) {
+      A[(size_t)r * T + i] = zr_mul(M, Ac[k], sc);
+      B[(size_t)r * T + i] = zr_mul(M, Bc[k], sc);
+    }
+  }
+  if (lane == 0) {
+    degA[i] = da < 0 ? 0 : da;
+    degB[i] = db;
+    st[i] = 0;
+  }
+}
+
+template <int KPL>
+__global__ void __launch_bounds__(64 * kThWaves)
+    k_thiele_wave(zr_mod M, uint32_t T, uint32_t nk, const uint64_t* __restrict__ X, const uint64_t* __restrict__ F,
+                  uint64_t* __restrict__ A, uint64_t* __restrict__ B, int32_t* __restrict__ degA,
+                  int32_t* __restrict__ degB, int32_t* __restrict__ st) {
+  const uint32_t i = blockIdx.x * kThWaves + (threadIdx.x >> 6);
+  if (i < T) thiele_wave<KPL>(M, T, nk, X, F, A, B, degA, degB, st, i);
+}
+
+// block b belongs to job seg(b): the largest s with prefix[s] <= b
+__device__ __forceinline__ uint32_t thiele_job_of(uint32_t n, const uint32_t* __restrict__ prefix, uint32_t b) {
   uint32_t lo = 0, hi = n;
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
-    if (prefix[mid] <= blockIdx.x) lo = mid;
+    if (prefix[mid] <= b) lo = mid;
     else hi = mid;
   }
-  const ThieleJob& j = jobs[lo];
-  const uint32_t i = (blockIdx.x - prefix[lo]) * blockDim.x + threadIdx.x;
+  return lo;
+}
+
+// Slices of many reconstructions in one launch, kThWaves slices per block.
+template <int KPL>
+__global__ void __launch_bounds__(64 * kThWaves)
+    k_thiele_wave_batch(zr_mod M, uint32_t n, const uint32_t* __restrict__ prefix, const ThieleJob* __restrict__ jobs) {
+  const uint32_t q = thiele_job_of(n, prefix, blockIdx.x);
+  const ThieleJob& j = jobs[q];
+  const uint32_t i = (blockIdx.x - prefix[q]) * kThWaves + (threadIdx.x >> 6);
+  if (i < j.T) thiele_wave<KPL>(M, j.T, j.nk, j.X, j.F, j.A, j.B, j.degA, j.degB, j.st, i);
+}
+
+// The same with one lane per slice (any nk; uses the jobs' scratch), 64 slices per block.
+__global__ void k_thiele_batch(zr_mod M, uint32_t n, const uint32_t* __restrict__ prefix,
+                               const ThieleJob* __restrict__ jobs) {
+  const uint32_t q = thiele_job_of(n, prefix, blockIdx.x);
+  const ThieleJob& j = jobs[q];
+  const uint32_t i = (blockIdx.x - prefix[q]) * blockDim.x + threadIdx.x;
   if (i < j.T) thiele_body(M, j.T, j.nk, j.X, j.F, j.A, j.B, j.degA, j.degB, j.st, j.scratch, i);
 }
 
+static int thiele_kpl(uint32_t nk) {
+  for (int kpl = 1; kpl <= kThMaxKpl; kpl *= 2)
+    if (nk + 1 <= 64u * kpl) return kpl;
+  return 0;  // one lane per slice
+}
+
+uint32_t thiele_slices_per_block(uint32_t max_nk) { return thiele_kpl(max_nk) ? kThWaves : 64; }
+
+size_t thiele_scratch_words(uint32_t T, uint32_t nk) {
+  return thiele_kpl(nk) ? 0 : (size_t)(3 * nk + 1) * std::max<uint32_t>(T, 1);
+}
+
 hipError_t thiele_slices_batch(const zr_mod& M, uint32_t n, const uint32_t* d_prefix, uint32_t total_blocks,
-                               const ThieleJob* d_jobs, hipStream_t s) {
+                               uint32_t max_nk, const ThieleJob* d_jobs, hipStream_t s) {
   if (n == 0 || total_blocks == 0) return hipSuccess;
   TimedLaunch tl("thiele", s);
-  hipLaunchKernelGGL(k_thiele_batch, dim3(total_blocks), dim3(64), 0, s, M, n, d_prefix, d_jobs);
+  const dim3 g(total_blocks), b(64 * kThWaves);
+  switch (thiele_kpl(max_nk)) {
+    case 1: hipLaunchKernelGGL(k_thiele_wave_batch<1>, g, b, 0, s, M, n, d_prefix, d_jobs); break;
+    case 2: hipLaunchKernelGGL(k_thiele_wave_batch<2>, g, b, 0, s, M, n, d_prefix, d_jobs); break;
+    case 4: hipLaunchKernelGGL(k_thiele_wave_batch<4>, g, b, 0, s, M, n, d_prefix, d_jobs); break;
+    case 8: hipLaunchKernelGGL(k_thiele_wave_batch<8>, g, b, 0, s, M, n, d_prefix, d_jobs); break;
+    default: hipLaunchKernelGGL(k_thiele_batch, g, dim3(64), 0, s, M, n, d_prefix, d_jobs); break;
+  }
   return hipGetLastError();
 }
 
@@ -171,7 +421,17 @@ hipError_t thiele_slices(const zr_mod& M, uint32_t T, uint32_t nk, const uint64_
                          uint64_t* B, int32_t* degA, int32_t* degB, int32_t* st, uint64_t* scratch, hipStream_t s) {
   if (T == 0) return hipSuccess;
   TimedLaunch tl("thiele", s);
-  hipLaunchKernelGGL(k_thiele, dim3(cdiv(T, 64)), dim3(64), 0, s, M, T, nk, X, F, A, B, degA, degB, st, scratch);
+  const dim3 g(cdiv(T, kThWaves)), b(64 * kThWaves);
+  switch (thiele_kpl(nk)) {
+    case 1: hipLaunchKernelGGL(k_thiele_wave<1>, g, b, 0, s, M, T, nk, X, F, A, B, degA, degB, st); break;
+    case 2: hipLaunchKernelGGL(k_thiele_wave<2>, g, b, 0, s, M, T, nk, X, F, A, B, degA, degB, st); break;
+    case 4: hipLaunchKernelGGL(k_thiele_wave<4>, g, b, 0, s, M, T, nk, X, F, A, B, degA, degB, st); break;
+    case 8: hipLaunchKernelGGL(k_thiele_wave<8>, g, b, 0, s, M, T, nk, X, F, A, B, degA, degB, st); break;
+    default:
+      if (!scratch) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(k_thiele, dim3(cdiv(T, 64)), dim3(64), 0, s, M, T, nk, X, F, A, B, degA, degB, st, scratch);
+      break;
+  }
   return hipGetLastError();
 }
 

@@ -75,12 +75,15 @@ hipError_t copy_u64(uint64_t* dst, const uint64_t* src, size_t n, hipStream_t s)
 // ---- balanced path ------------------------------------------------------------
 // Per-slice Thiele reconstruction (eq. 2).  F [nk][T] samples at nodes X[0..nk),
 // outputs per slice i: A[(nk+1)][T], B[(nk+1)][T] column i, degA/degB[T], status[T].
+// scratch: thiele_scratch_words(T, nk) words (none for nk <= 511).
+size_t thiele_scratch_words(uint32_t T, uint32_t nk);
 hipError_t thiele_slices(const zr_mod& M, uint32_t T, uint32_t nk, const uint64_t* X, const uint64_t* F,
                          uint64_t* A, uint64_t* B, int32_t* degA, int32_t* degB, int32_t* st, uint64_t* scratch,
                          hipStream_t s);
 
-// Thiele for the slices of several reconstructions in one launch (64 slices per
-// block; d_prefix[n+1] holds the prefix sums of cdiv(T_j, 64)).
+// Thiele for the slices of several reconstructions in one launch:
+// thiele_slices_per_block(max nk) slices per block, d_prefix[n+1] the prefix
+// sums of cdiv(T_j, that count); job scratch as for thiele_slices.
 struct ThieleJob {
   uint32_t T, nk;
   const uint64_t* X;
@@ -92,8 +95,9 @@ struct ThieleJob {
   int32_t* st;
   uint64_t* scratch;
 };
+uint32_t thiele_slices_per_block(uint32_t max_nk);
 hipError_t thiele_slices_batch(const zr_mod& M, uint32_t n, const uint32_t* d_prefix, uint32_t total_blocks,
-                               const ThieleJob* d_jobs, hipStream_t s);
+                               uint32_t max_nk, const ThieleJob* d_jobs, hipStream_t s);
 
 // Transposed Vandermonde apply: out[i] = sum_l a_l m_l^(i+1), i = 0..T-1.
 hipError_t vapply(const zr_mod& M, uint32_t t, const uint64_t* mono, const uint64_t* a, uint32_t T, uint64_t* out,

@@ -187,7 +187,6 @@ void advance(Server& S) {
     char* dxb = xb.upload(A, s);
     size_t hwords = 0;
     std::vector<ThieleJob> tj;
-    std::vector<uint32_t> tprefix{0};
     for (size_t q = 0; q < bal.size(); ++q) {
       Bal& b = bal[q];
       Request& r = *b.r;
@@ -201,7 +200,8 @@ void advance(Server& S) {
       b.dst = b.dgB + T1;
       b.nprev = A.alloc<uint64_t>(T1);
       b.dprev = A.alloc<uint64_t>(T1);
-      uint64_t* scr = A.alloc<uint64_t>((size_t)(3 * b.nk + 1) * T1);
+      const size_t sw = thiele_scratch_words(b.T, b.nk);
+      uint64_t* scr = sw ? A.alloc<uint64_t>(sw) : nullptr;
       b.hoff = hwords;
       hwords += 3 * (size_t)T1;
       try {
@@ -212,7 +212,6 @@ void advance(Server& S) {
       }
       // the slices of every request go through one Thiele launch below
       tj.push_back(ThieleJob{b.T, b.nk, b.dX, b.F, b.cA, b.cB, b.dgA, b.dgB, b.dst, scr});
-      tprefix.push_back(tprefix.back() + (b.T + 63) / 64);
       const size_t ww = std::max(vapply_work_words(r.SN.t, b.T), vapply_work_words(r.SD.t, b.T));
       uint64_t* wk = A.alloc<uint64_t>(ww);
       check(vapply(M, r.SN.t, r.SN.mono, r.SN.coef, b.T, b.nprev, wk, ww, s));
@@ -220,10 +219,15 @@ void advance(Server& S) {
       counters().mulmods += (uint64_t)b.T * (r.SN.t + r.SD.t);
     }
     if (!tj.empty()) {
+      uint32_t max_nk = 0;
+      for (const ThieleJob& j : tj) max_nk = std::max(max_nk, j.nk);
+      const uint32_t per = thiele_slices_per_block(max_nk);
+      std::vector<uint32_t> tprefix{0};
+      for (const ThieleJob& j : tj) tprefix.push_back(tprefix.back() + (j.T + per - 1) / per);
       Blob tb;
       const size_t oj = tb.add(tj), op = tb.add(tprefix);
       char* dt = tb.upload(A, s);
-      check(thiele_slices_batch(M, (uint32_t)tj.size(), (const uint32_t*)(dt + op), tprefix.back(),
+      check(thiele_slices_batch(M, (uint32_t)tj.size(), (const uint32_t*)(dt + op), tprefix.back(), max_nk,
                                 (const ThieleJob*)(dt + oj), s));
     }
     // one read-back of every slice's degrees and status
