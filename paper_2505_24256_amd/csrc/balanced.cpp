@@ -180,7 +180,7 @@ static void reconstruct_balanced(const zr_params* params, zr_blackbox_fn bb, voi
       check(copy_u64(valsD, SD.coef, tD, s));
       check(fill_i32(dst, 0, T, s));
       check(balance_rhs(P.M, T, nk, dX, cA, cB, dgA, dgB, nprev, dprev, tN, rhoN, valsN + tN, tN, tD, rhoD,
-                        valsD + tD, tD, dst, s));
+                        valsD + tD, tD, dst, A.alloc<uint64_t>(std::max<uint32_t>(T, 1)), s));
       for (int32_t v : d2h_i32(dst, T, s))
         if (v) throw Error(ZR_EDEGEN);
       solve_stage(P, SN, valsN, (uint32_t)rhoN, s, d_status);

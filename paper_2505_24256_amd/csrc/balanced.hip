@@ -516,38 +516,54 @@ __device__ uint64_t horner_col(const zr_mod& M, const uint64_t* c, uint32_t T, u
   return v;
 }
 
-__global__ void k_balance(zr_mod M, uint32_t T, const uint64_t* __restrict__ X, const uint64_t* __restrict__ A,
-                          const uint64_t* __restrict__ B, const int32_t* __restrict__ degA,
-                          const int32_t* __restrict__ degB, const uint64_t* __restrict__ nprev,
-                          const uint64_t* __restrict__ dprev, uint32_t tN, int32_t rhoN, uint64_t* __restrict__ vN,
-                          size_t ldN, uint32_t tD, int32_t rhoD, uint64_t* __restrict__ vD, size_t ldD,
-                          int32_t* __restrict__ st) {
+// beta_i from the two values at x_0 (one lane per slice; st[i] = -4 if neither exists)
+__global__ void k_balance_beta(zr_mod M, uint32_t T, const uint64_t* __restrict__ X, const uint64_t* __restrict__ A,
+                               const uint64_t* __restrict__ B, const int32_t* __restrict__ degA,
+                               const int32_t* __restrict__ degB, const uint64_t* __restrict__ nprev,
+                               const uint64_t* __restrict__ dprev, uint64_t* __restrict__ beta,
+                               int32_t* __restrict__ st) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= T) return;
-  const int32_t da = degA[i], db = degB[i];
-  const uint64_t a0 = horner_col(M, A, T, i, da, X[0]);
-  const uint64_t b0 = horner_col(M, B, T, i, db, X[0]);
-  uint64_t beta = 0;
-  if (nprev[i] != 0 && a0 != 0) beta = zr_mul(M, nprev[i], zr_inv(M, a0));
-  else if (dprev[i] != 0 && b0 != 0) beta = zr_mul(M, dprev[i], zr_inv(M, b0));
+  const uint64_t a0 = horner_col(M, A, T, i, degA[i], X[0]);
+  const uint64_t b0 = horner_col(M, B, T, i, degB[i], X[0]);
+  uint64_t b = 0;
+  if (nprev[i] != 0 && a0 != 0) b = zr_mul(M, nprev[i], zr_inv(M, a0));
+  else if (dprev[i] != 0 && b0 != 0) b = zr_mul(M, dprev[i], zr_inv(M, b0));
   else st[i] = -4;
-  if (i < tN)
-    for (int32_t j = 1; j <= rhoN; ++j)
-      vN[(size_t)(j - 1) * ldN + i] = zr_mul(M, beta, horner_col(M, A, T, i, da, X[j]));
-  if (i < tD)
-    for (int32_t j = 1; j <= rhoD; ++j)
-      vD[(size_t)(j - 1) * ldD + i] = zr_mul(M, beta, horner_col(M, B, T, i, db, X[j]));
+  beta[i] = b;
+}
+
+// One thread per (slice i, right-hand side u): u < rhoN is beta_i A_i(x_{u+1}),
+// the rest beta_i B_i(x_{u-rhoN+1}).
+__global__ void k_balance_rhs(zr_mod M, uint32_t T, const uint64_t* __restrict__ X, const uint64_t* __restrict__ A,
+                              const uint64_t* __restrict__ B, const int32_t* __restrict__ degA,
+                              const int32_t* __restrict__ degB, const uint64_t* __restrict__ beta, uint32_t tN,
+                              int32_t rhoN, uint64_t* __restrict__ vN, size_t ldN, uint32_t tD,
+                              uint64_t* __restrict__ vD, size_t ldD) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t u = blockIdx.y;
+  if (u < (uint32_t)rhoN) {
+    if (i < tN) vN[(size_t)u * ldN + i] = zr_mul(M, beta[i], horner_col(M, A, T, i, degA[i], X[u + 1]));
+  } else {
+    const uint32_t j = u - (uint32_t)rhoN;
+    if (i < tD) vD[(size_t)j * ldD + i] = zr_mul(M, beta[i], horner_col(M, B, T, i, degB[i], X[j + 1]));
+  }
 }
 
 hipError_t balance_rhs(const zr_mod& M, uint32_t T, uint32_t nk, const uint64_t* X, const uint64_t* A,
                        const uint64_t* B, const int32_t* degA, const int32_t* degB, const uint64_t* nprev,
                        const uint64_t* dprev, uint32_t tN, int32_t rhoN, uint64_t* vN, size_t ldN, uint32_t tD,
-                       int32_t rhoD, uint64_t* vD, size_t ldD, int32_t* st, hipStream_t s) {
+                       int32_t rhoD, uint64_t* vD, size_t ldD, int32_t* st, uint64_t* beta, hipStream_t s) {
   (void)nk;
   if (T == 0) return hipSuccess;
   TimedLaunch tl("balance", s);
-  hipLaunchKernelGGL(k_balance, dim3(cdiv(T, 128)), dim3(128), 0, s, M, T, X, A, B, degA, degB, nprev, dprev, tN, rhoN,
-                     vN, ldN, tD, rhoD, vD, ldD, st);
+  hipLaunchKernelGGL(k_balance_beta, dim3(cdiv(T, 64)), dim3(64), 0, s, M, T, X, A, B, degA, degB, nprev, dprev,
+                     beta, st);
+  const uint32_t units = (uint32_t)std::max(rhoN, 0) + (uint32_t)std::max(rhoD, 0);
+  const uint32_t rows = std::max(tN, tD);
+  if (units && rows)
+    hipLaunchKernelGGL(k_balance_rhs, dim3(cdiv(rows, 64), units), dim3(64), 0, s, M, T, X, A, B, degA, degB, beta,
+                       tN, rhoN, vN, ldN, tD, vD, ldD);
   return hipGetLastError();
 }
 

@@ -105,12 +105,13 @@ hipError_t vapply(const zr_mod& M, uint32_t t, const uint64_t* mono, const uint6
 size_t vapply_work_words(uint32_t t, uint32_t T);
 
 // Balanced right-hand sides: beta_i from N_{k-1}(y^i)/A_i(x_0) (fallback
-// D_{k-1}(y^i)/B_i(x_0)), then vN[j][i] = beta_i A_i(x_{j+1}) (j < rhoN, i < tN) and
-// vD[j][i] = beta_i B_i(x_{j+1}) (j < rhoD, i < tD).  st[i] |= 4 if no beta exists.
+// D_{k-1}(y^i)/B_i(x_0)) into beta[T], then vN[j][i] = beta_i A_i(x_{j+1})
+// (j < rhoN, i < tN) and vD[j][i] = beta_i B_i(x_{j+1}) (j < rhoD, i < tD).
+// st[i] = -4 if no beta exists.  tN, tD <= T.
 hipError_t balance_rhs(const zr_mod& M, uint32_t T, uint32_t nk, const uint64_t* X, const uint64_t* A,
                        const uint64_t* B, const int32_t* degA, const int32_t* degB, const uint64_t* nprev,
                        const uint64_t* dprev, uint32_t tN, int32_t rhoN, uint64_t* vN, size_t ldN, uint32_t tD,
-                       int32_t rhoD, uint64_t* vD, size_t ldD, int32_t* st, hipStream_t s);
+                       int32_t rhoD, uint64_t* vD, size_t ldD, int32_t* st, uint64_t* beta, hipStream_t s);
 
 // *out = code when any of st[0..T) is nonzero (out left alone otherwise).
 hipError_t fold_status(const int32_t* st, uint32_t T, int32_t* out, int32_t code, hipStream_t s);

@@ -278,7 +278,7 @@ void advance(Server& S) {
     check(copy_u64(valsD, r.SD.coef, tD, s));
     check(fill_i32(b.dst, 0, T1, s));
     check(balance_rhs(M, b.T, b.nk, b.dX, b.cA, b.cB, b.dgA, b.dgB, b.nprev, b.dprev, tN, b.rhoN, valsN + tN, tN, tD,
-                      b.rhoD, valsD + tD, tD, b.dst, s));
+                      b.rhoD, valsD + tD, tD, b.dst, A.alloc<uint64_t>(T1), s));
     check(fold_status(b.dst, b.T, r.d_status, ZR_EDEGEN, s));
     sj.push_back(SolveJob{tN, (uint32_t)b.rhoN, r.SN.mono, valsN + tN, r.d_status});
     sj.push_back(SolveJob{tD, (uint32_t)b.rhoD, r.SD.mono, valsD + tD, r.d_status});
