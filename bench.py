@@ -278,6 +278,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-slots", type=int, default=256)
     ap.add_argument("--serve-budget-gib", type=int, default=16)
+    ap.add_argument("--solve-variant", default="waves", choices=["waves", "producer_consumer", "mfma"],
+                    help="dot-product pass of the one-system solve")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; the reconstruction of independent instances would "
@@ -291,6 +293,7 @@ def main():
     import paper_2505_24256_amd as zr
     import synth
     zr.lib()  # raises if the HIP library is missing
+    zr.solve_variant(args.solve_variant)
 
     if args.microbench:
         print(json.dumps({"microbench": microbench(zr)}), flush=True)

@@ -162,6 +162,20 @@ zr_status zr_thiele_slices(uint64_t p, uint32_t T, uint32_t nk, const uint64_t* 
                            uint64_t* d_A, uint64_t* d_B, int32_t* d_degA, int32_t* d_degB, int32_t* d_status,
                            hipStream_t stream);
 
+/* One transposed Vandermonde system (§1, §2.2) through the one-system solve
+ * of the plain reconstruction: master polynomial, synthetic-division dot
+ * products (the pass chosen by zr_solve_variant), Horner and scaling.  Solves
+ *      sum_l a_l * m_l^i = v_i,   i = 1..t
+ * for each of R right-hand sides.
+ *   d_mono   device [t], distinct nonzero values < p
+ *   d_rhs    device [R][t]: v_i of right-hand side j at [j][i-1]
+ *   d_out    device [R][t]: a_l of right-hand side j at [j][l]; may equal d_rhs
+ *   d_status device int32: ZR_OK, or ZR_ESINGULAR when two m_l coincide or
+ *            one is 0 (d_out then unspecified)
+ * Asynchronous on `stream`; argument errors return at once. */
+zr_status zr_vandermonde_solve(uint64_t p, uint32_t t, uint32_t R, const uint64_t* d_mono, const uint64_t* d_rhs,
+                               uint64_t* d_out, int32_t* d_status, hipStream_t stream);
+
 /* Batched transposed Vandermonde solve (the O(t^2) step of §1 and §2.2, many
  * systems and right-hand sides at once).  System s has t_s unknowns and R_s
  * right-hand sides; for each right-hand side j it solves
@@ -196,11 +210,14 @@ zr_status vandermonde_solve_batch(size_t nsys, uint64_t p, const uint64_t* d_sys
 zr_status zippel_reconstruct_batch(uint32_t n, const zr_params* params, zr_blackbox_fn bb, void* const* ctx,
                                    hipStream_t stream, zr_poly* out, int32_t* status);
 
-/* Dot-product pass of the one-system solve when the right-hand sides span
- * several tiles: 0 (default) one wave per tile, each running the synthetic
- * division chain; 1 a producer wave runs the chain once per row block and
- * publishes it through LDS to one consumer wave per tile.  Same results. */
-void zr_solve_variant(int producer_consumer);
+/* Dot-product pass of the one-system solve (§2.2, the O(t^2 R) sums):
+ * 0 (default) one wave per tile of right-hand sides, each running the
+ * synthetic division chain with carry-free 64-bit multiply-accumulates;
+ * 1 a producer wave runs the chain once per row block and publishes it through
+ * LDS to one consumer wave per tile; 2 the sums as exact int8 matrix products
+ * on the matrix cores (signed base-256 digits of both factors, int32
+ * accumulation).  Other values select 0.  Same results for all. */
+void zr_solve_variant(int variant);
 
 /* Graph mode of the batched paths (zippel_reconstruct_batch, the server,
  * vandermonde_solve_batch): with on != 0 each stage's device-side solve

@@ -29,6 +29,7 @@ EXPORTS = [
     "zr_microbench", "zippel_reconstruct_batch", "zr_autotune", "zr_tuning_get", "zr_tuning_set",
     "zr_server_create", "zr_server_destroy", "zr_server_submit", "zr_server_step", "zr_server_poll",
     "zr_server_get_stats", "zr_batch_graphs", "zr_solve_variant", "zr_thiele_slices",
+    "zr_vandermonde_solve",
 ]
 MB_KINDS = {"mad_u64_u32": 0, "mul_lo_u32": 1, "mul_hi_u32": 2, "add_u32": 3, "mac192": 4, "shoup": 5, "copy": 6}
 
@@ -108,6 +109,7 @@ def lib():
                                                   ctypes.POINTER(ZrPoly)]
         L.vandermonde_solve_batch.argtypes = [sz, u64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.zr_thiele_slices.argtypes = [u64, u32, u32, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.zr_vandermonde_solve.argtypes = [u64, u32, u32, vp, vp, vp, vp, vp]
         L.zippel_reconstruct_batch.argtypes = [u32, ctypes.POINTER(ZrParams), vp, vp, vp, ctypes.POINTER(ZrPoly),
                                                vp]
         L.zr_autotune.argtypes = [u64, vp, ctypes.POINTER(ZrBandChoice)]
@@ -393,9 +395,16 @@ def autotune(p: int, stream=None):
     return [(t.packed, t.min_chunk) for t in tab]
 
 
-def solve_variant(producer_consumer: bool):
-    """Select the dot-product pass of the one-system solve (zr_solve_variant)."""
-    lib().zr_solve_variant(1 if producer_consumer else 0)
+SOLVE_VARIANTS = {"waves": 0, "producer_consumer": 1, "mfma": 2}
+
+
+def solve_variant(variant):
+    """Select the dot-product pass of the one-system solve (zr_solve_variant):
+    "waves" (default), "producer_consumer" or "mfma"; True/False are the
+    producer/consumer form and the default."""
+    if isinstance(variant, bool):
+        variant = "producer_consumer" if variant else "waves"
+    lib().zr_solve_variant(SOLVE_VARIANTS[variant])
 
 
 def batch_graphs(on: bool):
@@ -524,6 +533,28 @@ def vandermonde_solve_batch(p: int, systems: List[Tuple[np.ndarray, np.ndarray]]
     out = d_out.cpu().numpy().view(np.uint64)
     res = [out[int(rhs_off[i]):int(rhs_off[i + 1])].reshape(int(R[i]), int(t[i])) for i in range(nsys)]
     return res, d_status.cpu().numpy()[:nsys]
+
+
+def vandermonde_solve(p: int, m, rhs, stream=None):
+    """One system sum_l a_l m_l^i = v_i (i = 1..t) through the one-system solve
+    (zr_vandermonde_solve): m [t], rhs [R][t].  Returns (a [R][t], status)."""
+    import torch
+    m = _u64(m)
+    t = len(m)
+    rhs = _u64(rhs).reshape(-1, t) if t else np.zeros((0, 0), np.uint64)
+    R = rhs.shape[0]
+    dev = torch.device("cuda")
+    d_m = torch.from_numpy(np.concatenate([m, np.zeros(1, np.uint64)]).view(np.int64)).to(dev)
+    d_r = torch.from_numpy(np.concatenate([rhs.reshape(-1), np.zeros(1, np.uint64)]).view(np.int64)).to(dev)
+    d_o = torch.zeros_like(d_r)
+    d_s = torch.zeros(1, dtype=torch.int32, device=dev)
+    st = lib().zr_vandermonde_solve(p, t, R, d_m.data_ptr(), d_r.data_ptr(), d_o.data_ptr(), d_s.data_ptr(),
+                                    _stream(stream))
+    if st != ZR_OK:
+        raise ZippelError(st, "zr_vandermonde_solve")
+    torch.cuda.synchronize()
+    out = d_o.cpu().numpy().view(np.uint64)[:R * t].reshape(R, t)
+    return out, int(d_s.cpu().item())
 
 
 def thiele_slices(p: int, x, f, stream=None):

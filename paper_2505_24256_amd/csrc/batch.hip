@@ -727,6 +727,7 @@ void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs_in, hipStr
     b.a.t = P.t;
     b.a.L = P.L;
     b.a.S = P.S;
+    b.a.Sd = P.S;
     b.a.R = P.R;
     b.a.ldv = P.ldv;
     b.a.mono = jobs[i].mono;

@@ -31,10 +31,12 @@ namespace zr {
 static uint32_t dots_waves_per_cu(uint32_t RT);
 static uint32_t dots_pc_blocks_per_cu(uint32_t RT, uint32_t ntile);
 
-// Variant of the dot-product pass for several tiles: one wave per tile (the
-// default), or the producer/consumer form (zr_solve_variant(1)).
-static std::atomic<int> g_dots_pc{0};
-static bool dots_pc_enabled() { return g_dots_pc.load() != 0; }
+// Variant of the dot-product pass: one wave per tile (0, the default), the
+// producer/consumer form (1) or the int8 matrix-core form (2); see
+// zr_solve_variant.
+static std::atomic<int> g_dots_variant{0};
+static bool dots_pc_enabled() { return g_dots_variant.load() == 1; }
+static bool dots_mf_enabled() { return g_dots_variant.load() == 2; }
 
 // Widest tile of the one-wave-per-tile pass: 16 right-hand sides keep two
 // waves per SIMD (20 would drop to one).
@@ -44,6 +46,28 @@ VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
   VsolvePlan P;
   P.t = t;
   P.R = R;
+  P.mf = 0;
+  P.tp = 0;
+  if (R > 0 && dots_mf_enabled()) {
+    // int8 matrix-core pass: waves of 16 rows x four chunks x up to 16
+    // right-hand sides; about four rounds of one wave per SIMD, chunks of at
+    // least 64 steps (four K-blocks) and at most kMfMaxL
+    P.mf = 1;
+    P.pc = 0;
+    P.ntile = cdiv(R, 2 * kMfMaxNT);
+    P.RT = cdiv(R, P.ntile);
+    P.ldv = 0;
+    P.tp = ((t + 15) & ~15u) + 16;  // 16 zero bytes after every plane
+    const uint32_t rblocks = std::max<uint32_t>(1, cdiv(t, kMfRows));
+    const uint32_t slots = std::max<uint32_t>(1, num_cus) * 4;
+    const uint32_t G = std::max<uint32_t>(1, cdiv(4ull * slots, (uint64_t)rblocks * P.ntile));  // work items per row block and tile
+    uint32_t L = std::max<uint32_t>(std::min<uint32_t>(64, P.tp), (cdiv(t, 4 * kMfCh * G) + 15) & ~15u);
+    L = std::min<uint32_t>(L, kMfMaxL);
+    P.L = L;
+    P.S = std::max<uint32_t>(1, cdiv(t, L));
+    P.Sd = cdiv(P.S, 4 * kMfCh);
+    return P;
+  }
   const uint32_t row_blocks = std::max<uint32_t>(1, cdiv(t, 64));
   // Above kPcMinR right-hand sides the chain runs once per row block in a
   // producer wave (k_vs_dots_pc) and consumer waves take tiles of at most
@@ -69,14 +93,30 @@ VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
   S = std::min<uint32_t>(S, 256);
   P.L = std::max<uint32_t>(1, cdiv(t, S));
   P.S = std::max<uint32_t>(1, cdiv(t, P.L));
+  P.Sd = P.S;
   return P;
 }
 
-// workspace layout (64-bit words): VT [ntile][t][ldv/2] | mono_p [t] | Bc [S][t] |
-//                   qstart [S][t] | mL [t] | spart [S][R][t] | hpart [S][t] | winv [2t]
+// workspace layout (64-bit words): right-hand sides (VT [ntile][t][ldv/2], or
+//                   the digit planes [R][8][tp] bytes) | mono_p [t] | Bc [S][t] |
+//                   qstart [S][t] | mL [t] | spart [Sd][R][t] | hpart [S][t] | winv [2t]
+static size_t vsolve_rhs_words(const VsolvePlan& P) {
+  return P.mf ? (size_t)P.R * P.tp : (size_t)P.ntile * P.t * (P.ldv / 2);
+}
+
 size_t vsolve_workspace_words(const VsolvePlan& P) {
   const size_t t = P.t, S = P.S;
-  return P.ntile * t * (P.ldv / 2) + t + 2 * S * t + t + S * (size_t)P.R * t + S * t + 2 * t + 64;
+  return vsolve_rhs_words(P) + t + 2 * S * t + t + P.Sd * (size_t)P.R * t + S * t + 2 * t + 64;
+}
+
+// Digit planes of the right-hand sides and Shoup constants of the monomials.
+__global__ void k_pack_digits(uint32_t t, uint32_t tp, uint32_t R, const uint64_t* __restrict__ rhs, size_t ld_rhs,
+                              uint32_t* __restrict__ Dg, const uint64_t* __restrict__ mono,
+                              uint64_t* __restrict__ mono_p, zr_mod M) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t per = tp / 4;
+  if (idx < (size_t)R * per) pack_digits_body(t, tp, M.p, (uint32_t)(idx / per), (uint32_t)(idx % per), rhs, ld_rhs, Dg);
+  if (idx < t) mono_p[idx] = zr_shoup_pre(M, mono[idx]);
 }
 
 // Packed right-hand sides [ntile][t][ldv] and Shoup constants of the monomials.
@@ -112,6 +152,12 @@ __global__ void __launch_bounds__(64 * (1 + kPcMaxTiles)) k_vs_dots_pc(VsArgs a,
   vs_dots_pc_body<RT>(a, blockIdx.x, blockIdx.y, ntile, qbuf);
 }
 
+template <int NT>
+__global__ void __launch_bounds__(64) k_vs_mfma(VsArgs a, const uint32_t* __restrict__ Dg, uint32_t tp, uint32_t RT) {
+  if (blockIdx.z == 0) vs_mfma_body<NT, true>(a, Dg, tp, RT, blockIdx.x, blockIdx.y, 0);
+  else vs_mfma_body<NT, false>(a, Dg, tp, RT, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 __global__ void k_vs_delta(VsArgs a, const uint64_t* __restrict__ mLv, uint64_t* __restrict__ winv,
                            int32_t* __restrict__ status) {
   const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
@@ -135,6 +181,13 @@ static DotsKernel dots_kernel(uint32_t RT) {
       dots_ptr<12>(), dots_ptr<13>(), dots_ptr<14>(), dots_ptr<15>(), dots_ptr<16>(), dots_ptr<17>(),
       dots_ptr<18>(), dots_ptr<19>(), dots_ptr<20>()};
   return RT >= 1 && RT <= kMaxRT ? table[RT] : nullptr;
+}
+
+typedef void (*MfKernel)(VsArgs, const uint32_t*, uint32_t, uint32_t);
+static MfKernel mf_kernel(uint32_t NT) {
+  static const MfKernel table[kMfMaxNT + 1] = {nullptr,      k_vs_mfma<1>, k_vs_mfma<2>, k_vs_mfma<3>, k_vs_mfma<4>,
+                                               k_vs_mfma<5>, k_vs_mfma<6>, k_vs_mfma<7>, k_vs_mfma<8>};
+  return NT >= 1 && NT <= kMfMaxNT ? table[NT] : nullptr;
 }
 
 typedef void (*DotsPcKernel)(VsArgs, uint32_t);
@@ -179,17 +232,18 @@ hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, co
   if (P.t == 0) return hipSuccess;
   const size_t t = P.t, S = P.S;
   uint64_t* VT = work;
-  uint64_t* mono_p = VT + P.ntile * t * (P.ldv / 2);
+  uint64_t* mono_p = VT + vsolve_rhs_words(P);
   uint64_t* Bc = mono_p + t;
   uint64_t* qstart = Bc + S * t;
   uint64_t* mL = qstart + S * t;
   uint64_t* spart = mL + t;
-  uint64_t* hpart = spart + S * (size_t)P.R * t;
+  uint64_t* hpart = spart + P.Sd * (size_t)P.R * t;
   VsArgs a;
   a.M = M;
   a.t = P.t;
   a.L = P.L;
   a.S = P.S;
+  a.Sd = P.Sd;
   a.R = P.R;
   a.ldv = P.ldv;
   a.mono = mono;
@@ -200,7 +254,12 @@ hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, co
   a.Bc = Bc;
   a.spart = spart;
   a.hpart = hpart;
-  {
+  if (P.mf) {
+    const size_t total = std::max<size_t>((size_t)P.R * (P.tp / 4), t);
+    TimedLaunch tl("vs_pack", s);
+    hipLaunchKernelGGL(k_pack_digits, dim3(cdiv(total, 256)), dim3(256), 0, s, P.t, P.tp, P.R, rhs, ld_rhs,
+                       (uint32_t*)VT, mono, mono_p, M);
+  } else {
     const size_t total = std::max<size_t>(P.ntile * t * P.ldv, t);  // 32-bit words
     TimedLaunch tl("vs_pack", s);
     hipLaunchKernelGGL(k_pack, dim3(cdiv(total, 256)), dim3(256), 0, s, P.t, P.R, P.RT, P.ntile, P.ldv, rhs, ld_rhs,
@@ -216,7 +275,13 @@ hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, co
       hipLaunchKernelGGL(k_vs_scan, dim3(cdiv(t, 256)), dim3(256), 0, s, a, qstart, mL);
     }
   }
-  if (P.pc) {
+  if (P.mf) {
+    MfKernel km = mf_kernel(cdiv(P.RT, 2));
+    if (!km) return hipErrorInvalidValue;
+    TimedLaunch tl("vs_dots", s);
+    hipLaunchKernelGGL(km, dim3(cdiv(t, kMfRows), P.Sd, P.ntile), dim3(64), 0, s, a, (const uint32_t*)VT, P.tp,
+                       P.RT);
+  } else if (P.pc) {
     DotsPcKernel kp = dots_pc_kernel(P.RT);
     if (!kp) return hipErrorInvalidValue;
     TimedLaunch tl("vs_dots", s);
@@ -581,7 +646,7 @@ TimedLaunch::~TimedLaunch() {
 }  // namespace zr
 
 extern "C" {
-void zr_solve_variant(int producer_consumer) { zr::g_dots_pc.store(producer_consumer ? 1 : 0); }
+void zr_solve_variant(int variant) { zr::g_dots_variant.store(variant == 1 || variant == 2 ? variant : 0); }
 
 void zr_timing_enable(int on) {
   std::lock_guard<std::mutex> g(zr::g_timing.mu);

@@ -20,6 +20,9 @@ struct VsolvePlan {
   uint32_t RT, ntile;  // right-hand sides per tile (even), number of tiles
   uint32_t ldv;        // row stride (32-bit words) of one packed row of a tile
   uint32_t pc;         // 1: producer/consumer pass (chain once per row block, one wave per tile)
+  uint32_t mf;         // 1: int8 matrix-core pass (digit planes of the right-hand sides, padded length tp)
+  uint32_t tp;
+  uint32_t Sd;         // partial dot-product sums per row and right-hand side (chunk groups for mf)
 };
 VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus);
 

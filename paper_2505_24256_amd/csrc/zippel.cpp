@@ -635,6 +635,30 @@ zr_status zr_schedule(uint64_t p, uint32_t nvars, const uint32_t* nnodes, uint64
   return ZR_OK;
 }
 
+zr_status zr_vandermonde_solve(uint64_t p, uint32_t t, uint32_t R, const uint64_t* d_mono, const uint64_t* d_rhs,
+                               uint64_t* d_out, int32_t* d_status, hipStream_t stream) {
+  if (p < 3 || p >= ((uint64_t)1 << 63) || !d_status || t >= ((uint32_t)1 << 31)) return ZR_EINVAL;
+  if (t && R && (!d_mono || !d_rhs || !d_out)) return ZR_EINVAL;
+  if (!is_prime_u64(p)) return ZR_ENOTPRIME;
+  try {
+    check(fill_i32(d_status, 0, 1, stream));
+    if (t == 0 || R == 0) return ZR_OK;
+    const zr_mod M = zr_mod_make(p);
+    DevArena A(stream);
+    uint64_t* Mc = A.alloc<uint64_t>(t);
+    uint64_t* tmp = A.alloc<uint64_t>(master_tmp_words(t));
+    check(master_poly(M, t, d_mono, Mc, tmp, stream));
+    VsolvePlan plan = vsolve_plan(t, R, device_cus());
+    uint64_t* work = A.alloc<uint64_t>(vsolve_workspace_words(plan));
+    check(vsolve(M, plan, d_mono, Mc, d_rhs, t, d_out, t, work, d_status, stream));
+    return ZR_OK;
+  } catch (const Error& e) {
+    return (zr_status)e.code;
+  } catch (const std::bad_alloc&) {
+    return ZR_ENOMEM;
+  }
+}
+
 zr_status zippel_reconstruct(const zr_params* params, zr_blackbox_fn bb, void* ctx, hipStream_t stream,
                              zr_poly* out) {
   if (!out || !bb) return ZR_EINVAL;

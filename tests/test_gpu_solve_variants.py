@@ -1,0 +1,150 @@
+"""GPU parity of the one-system transposed Vandermonde solve (§1, §2.2) for
+every form of its dot-product pass: one wave per right-hand-side tile, the
+producer/consumer form and the int8 matrix-core form (signed base-256 digits,
+exact int32 sums).  Each solve goes through zr_vandermonde_solve and is
+compared with the oracle's solve bit for bit; sizes straddle the row blocks
+(16, 64), the chunk groups and the right-hand-side tiles (1, 2, 15, 16, 17,
+30, 33, 40), and the values include the edges of the field and small primes.
+Whole reconstructions with the matrix-core pass are checked against the
+oracle and the hidden polynomial."""
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = ["waves", "producer_consumer", "mfma"]
+
+
+def _note(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def zr():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2505_24256_amd as m
+    m.lib()
+    yield m
+    m.solve_variant("waves")
+
+
+def _system(p, t, R, seed):
+    rng = random.Random(f"vs/{p}/{t}/{R}/{seed}")
+    m = set()
+    while len(m) < t:
+        m.add(rng.randrange(1, p))
+    m = np.array(sorted(m, key=lambda _: rng.random()), dtype=np.uint64)
+    rhs = np.array([[rng.randrange(p) for _ in range(t)] for _ in range(R)], dtype=np.uint64).reshape(R, t)
+    return m, rhs
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("t,R", [(1, 1), (2, 3), (15, 1), (16, 2), (17, 5), (63, 10), (64, 16), (65, 17),
+                                 (200, 30), (1000, 33), (777, 40), (1100, 15), (2500, 30)])
+def test_solve_matches_oracle(zr, variant, t, R):
+    p = synth.make_prime()
+    m, rhs = _system(p, t, R, 1)
+    zr.solve_variant(variant)
+    _note(f"solve {variant} t={t} R={R}")
+    got, st = zr.vandermonde_solve(p, m, rhs)
+    assert st == 0
+    assert np.array_equal(got, oracle.vandermonde_solve(p, m, rhs))
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_solve_field_edges(zr, variant):
+    """Largest prime below 2^63, values at 0, 1, p-1, p/2 +- 1 (the digit split's turning point)."""
+    p = (1 << 63) - 25
+    h = p // 2
+    m = np.array([1, 2, p - 1, p - 2, 1 << 62, 3, h, h + 1, h + 2, h - 1] + list(range(5, 75)), dtype=np.uint64)
+    t = len(m)
+    vals = [p - 1, 0, 1, h, h + 1, h - 1]
+    rhs = np.array([[vals[(i * 7 + j) % len(vals)] for i in range(t)] for j in range(18)], dtype=np.uint64)
+    zr.solve_variant(variant)
+    got, st = zr.vandermonde_solve(p, m, rhs)
+    assert st == 0
+    assert np.array_equal(got, oracle.vandermonde_solve(p, m, rhs))
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("p", [65537, (1 << 40) + 15, 2305843009213693951])
+def test_solve_other_primes(zr, variant, p):
+    assert synth.is_prime(p)
+    m, rhs = _system(p, 300, 9, 2)
+    zr.solve_variant(variant)
+    got, st = zr.vandermonde_solve(p, m, rhs)
+    assert st == 0
+    assert np.array_equal(got, oracle.vandermonde_solve(p, m, rhs))
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_solve_singular_and_empty(zr, variant):
+    p = synth.make_prime()
+    zr.solve_variant(variant)
+    _, st = zr.vandermonde_solve(p, np.array([5, 9, 5], dtype=np.uint64), np.array([[1, 2, 3]], dtype=np.uint64))
+    assert st == zr.ZR_ESINGULAR
+    _, st = zr.vandermonde_solve(p, np.array([4, 0], dtype=np.uint64), np.array([[1, 2]], dtype=np.uint64))
+    assert st == zr.ZR_ESINGULAR
+    got, st = zr.vandermonde_solve(p, np.zeros(0, dtype=np.uint64), np.zeros((2, 0), dtype=np.uint64))
+    assert st == 0 and got.size == 0
+
+
+@pytest.mark.parametrize("t,R", [(10_000, 30), (20_000, 40)])
+def test_solve_large_sampled_rows(zr, t, R):
+    """Full-size systems (the n = 6 stage size and a larger one) with the
+    matrix-core pass: rows sampled and solved one by one by the oracle."""
+    p = synth.make_prime()
+    g = synth.SplitMix64(t + R)
+    m = g.uniform_block(1, p, t)
+    assert len(set(int(x) for x in m)) == t
+    rhs = g.uniform_block(0, p, t * R).reshape(R, t)
+    zr.solve_variant("mfma")
+    _note(f"solve mfma t={t} R={R}")
+    got, st = zr.vandermonde_solve(p, m, rhs)
+    assert st == 0
+    rng = random.Random(t)
+    rows = sorted(rng.sample(range(t), 40) + [0, 1, 15, 16, t - 1])
+    want = oracle.vandermonde_solve_rows(p, m, rhs, rows)
+    assert np.array_equal(got[:, rows], want)
+
+
+def _box(zr, hidden):
+    b = synth.BlackBox(hidden)
+    return zr.HostBlackBox(b.eval, hidden.nvars)
+
+
+def test_reconstruct_mfma_config1_every_stage(zr):
+    w = synth.config_workload(1)
+    zr.solve_variant("mfma")
+    for L in range(1, 4):
+        e, c = zr.reconstruct(w.p, w.deg, _box(zr, w.hidden), sched=w.schedule, last_stage=L)
+        oe, oc = oracle.zippel(w.p, w.deg, w.schedule, synth.BlackBox(w.hidden), last_stage=L)
+        assert np.array_equal(e, oe) and np.array_equal(c, oc)
+
+
+@pytest.mark.parametrize("nvars,deg,nterms,seed", [(4, 12, 2000, 21), (3, 40, 700, 9), (3, 30, 3000, 33)])
+def test_reconstruct_mfma_matches_oracle(zr, nvars, deg, nterms, seed):
+    w = synth.poly_workload("mf", nvars, deg, nterms, seed, 1000 + seed, nprobes=2)
+    zr.solve_variant("mfma")
+    e, c = zr.reconstruct(w.p, w.deg, _box(zr, w.hidden), sched=w.schedule)
+    oe, oc = oracle.zippel(w.p, w.deg, w.schedule, synth.BlackBox(w.hidden))
+    assert np.array_equal(e, oe) and np.array_equal(c, oc)
+    assert np.array_equal(e, w.hidden.exps) and np.array_equal(c, w.hidden.coefs)
+
+
+def test_reconstruct_mfma_config2_full(zr):
+    """n = 6, per-variable degree 30, 10^4 terms: equals the hidden polynomial."""
+    w = synth.config_workload(2)
+    zr.solve_variant("mfma")
+    _note("config2 full reconstruction, matrix-core pass")
+    e, c = zr.reconstruct(w.p, w.deg, synth.DeviceBlackBox(w.hidden, nthreads=16), sched=w.schedule)
+    assert np.array_equal(e, w.hidden.exps) and np.array_equal(c, w.hidden.coefs)
