@@ -34,12 +34,15 @@ if ROOT not in sys.path:
 CU, SIMD, LANES, CLOCK_GHZ = 256, 4, 16, 2.4
 MUL32_PEAK_TOPS = CU * SIMD * LANES * CLOCK_GHZ * 1e9 / 1e12
 MUL32_PER_MULMOD = 4
+# MI355X dense int8 matrix-core peak (no sparsity)
+INT8_PEAK_TOPS = 5000.0
+INT8_OPS_PER_PRODUCT = 2 * 64
 
 # HBM bytes per k_vs_dots launch on this workload, from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE scaled by the copy-probe calibration (0.5x read, 1.0x write); see
 # profiles/k_vs_dots_plain_n6_d30_t1e4_hbm_counters.md.  Valid only for the
 # kernel sources those counters were taken on.
-DOTS_TRAFFIC = {"sources_sha16": "814bca904f8597eb", "bytes_per_launch": 82.05e6}
+DOTS_TRAFFIC = {"sources_sha16": "814bca904f8597eb", "variant": "waves", "bytes_per_launch": 82.05e6}
 
 
 def _dots_sources_sha16() -> str:
@@ -278,7 +281,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-slots", type=int, default=256)
     ap.add_argument("--serve-budget-gib", type=int, default=16)
-    ap.add_argument("--solve-variant", default="waves", choices=["waves", "producer_consumer", "mfma"],
+    ap.add_argument("--solve-variant", default="mfma", choices=["waves", "producer_consumer", "mfma"],
                     help="dot-product pass of the one-system solve")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -343,15 +346,29 @@ def main():
     value = mulmods / elapsed
     solve_alg = cnt["solve_mulmods"] * steps          # R t^2 + 2 t (t-1) per system: what vs_dots computes
     achieved_mulmod_s = solve_alg / (ms_dots / 1e3) if ms_dots else 0.0
-    achieved = achieved_mulmod_s * MUL32_PER_MULMOD / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(MUL32_PEAK_TOPS, 3),
-                "unit": "TOP/s (32x32-bit multiplies; one 64x64-bit modular product or multiply-accumulate = 4)",
-                "frac": round(achieved / MUL32_PEAK_TOPS, 4),
-                "traffic": (DOTS_TRAFFIC["bytes_per_launch"] if _dots_sources_sha16() == DOTS_TRAFFIC["sources_sha16"]
-                            else None),
-                "traffic_unit": "bytes per launch (HBM, rocprofv3 counters, calibrated)",
-                "kernel": "k_vs_dots", "launches_per_step": n_dots // steps if steps else 0,
-                "avg_launch_ms": round(ms_dots / n_dots, 4) if n_dots else None}
+    alu = achieved_mulmod_s * MUL32_PER_MULMOD / 1e12
+    traffic = (DOTS_TRAFFIC["bytes_per_launch"]
+               if _dots_sources_sha16() == DOTS_TRAFFIC["sources_sha16"] and DOTS_TRAFFIC["variant"] == args.solve_variant
+               else None)
+    common = {"traffic": traffic, "traffic_unit": "bytes per launch (HBM, rocprofv3 counters, calibrated)",
+              "launches_per_step": n_dots // steps if steps else 0,
+              "avg_launch_ms": round(ms_dots / n_dots, 4) if n_dots else None}
+    if args.solve_variant == "mfma":
+        # the R t^2 dot products run on the int8 matrix cores: one 63x63-bit
+        # product is 64 digit products (8 x 8 signed base-256 digits), two ops each
+        dots = cnt["dot_products"] * steps
+        achieved = dots * INT8_OPS_PER_PRODUCT / (ms_dots / 1e3) / 1e12 if ms_dots else 0.0
+        roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": INT8_PEAK_TOPS,
+                    "unit": "TOP/s (int8 MFMA ops; one 64x64-bit product = 64 digit products = 128 ops)",
+                    "frac": round(achieved / INT8_PEAK_TOPS, 4), **common, "kernel": "k_vs_mfma",
+                    "alu_equivalent": {"achieved": round(alu, 3), "peak": round(MUL32_PEAK_TOPS, 3),
+                                       "frac": round(alu / MUL32_PEAK_TOPS, 4),
+                                       "unit": "TOP/s of 32x32-bit multiplies at 4 per modular product (whole solve work)"}}
+    else:
+        roofline = {"bound": "alu", "achieved": round(alu, 3), "peak": round(MUL32_PEAK_TOPS, 3),
+                    "unit": "TOP/s (32x32-bit multiplies; one 64x64-bit modular product or multiply-accumulate = 4)",
+                    "frac": round(alu / MUL32_PEAK_TOPS, 4), **common,
+                    "kernel": "k_vs_dots_pc" if args.solve_variant == "producer_consumer" else "k_vs_dots"}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -211,12 +211,12 @@ zr_status zippel_reconstruct_batch(uint32_t n, const zr_params* params, zr_black
                                    hipStream_t stream, zr_poly* out, int32_t* status);
 
 /* Dot-product pass of the one-system solve (§2.2, the O(t^2 R) sums):
- * 0 (default) one wave per tile of right-hand sides, each running the
- * synthetic division chain with carry-free 64-bit multiply-accumulates;
- * 1 a producer wave runs the chain once per row block and publishes it through
- * LDS to one consumer wave per tile; 2 the sums as exact int8 matrix products
+ * 0 one wave per tile of right-hand sides, each running the synthetic
+ * division chain with carry-free 64-bit multiply-accumulates; 1 a producer
+ * wave runs the chain once per row block and publishes it through LDS to one
+ * consumer wave per tile; 2 (default) the sums as exact int8 matrix products
  * on the matrix cores (signed base-256 digits of both factors, int32
- * accumulation).  Other values select 0.  Same results for all. */
+ * accumulation).  Other values select the default.  Same results for all. */
 void zr_solve_variant(int variant);
 
 /* Graph mode of the batched paths (zippel_reconstruct_batch, the server,
@@ -318,6 +318,7 @@ typedef struct {
   uint64_t vsolve_terms;  /* sum of t*R over all solved systems */
   uint32_t stages;
   uint64_t max_t;
+  uint64_t dot_products;  /* of which the dot products of the solves: R t^2 per system */
 } zr_counters;
 void zr_last_counters(zr_counters* out);
 

@@ -75,7 +75,7 @@ class ZrServerStats(ctypes.Structure):
 
 class ZrCounters(ctypes.Structure):
     _fields_ = [("mulmods", ctypes.c_uint64), ("solve_mulmods", ctypes.c_uint64), ("vsolve_terms", ctypes.c_uint64),
-                ("stages", ctypes.c_uint32), ("max_t", ctypes.c_uint64)]
+                ("stages", ctypes.c_uint32), ("max_t", ctypes.c_uint64), ("dot_products", ctypes.c_uint64)]
 
 
 BLACKBOX_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ZrPoints), ctypes.c_void_p,
@@ -396,14 +396,12 @@ def autotune(p: int, stream=None):
 
 
 SOLVE_VARIANTS = {"waves": 0, "producer_consumer": 1, "mfma": 2}
+DEFAULT_SOLVE_VARIANT = "mfma"
 
 
-def solve_variant(variant):
+def solve_variant(variant=DEFAULT_SOLVE_VARIANT):
     """Select the dot-product pass of the one-system solve (zr_solve_variant):
-    "waves" (default), "producer_consumer" or "mfma"; True/False are the
-    producer/consumer form and the default."""
-    if isinstance(variant, bool):
-        variant = "producer_consumer" if variant else "waves"
+    "waves", "producer_consumer" or "mfma" (the default)."""
     lib().zr_solve_variant(SOLVE_VARIANTS[variant])
 
 

@@ -31,10 +31,11 @@ namespace zr {
 static uint32_t dots_waves_per_cu(uint32_t RT);
 static uint32_t dots_pc_blocks_per_cu(uint32_t RT, uint32_t ntile);
 
-// Variant of the dot-product pass: one wave per tile (0, the default), the
-// producer/consumer form (1) or the int8 matrix-core form (2); see
-// zr_solve_variant.
-static std::atomic<int> g_dots_variant{0};
+// Variant of the dot-product pass: one wave per tile (0), the
+// producer/consumer form (1) or the int8 matrix-core form (2, the default);
+// see zr_solve_variant.
+constexpr int kDefaultDotsVariant = 2;
+static std::atomic<int> g_dots_variant{kDefaultDotsVariant};
 static bool dots_pc_enabled() { return g_dots_variant.load() == 1; }
 static bool dots_mf_enabled() { return g_dots_variant.load() == 2; }
 
@@ -152,10 +153,10 @@ __global__ void __launch_bounds__(64 * (1 + kPcMaxTiles)) k_vs_dots_pc(VsArgs a,
   vs_dots_pc_body<RT>(a, blockIdx.x, blockIdx.y, ntile, qbuf);
 }
 
-template <int NT>
+template <int NT, bool LAZY>
 __global__ void __launch_bounds__(64) k_vs_mfma(VsArgs a, const uint32_t* __restrict__ Dg, uint32_t tp, uint32_t RT) {
-  if (blockIdx.z == 0) vs_mfma_body<NT, true>(a, Dg, tp, RT, blockIdx.x, blockIdx.y, 0);
-  else vs_mfma_body<NT, false>(a, Dg, tp, RT, blockIdx.x, blockIdx.y, blockIdx.z);
+  if (blockIdx.z == 0) vs_mfma_body<NT, true, LAZY>(a, Dg, tp, RT, blockIdx.x, blockIdx.y, 0);
+  else vs_mfma_body<NT, false, LAZY>(a, Dg, tp, RT, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 __global__ void k_vs_delta(VsArgs a, const uint64_t* __restrict__ mLv, uint64_t* __restrict__ winv,
@@ -184,10 +185,13 @@ static DotsKernel dots_kernel(uint32_t RT) {
 }
 
 typedef void (*MfKernel)(VsArgs, const uint32_t*, uint32_t, uint32_t);
-static MfKernel mf_kernel(uint32_t NT) {
-  static const MfKernel table[kMfMaxNT + 1] = {nullptr,      k_vs_mfma<1>, k_vs_mfma<2>, k_vs_mfma<3>, k_vs_mfma<4>,
-                                               k_vs_mfma<5>, k_vs_mfma<6>, k_vs_mfma<7>, k_vs_mfma<8>};
-  return NT >= 1 && NT <= kMfMaxNT ? table[NT] : nullptr;
+static MfKernel mf_kernel(uint32_t NT, bool lazy) {
+  static const MfKernel table[2][kMfMaxNT + 1] = {
+      {nullptr, k_vs_mfma<1, false>, k_vs_mfma<2, false>, k_vs_mfma<3, false>, k_vs_mfma<4, false>,
+       k_vs_mfma<5, false>, k_vs_mfma<6, false>, k_vs_mfma<7, false>, k_vs_mfma<8, false>},
+      {nullptr, k_vs_mfma<1, true>, k_vs_mfma<2, true>, k_vs_mfma<3, true>, k_vs_mfma<4, true>, k_vs_mfma<5, true>,
+       k_vs_mfma<6, true>, k_vs_mfma<7, true>, k_vs_mfma<8, true>}};
+  return NT >= 1 && NT <= kMfMaxNT ? table[lazy ? 1 : 0][NT] : nullptr;
 }
 
 typedef void (*DotsPcKernel)(VsArgs, uint32_t);
@@ -276,7 +280,7 @@ hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, co
     }
   }
   if (P.mf) {
-    MfKernel km = mf_kernel(cdiv(P.RT, 2));
+    MfKernel km = mf_kernel(cdiv(P.RT, 2), M.p <= kMfLazyMaxP);
     if (!km) return hipErrorInvalidValue;
     TimedLaunch tl("vs_dots", s);
     hipLaunchKernelGGL(km, dim3(cdiv(t, kMfRows), P.Sd, P.ntile), dim3(64), 0, s, a, (const uint32_t*)VT, P.tp,
@@ -646,7 +650,9 @@ TimedLaunch::~TimedLaunch() {
 }  // namespace zr
 
 extern "C" {
-void zr_solve_variant(int variant) { zr::g_dots_variant.store(variant == 1 || variant == 2 ? variant : 0); }
+void zr_solve_variant(int variant) {
+  zr::g_dots_variant.store(variant >= 0 && variant <= 2 ? variant : zr::kDefaultDotsVariant);
+}
 
 void zr_timing_enable(int on) {
   std::lock_guard<std::mutex> g(zr::g_timing.mu);

@@ -483,28 +483,56 @@ __device__ __forceinline__ uint64_t mf_load_mr(const uint64_t* __restrict__ Mc, 
   return Mc[pos < len ? hi - 1 - pos : 0];
 }
 
-// Sixteen chain steps of one lane from position 16 kb of its chunk [lo, hi):
-// the digits of q_{l,r} for those steps (zero past the chunk's end) as the
-// eight A operands, and q (and Horner's h) advanced.  M_r of step s comes from
-// lane s of the quarter (mw, loaded by mf_load_mr).  Branch-free.
-template <bool HORNER>
-__device__ __forceinline__ void mf_chain_block(const zr_mod& M, uint64_t m, uint64_t mp, uint32_t kb, uint32_t len,
-                                               uint64_t mw, uint64_t& q, uint64_t& h, i32x4 (&A)[8]) {
-  uint32_t dlo[16], dhi[16];
+// Largest p for the lazy chain: q is kept in [0, 2p) (one conditional
+// subtraction per step instead of two) and its digits are those of q - p, in
+// (-p, p), which the eight signed base-256 digits cover for p up to this bound.
+constexpr uint64_t kMfLazyMaxP = 0x7F7F7F7F7F7F7F7Full;
+
+// Sixteen chain steps, from position 16 kb, of each of the lane's kMfCh
+// chains (chunk k of length len[k]), the chains advanced together step by
+// step so that their instructions interleave: the digits of q_{l,r} for those
+// steps (zero past a chunk's end) as the eight A operands of each chain, and
+// q (and Horner's h) advanced.  M_r of step s comes from lane s of the quarter
+// (mw[k], loaded by mf_load_mr).  Branch-free.  LAZY: q and h in [0, 2p)
+// (Shoup's product without its final correction, then one correction of the
+// sum, carry included); cmp = C - p mod 2^64.
+template <bool HORNER, bool LAZY>
+__device__ __forceinline__ void mf_chain_block(const zr_mod& M, uint64_t m, uint64_t mp, uint32_t kb,
+                                               const uint32_t (&len)[kMfCh], const uint64_t (&mw)[kMfCh],
+                                               uint64_t cmp, uint64_t (&q)[kMfCh], uint64_t (&h)[kMfCh],
+                                               i32x4 (&A)[kMfCh][8]) {
+  constexpr uint64_t C = 0x0080808080808080ull;
+  uint32_t dlo[kMfCh][16], dhi[kMfCh][16];
   auto step = [&](auto S) {
     constexpr int s = decltype(S)::value;
-    const bool on = 16 * kb + s < len;
-    const uint64_t Mr = row_bcast<s>(mw);
-    const uint64_t dq = sdigits(q, M.p);  // computed for every lane, then selected (no branch)
-    const uint64_t d = on ? dq : 0;
-    if (HORNER) {
-      const uint64_t hn = zr_add(M, zr_shoup(M, h, m, mp), q);
-      h = on ? hn : h;
+#pragma unroll
+    for (int k = 0; k < kMfCh; ++k) {
+      const bool on = 16 * kb + s < len[k];
+      const uint64_t Mr = row_bcast<s>(mw[k]);
+      // computed for every lane, then selected (no branch)
+      const uint64_t dq = LAZY ? (q[k] + cmp) ^ C : sdigits(q[k], M.p);
+      const uint64_t d = on ? dq : 0;
+      if (HORNER) {
+        uint64_t hn;
+        if (LAZY) {
+          const uint64_t r = zr_shoup_lazy(M, h[k], m, mp), u = r + q[k];
+          hn = (u < r || u >= 2 * M.p) ? u - 2 * M.p : u;
+        } else {
+          hn = zr_add(M, zr_shoup(M, h[k], m, mp), q[k]);
+        }
+        h[k] = on ? hn : h[k];
+      }
+      uint64_t qn;
+      if (LAZY) {
+        const uint64_t r = zr_shoup_lazy(M, q[k], m, mp), u = r + Mr;
+        qn = (u < r || u >= M.p) ? u - M.p : u;
+      } else {
+        qn = zr_add(M, zr_shoup(M, q[k], m, mp), Mr);
+      }
+      q[k] = on ? qn : q[k];
+      dlo[k][s] = (uint32_t)d;
+      dhi[k][s] = (uint32_t)(d >> 32);
     }
-    const uint64_t qn = zr_add(M, zr_shoup(M, q, m, mp), Mr);
-    q = on ? qn : q;
-    dlo[s] = (uint32_t)d;
-    dhi[s] = (uint32_t)(d >> 32);
   };
   step(std::integral_constant<int, 0>{});
   step(std::integral_constant<int, 1>{});
@@ -523,19 +551,21 @@ __device__ __forceinline__ void mf_chain_block(const zr_mod& M, uint64_t m, uint
   step(std::integral_constant<int, 14>{});
   step(std::integral_constant<int, 15>{});
 #pragma unroll
-  for (int w = 0; w < 4; ++w) {
-    uint32_t y0, y1, y2, y3;
-    transpose4(dlo[4 * w], dlo[4 * w + 1], dlo[4 * w + 2], dlo[4 * w + 3], y0, y1, y2, y3);
-    A[0][w] = (int32_t)y0;
-    A[1][w] = (int32_t)y1;
-    A[2][w] = (int32_t)y2;
-    A[3][w] = (int32_t)y3;
-    transpose4(dhi[4 * w], dhi[4 * w + 1], dhi[4 * w + 2], dhi[4 * w + 3], y0, y1, y2, y3);
-    A[4][w] = (int32_t)y0;
-    A[5][w] = (int32_t)y1;
-    A[6][w] = (int32_t)y2;
-    A[7][w] = (int32_t)y3;
-  }
+  for (int k = 0; k < kMfCh; ++k)
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      uint32_t y0, y1, y2, y3;
+      transpose4(dlo[k][4 * w], dlo[k][4 * w + 1], dlo[k][4 * w + 2], dlo[k][4 * w + 3], y0, y1, y2, y3);
+      A[k][0][w] = (int32_t)y0;
+      A[k][1][w] = (int32_t)y1;
+      A[k][2][w] = (int32_t)y2;
+      A[k][3][w] = (int32_t)y3;
+      transpose4(dhi[k][4 * w], dhi[k][4 * w + 1], dhi[k][4 * w + 2], dhi[k][4 * w + 3], y0, y1, y2, y3);
+      A[k][4][w] = (int32_t)y0;
+      A[k][5][w] = (int32_t)y1;
+      A[k][6][w] = (int32_t)y2;
+      A[k][7][w] = (int32_t)y3;
+    }
 }
 
 // Work item (row block rb, group pair gg, tile): rows 16 rb .. 16 rb + 15,
@@ -543,7 +573,7 @@ __device__ __forceinline__ void mf_chain_block(const zr_mod& M, uint64_t m, uint
 // one per quarter of the wave), right-hand sides tile*RT .. tile*RT + RT - 1
 // (RT <= 2 NT).  Writes spart[gg][j][l] and, with HORNER (tile 0), hpart[c][l]
 // of its chunks.
-template <int NT, bool HORNER>
+template <int NT, bool HORNER, bool LAZY>
 __device__ __forceinline__ void vs_mfma_body(const VsArgs& a, const uint32_t* __restrict__ Dg, uint32_t tp,
                                              uint32_t RT, uint32_t rb, uint32_t gg, uint32_t tile) {
   const uint32_t lane = threadIdx.x & 63;
@@ -600,6 +630,7 @@ __device__ __forceinline__ void vs_mfma_body(const VsArgs& a, const uint32_t* __
       }
     }
   };
+  const uint64_t cmp = 0x0080808080808080ull - M.p;
   // Pipeline: block kb's products at the top of iteration kb, then the loads
   // of block kb+1's right-hand sides (consumed one iteration later) and the
   // chains of block kb+1, whose master coefficients were loaded an iteration
@@ -611,8 +642,7 @@ __device__ __forceinline__ void vs_mfma_body(const VsArgs& a, const uint32_t* __
   load_b(0, B);
 #pragma unroll
   for (int k = 0; k < kMfCh; ++k) mwn[k] = mf_load_mr(a.Mc, 1, row, hi[k], len[k]);
-#pragma unroll
-  for (int k = 0; k < kMfCh; ++k) mf_chain_block<HORNER>(M, m, mp, 0, len[k], mw[k], q[k], h[k], A[k]);
+  mf_chain_block<HORNER, LAZY>(M, m, mp, 0, len, mw, cmp, q, h, A);
 #pragma unroll
   for (int k = 0; k < kMfCh; ++k) mw[k] = mwn[k];
   for (uint32_t kb = 0; kb < nkb; ++kb) {
@@ -628,8 +658,7 @@ __device__ __forceinline__ void vs_mfma_body(const VsArgs& a, const uint32_t* __
     for (int k = 0; k < kMfCh; ++k) mwn[k] = mf_load_mr(a.Mc, kb + 2, row, hi[k], len[k]);
     // keep the loads ahead of the chains
     __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int k = 0; k < kMfCh; ++k) mf_chain_block<HORNER>(M, m, mp, kb + 1, len[k], mw[k], q[k], h[k], A[k]);
+    mf_chain_block<HORNER, LAZY>(M, m, mp, kb + 1, len, mw, cmp, q, h, A);
 #pragma unroll
     for (int k = 0; k < kMfCh; ++k) mw[k] = mwn[k];
   }
@@ -657,7 +686,7 @@ __device__ __forceinline__ void vs_mfma_body(const VsArgs& a, const uint32_t* __
   if (HORNER && l0 < a.t) {
 #pragma unroll
     for (int k = 0; k < kMfCh; ++k)
-      if (has[k]) a.hpart[(size_t)c[k] * a.t + l0] = h[k];
+      if (has[k]) a.hpart[(size_t)c[k] * a.t + l0] = (LAZY && h[k] >= M.p) ? h[k] - M.p : h[k];
   }
 }
 

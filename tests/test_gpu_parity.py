@@ -238,14 +238,14 @@ def test_balanced_enorm(zr):
 
 def test_zippel_producer_consumer_pass(zr):
     """The producer/consumer dot-product pass gives the same result as the
-    default one (systems with 12 and 30 right-hand sides)."""
+    default (matrix-core) one (systems with 12 and 30 right-hand sides)."""
     for nvars, deg, nterms, seed in ((4, 12, 2000, 21), (3, 30, 3000, 33)):
         w = synth.poly_workload("pc", nvars, deg, nterms, seed, 1000 + seed, nprobes=2)
         base = zr.reconstruct(w.p, w.deg, _box(zr, w.hidden), sched=w.schedule)
         try:
-            zr.solve_variant(True)
+            zr.solve_variant("producer_consumer")
             pc = zr.reconstruct(w.p, w.deg, _box(zr, w.hidden), sched=w.schedule)
         finally:
-            zr.solve_variant(False)
+            zr.solve_variant()
         assert np.array_equal(base[0], pc[0]) and np.array_equal(base[1], pc[1])
         assert np.array_equal(pc[0], w.hidden.exps) and np.array_equal(pc[1], w.hidden.coefs)

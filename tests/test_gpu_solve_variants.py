@@ -34,7 +34,7 @@ def zr():
     import paper_2505_24256_amd as m
     m.lib()
     yield m
-    m.solve_variant("waves")
+    m.solve_variant()
 
 
 def _system(p, t, R, seed):
