@@ -38,11 +38,11 @@ MUL32_PER_MULMOD = 4
 INT8_PEAK_TOPS = 5000.0
 INT8_OPS_PER_PRODUCT = 2 * 64
 
-# HBM bytes per k_vs_dots launch on this workload, from rocprofv3 FETCH_SIZE /
-# WRITE_SIZE scaled by the copy-probe calibration (0.5x read, 1.0x write); see
-# profiles/k_vs_dots_plain_n6_d30_t1e4_hbm_counters.md.  Valid only for the
-# kernel sources those counters were taken on.
-DOTS_TRAFFIC = {"sources_sha16": "814bca904f8597eb", "variant": "waves", "bytes_per_launch": 82.05e6}
+# HBM bytes per launch of the dominant solve kernel on this workload, from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by the copy-probe calibration (0.5x
+# read, 1.0x write); see profiles/k_vs_mfma_n6_d30_t1e4_hbm_counters.md.  Valid
+# only for the kernel sources and solve variant those counters were taken on.
+DOTS_TRAFFIC = {"sources_sha16": "7944191bda489b83", "variant": "mfma", "bytes_per_launch": 53.43e6}
 
 
 def _dots_sources_sha16() -> str:
