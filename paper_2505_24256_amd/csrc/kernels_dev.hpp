@@ -495,8 +495,9 @@ constexpr uint64_t kMfLazyMaxP = 0x7F7F7F7F7F7F7F7Full;
 // q (and Horner's h) advanced.  M_r of step s comes from lane s of the quarter
 // (mw[k], loaded by mf_load_mr).  Branch-free.  LAZY: q and h in [0, 2p)
 // (Shoup's product without its final correction, then one correction of the
-// sum, carry included); cmp = C - p mod 2^64.
-template <bool HORNER, bool LAZY>
+// sum, carry included); cmp = C - p mod 2^64.  FULL: no step of the block
+// lies past a chunk's end (no selects).
+template <bool HORNER, bool LAZY, bool FULL>
 __device__ __forceinline__ void mf_chain_block(const zr_mod& M, uint64_t m, uint64_t mp, uint32_t kb,
                                                const uint32_t (&len)[kMfCh], const uint64_t (&mw)[kMfCh],
                                                uint64_t cmp, uint64_t (&q)[kMfCh], uint64_t (&h)[kMfCh],
@@ -507,7 +508,7 @@ __device__ __forceinline__ void mf_chain_block(const zr_mod& M, uint64_t m, uint
     constexpr int s = decltype(S)::value;
 #pragma unroll
     for (int k = 0; k < kMfCh; ++k) {
-      const bool on = 16 * kb + s < len[k];
+      const bool on = FULL || 16 * kb + s < len[k];  // FULL: the block lies inside every chunk
       const uint64_t Mr = row_bcast<s>(mw[k]);
       // computed for every lane, then selected (no branch)
       const uint64_t dq = LAZY ? (q[k] + cmp) ^ C : sdigits(q[k], M.p);
@@ -599,6 +600,13 @@ __device__ __forceinline__ void vs_mfma_body(const VsArgs& a, const uint32_t* __
   uint32_t lo0, hi0;
   chunk_range(a.t, a.L, 4 * kMfCh * gg, lo0, hi0);  // the first chunk of the item is its longest
   const uint32_t nkb = (hi0 - lo0 + 15) / 16;
+  // K-blocks that lie inside every chunk of the item (the same on all lanes)
+  uint32_t nfull = nkb;
+  for (uint32_t cc = 4 * kMfCh * gg; cc < 4 * kMfCh * (gg + 1); ++cc) {
+    uint32_t clo = 0, chi = 0;
+    if (cc < a.S) chunk_range(a.t, a.L, cc, clo, chi);
+    nfull = std::min<uint32_t>(nfull, (chi - clo) / 16);
+  }
   i32x4 acc[8][NT];
 #pragma unroll
   for (int x = 0; x < 8; ++x)
@@ -642,7 +650,8 @@ __device__ __forceinline__ void vs_mfma_body(const VsArgs& a, const uint32_t* __
   load_b(0, B);
 #pragma unroll
   for (int k = 0; k < kMfCh; ++k) mwn[k] = mf_load_mr(a.Mc, 1, row, hi[k], len[k]);
-  mf_chain_block<HORNER, LAZY>(M, m, mp, 0, len, mw, cmp, q, h, A);
+  if (nfull > 0) mf_chain_block<HORNER, LAZY, true>(M, m, mp, 0, len, mw, cmp, q, h, A);
+  else mf_chain_block<HORNER, LAZY, false>(M, m, mp, 0, len, mw, cmp, q, h, A);
 #pragma unroll
   for (int k = 0; k < kMfCh; ++k) mw[k] = mwn[k];
   for (uint32_t kb = 0; kb < nkb; ++kb) {
@@ -658,7 +667,8 @@ __device__ __forceinline__ void vs_mfma_body(const VsArgs& a, const uint32_t* __
     for (int k = 0; k < kMfCh; ++k) mwn[k] = mf_load_mr(a.Mc, kb + 2, row, hi[k], len[k]);
     // keep the loads ahead of the chains
     __builtin_amdgcn_sched_barrier(0);
-    mf_chain_block<HORNER, LAZY>(M, m, mp, kb + 1, len, mw, cmp, q, h, A);
+    if (kb + 1 < nfull) mf_chain_block<HORNER, LAZY, true>(M, m, mp, kb + 1, len, mw, cmp, q, h, A);
+    else mf_chain_block<HORNER, LAZY, false>(M, m, mp, kb + 1, len, mw, cmp, q, h, A);
 #pragma unroll
     for (int k = 0; k < kMfCh; ++k) mw[k] = mwn[k];
   }
