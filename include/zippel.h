@@ -188,7 +188,7 @@ zr_status zr_vandermonde_solve(uint64_t p, uint32_t t, uint32_t R, const uint64_
  *   d_rhs_off [nsys+1] device, prefix sums of R_s * t_s; h_rhs_off the host copy
  *   d_rhs     device, system s at d_rhs + rhs_off[s], laid out [R_s][t_s]: v_i at [j][i-1]
  *   d_out     device, same layout as d_rhs: a_l at [j][l]  (may not alias d_rhs)
- *   d_status  [nsys] device int32: ZR_OK or ZR_ESINGULAR (outputs of that system are 0)
+ *   d_status  [nsys] device int32: ZR_OK or ZR_ESINGULAR (outputs of that system unspecified)
  * Asynchronous on `stream`; host-side argument errors return immediately. */
 zr_status vandermonde_solve_batch(size_t nsys, uint64_t p, const uint64_t* d_sys_off, const uint64_t* h_sys_off,
                                   const uint64_t* d_mono, const uint32_t* h_nrhs, const uint64_t* d_rhs_off,

@@ -656,8 +656,22 @@ static BPlan bplan(uint32_t t, uint32_t R, double cap, const Tuning& T) {
 
 void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs_in, hipStream_t s) {
   std::vector<SolveJob> jobs;
-  for (const auto& j : jobs_in)
-    if (j.t && j.R) jobs.push_back(j);
+  for (const auto& j : jobs_in) {
+    if (!j.t || !j.R) continue;
+    if (j.t >= kBatchOwnSolveMinT && vsolve_uses_mfma()) {
+      // a large system fills the device on its own: the one-system solve, whose
+      // dot products run on the matrix cores (outside any graph capture)
+      DevArena A(s);
+      uint64_t* Mc = A.alloc<uint64_t>(j.t);
+      uint64_t* tmp = A.alloc<uint64_t>(master_tmp_words(j.t));
+      check(master_poly(M, j.t, j.mono, Mc, tmp, s));
+      const VsolvePlan P = vsolve_plan(j.t, j.R, device_cus());
+      uint64_t* work = A.alloc<uint64_t>(vsolve_workspace_words(P));
+      check(vsolve(M, P, j.mono, Mc, j.rhs, j.t, j.rhs, j.t, work, j.status, s));
+      continue;
+    }
+    jobs.push_back(j);
+  }
   if (jobs.empty()) return;
   const uint32_t n = (uint32_t)jobs.size();
   const Tuning& T = tuning();

@@ -57,6 +57,10 @@ struct SolveJob {
 };
 
 // Master polynomials and solves of all jobs (enqueued on s, no host sync).
+// Systems of at least kBatchOwnSolveMinT unknowns go through the one-system
+// solve when its dot products run on the matrix cores; the others share the
+// persistent work-queue pass.
+constexpr uint32_t kBatchOwnSolveMinT = 8192;
 void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs, hipStream_t s);
 
 // Newton matrices and powers of y_k for many (nodes, y_k) sets at once:

@@ -25,6 +25,8 @@ struct VsolvePlan {
   uint32_t Sd;         // partial dot-product sums per row and right-hand side (chunk groups for mf)
 };
 VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus);
+// true when the one-system solve's dot products run on the matrix cores (solve variant 2)
+bool vsolve_uses_mfma();
 
 // Workspace (device, uint64 elements) needed by vsolve for a plan.
 size_t vsolve_workspace_words(const VsolvePlan& P);
