@@ -79,14 +79,19 @@ __device__ __forceinline__ void vs_chain_body(const VsArgs& a, uint32_t l, uint3
     const uint32_t rn = r > lo + 8 ? r - 8 : lo;
 #pragma unroll
     for (int u = 0; u < 8; ++u) nxt[u] = rn >= (uint32_t)u + 1 + lo ? a.Mc[rn - 1 - u] : 0;
+    // x kept in [0, 2p): Shoup's product without its final correction, then
+    // one correction of the sum (its carry included)
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (r > lo + (uint32_t)u) x = zr_add(a.M, zr_shoup(a.M, x, m, mp), cur[u]);
+      if (r > lo + (uint32_t)u) {
+        const uint64_t pr = zr_shoup_lazy(a.M, x, m, mp), sm = pr + cur[u];
+        x = (sm < pr || sm >= a.M.p) ? sm - a.M.p : sm;
+      }
     r = rn;
 #pragma unroll
     for (int u = 0; u < 8; ++u) cur[u] = nxt[u];
   }
-  a.Bc[(size_t)c * a.t + l] = x;
+  a.Bc[(size_t)c * a.t + l] = x >= a.M.p ? x - a.M.p : x;
 }
 
 // Per-row scan over chunks: qstart[0] = 1, qstart[c] = m^L qstart[c-1] + B_{c-1}.
