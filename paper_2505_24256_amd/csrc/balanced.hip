@@ -12,7 +12,7 @@
 
 namespace zr {
 
-static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+__host__ __device__ static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
 // ----------------------------------------------------------------------------
 // Thiele, one lane per slice.  Samples F[j][i] at nodes X[j], j < nk.
@@ -454,13 +454,14 @@ __device__ __forceinline__ uint64_t wave_sum_mod(const zr_mod& M, uint64_t v) {
   return v;
 }
 
-__global__ void __launch_bounds__(kApW * 64) k_vapply(zr_mod M, uint32_t t, const uint64_t* __restrict__ mono,
-                                                      const uint64_t* __restrict__ a, uint32_t T,
-                                                      uint64_t* __restrict__ partial) {
-  __shared__ uint64_t sh[kApW][kApB];
+// block (bx, by): powers i0 = kApB bx .. + kApB, terms kApW*64 by .. (one partial row by)
+__device__ __forceinline__ void vapply_body(const zr_mod& M, uint32_t t, const uint64_t* __restrict__ mono,
+                                            const uint64_t* __restrict__ a, uint32_t T,
+                                            uint64_t* __restrict__ partial, uint32_t bx, uint32_t by,
+                                            uint64_t (*sh)[kApB]) {
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint32_t l = blockIdx.y * (kApW * 64) + threadIdx.x;
-  const uint32_t i0 = blockIdx.x * kApB;
+  const uint32_t l = by * (kApW * 64) + threadIdx.x;
+  const uint32_t i0 = bx * kApB;
   const uint32_t nb = std::min<uint32_t>(kApB, T - i0);
   uint64_t m = 0, mp = 0, b = 0;
   if (l < t) {
@@ -477,8 +478,15 @@ __global__ void __launch_bounds__(kApW * 64) k_vapply(zr_mod M, uint32_t t, cons
   for (uint32_t ii = threadIdx.x; ii < nb; ii += blockDim.x) {
     uint64_t s = sh[0][ii];
     for (int w = 1; w < kApW; ++w) s = zr_add(M, s, sh[w][ii]);
-    partial[(size_t)blockIdx.y * T + i0 + ii] = s;
+    partial[(size_t)by * T + i0 + ii] = s;
   }
+}
+
+__global__ void __launch_bounds__(kApW * 64) k_vapply(zr_mod M, uint32_t t, const uint64_t* __restrict__ mono,
+                                                      const uint64_t* __restrict__ a, uint32_t T,
+                                                      uint64_t* __restrict__ partial) {
+  __shared__ uint64_t sh[kApW][kApB];
+  vapply_body(M, t, mono, a, T, partial, blockIdx.x, blockIdx.y, sh);
 }
 
 __global__ void k_vapply_sum(zr_mod M, uint32_t T, uint32_t nparts, const uint64_t* __restrict__ partial,
@@ -503,6 +511,39 @@ hipError_t vapply(const zr_mod& M, uint32_t t, const uint64_t* mono, const uint6
   TimedLaunch tl("vapply", s);
   hipLaunchKernelGGL(k_vapply, dim3(cdiv(T, kApB), nparts), dim3(kApW * 64), 0, s, M, t, mono, a, T, work);
   hipLaunchKernelGGL(k_vapply_sum, dim3(cdiv(T, 256)), dim3(256), 0, s, M, T, nparts, work, out);
+  return hipGetLastError();
+}
+
+// ---- many applies in two launches (block -> job by binary search over prefix sums)
+uint32_t vapply_batch_blocks(uint32_t t, uint32_t T) { return t ? cdiv(T, kApB) * cdiv(t, kApW * 64) : 0; }
+
+__global__ void __launch_bounds__(kApW * 64) k_vapply_batch(zr_mod M, uint32_t n, const uint32_t* __restrict__ prefix,
+                                                            const VapplyJob* __restrict__ jobs) {
+  __shared__ uint64_t sh[kApW][kApB];
+  const uint32_t q = thiele_job_of(n, prefix, blockIdx.x);
+  const VapplyJob& j = jobs[q];
+  const uint32_t lb = blockIdx.x - prefix[q], nbx = cdiv(j.T, kApB);
+  vapply_body(M, j.t, j.mono, j.a, j.T, j.work, lb % nbx, lb / nbx, sh);
+}
+
+__global__ void k_vapply_sum_batch(zr_mod M, uint32_t n, const uint32_t* __restrict__ prefix,
+                                   const VapplyJob* __restrict__ jobs) {
+  const uint32_t q = thiele_job_of(n, prefix, blockIdx.x);
+  const VapplyJob& j = jobs[q];
+  const uint32_t i = (blockIdx.x - prefix[q]) * blockDim.x + threadIdx.x;
+  if (i >= j.T) return;
+  const uint32_t nparts = j.t ? cdiv(j.t, kApW * 64) : 0;
+  uint64_t s = 0;
+  for (uint32_t c = 0; c < nparts; ++c) s = zr_add(M, s, j.work[(size_t)c * j.T + i]);
+  j.out[i] = s;
+}
+
+hipError_t vapply_batch(const zr_mod& M, uint32_t n, const uint32_t* d_prefix, uint32_t total,
+                        const uint32_t* d_sum_prefix, uint32_t sum_total, const VapplyJob* d_jobs, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  TimedLaunch tl("vapply", s);
+  if (total) hipLaunchKernelGGL(k_vapply_batch, dim3(total), dim3(kApW * 64), 0, s, M, n, d_prefix, d_jobs);
+  if (sum_total) hipLaunchKernelGGL(k_vapply_sum_batch, dim3(sum_total), dim3(256), 0, s, M, n, d_sum_prefix, d_jobs);
   return hipGetLastError();
 }
 
@@ -564,6 +605,51 @@ hipError_t balance_rhs(const zr_mod& M, uint32_t T, uint32_t nk, const uint64_t*
   if (units && rows)
     hipLaunchKernelGGL(k_balance_rhs, dim3(cdiv(rows, 64), units), dim3(64), 0, s, M, T, X, A, B, degA, degB, beta,
                        tN, rhoN, vN, ldN, tD, vD, ldD);
+  return hipGetLastError();
+}
+
+// ---- the balancing of many reconstructions in two launches
+__global__ void k_balance_beta_batch(zr_mod M, uint32_t n, const uint32_t* __restrict__ prefix,
+                                     const BalanceJob* __restrict__ jobs) {
+  const uint32_t q = thiele_job_of(n, prefix, blockIdx.x);
+  const BalanceJob& j = jobs[q];
+  const uint32_t i = (blockIdx.x - prefix[q]) * blockDim.x + threadIdx.x;
+  if (i >= j.T) return;
+  const uint64_t a0 = horner_col(M, j.A, j.T, i, j.degA[i], j.X[0]);
+  const uint64_t b0 = horner_col(M, j.B, j.T, i, j.degB[i], j.X[0]);
+  uint64_t b = 0;
+  if (j.nprev[i] != 0 && a0 != 0) b = zr_mul(M, j.nprev[i], zr_inv(M, a0));
+  else if (j.dprev[i] != 0 && b0 != 0) b = zr_mul(M, j.dprev[i], zr_inv(M, b0));
+  else *j.status = -4;  // ZR_EDEGEN for the whole reconstruction (every writer stores the same value)
+  j.beta[i] = b;
+}
+
+__global__ void k_balance_rhs_batch(zr_mod M, uint32_t n, const uint32_t* __restrict__ prefix,
+                                    const BalanceJob* __restrict__ jobs) {
+  const uint32_t q = thiele_job_of(n, prefix, blockIdx.x);
+  const BalanceJob& j = jobs[q];
+  const uint32_t rows = std::max(j.tN, j.tD), nbx = cdiv(rows, 64);
+  const uint32_t lb = blockIdx.x - prefix[q];
+  const uint32_t i = (lb % nbx) * 64 + threadIdx.x, u = lb / nbx;
+  if (u < (uint32_t)j.rhoN) {
+    if (i < j.tN) j.vN[(size_t)u * j.ldN + i] = zr_mul(M, j.beta[i], horner_col(M, j.A, j.T, i, j.degA[i], j.X[u + 1]));
+  } else {
+    const uint32_t v = u - (uint32_t)j.rhoN;
+    if (i < j.tD) j.vD[(size_t)v * j.ldD + i] = zr_mul(M, j.beta[i], horner_col(M, j.B, j.T, i, j.degB[i], j.X[v + 1]));
+  }
+}
+
+uint32_t balance_beta_blocks(uint32_t T) { return cdiv(T, 64); }
+uint32_t balance_rhs_blocks(uint32_t tN, uint32_t tD, int32_t rhoN, int32_t rhoD) {
+  return cdiv(std::max(tN, tD), 64) * (uint32_t)(std::max(rhoN, 0) + std::max(rhoD, 0));
+}
+
+hipError_t balance_batch(const zr_mod& M, uint32_t n, const uint32_t* d_beta_prefix, uint32_t beta_total,
+                         const uint32_t* d_rhs_prefix, uint32_t rhs_total, const BalanceJob* d_jobs, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  TimedLaunch tl("balance", s);
+  if (beta_total) hipLaunchKernelGGL(k_balance_beta_batch, dim3(beta_total), dim3(64), 0, s, M, n, d_beta_prefix, d_jobs);
+  if (rhs_total) hipLaunchKernelGGL(k_balance_rhs_batch, dim3(rhs_total), dim3(64), 0, s, M, n, d_rhs_prefix, d_jobs);
   return hipGetLastError();
 }
 

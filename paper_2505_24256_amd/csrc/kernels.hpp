@@ -109,6 +109,45 @@ hipError_t vapply(const zr_mod& M, uint32_t t, const uint64_t* mono, const uint6
                   uint64_t* work, size_t work_words, hipStream_t s);
 size_t vapply_work_words(uint32_t t, uint32_t T);
 
+// Many applies in two launches: d_prefix[n+1] prefix sums of
+// vapply_batch_blocks(t_q, T_q), d_sum_prefix[n+1] of cdiv(T_q, 256); each
+// job's work holds vapply_work_words(t, T) words.
+struct VapplyJob {
+  uint32_t t, T;
+  const uint64_t* mono;
+  const uint64_t* a;
+  uint64_t* out;
+  uint64_t* work;
+};
+uint32_t vapply_batch_blocks(uint32_t t, uint32_t T);
+hipError_t vapply_batch(const zr_mod& M, uint32_t n, const uint32_t* d_prefix, uint32_t total,
+                        const uint32_t* d_sum_prefix, uint32_t sum_total, const VapplyJob* d_jobs, hipStream_t s);
+
+// The balancing of many reconstructions in two launches (as balance_rhs per
+// job, with beta[T] per job; a slice without a factor sets *status = ZR_EDEGEN):
+// d_beta_prefix of balance_beta_blocks(T), d_rhs_prefix of balance_rhs_blocks(...).
+struct BalanceJob {
+  uint32_t T, tN, tD;
+  int32_t rhoN, rhoD;
+  const uint64_t* X;
+  const uint64_t* A;
+  const uint64_t* B;
+  const int32_t* degA;
+  const int32_t* degB;
+  const uint64_t* nprev;
+  const uint64_t* dprev;
+  uint64_t* beta;
+  uint64_t* vN;
+  size_t ldN;
+  uint64_t* vD;
+  size_t ldD;
+  int32_t* status;
+};
+uint32_t balance_beta_blocks(uint32_t T);
+uint32_t balance_rhs_blocks(uint32_t tN, uint32_t tD, int32_t rhoN, int32_t rhoD);
+hipError_t balance_batch(const zr_mod& M, uint32_t n, const uint32_t* d_beta_prefix, uint32_t beta_total,
+                         const uint32_t* d_rhs_prefix, uint32_t rhs_total, const BalanceJob* d_jobs, hipStream_t s);
+
 // Balanced right-hand sides: beta_i from N_{k-1}(y^i)/A_i(x_0) (fallback
 // D_{k-1}(y^i)/B_i(x_0)) into beta[T], then vN[j][i] = beta_i A_i(x_{j+1})
 // (j < rhoN, i < tN) and vD[j][i] = beta_i B_i(x_{j+1}) (j < rhoD, i < tD).

@@ -187,6 +187,7 @@ void advance(Server& S) {
     char* dxb = xb.upload(A, s);
     size_t hwords = 0;
     std::vector<ThieleJob> tj;
+    std::vector<VapplyJob> vj;
     for (size_t q = 0; q < bal.size(); ++q) {
       Bal& b = bal[q];
       Request& r = *b.r;
@@ -212,11 +213,24 @@ void advance(Server& S) {
       }
       // the slices of every request go through one Thiele launch below
       tj.push_back(ThieleJob{b.T, b.nk, b.dX, b.F, b.cA, b.cB, b.dgA, b.dgB, b.dst, scr});
-      const size_t ww = std::max(vapply_work_words(r.SN.t, b.T), vapply_work_words(r.SD.t, b.T));
-      uint64_t* wk = A.alloc<uint64_t>(ww);
-      check(vapply(M, r.SN.t, r.SN.mono, r.SN.coef, b.T, b.nprev, wk, ww, s));
-      check(vapply(M, r.SD.t, r.SD.mono, r.SD.coef, b.T, b.dprev, wk, ww, s));
+      // N_{k-1} and D_{k-1} at y^i: applies of all requests go through two launches below
+      vj.push_back(VapplyJob{r.SN.t, b.T, r.SN.mono, r.SN.coef, b.nprev,
+                             A.alloc<uint64_t>(vapply_work_words(r.SN.t, b.T))});
+      vj.push_back(VapplyJob{r.SD.t, b.T, r.SD.mono, r.SD.coef, b.dprev,
+                             A.alloc<uint64_t>(vapply_work_words(r.SD.t, b.T))});
       counters().mulmods += (uint64_t)b.T * (r.SN.t + r.SD.t);
+    }
+    if (!vj.empty()) {
+      std::vector<uint32_t> pre{0}, spre{0};
+      for (const VapplyJob& j : vj) {
+        pre.push_back(pre.back() + vapply_batch_blocks(j.t, j.T));
+        spre.push_back(spre.back() + (j.T + 255) / 256);
+      }
+      Blob vb;
+      const size_t oj = vb.add(vj), op = vb.add(pre), os = vb.add(spre);
+      char* dv = vb.upload(A, s);
+      check(vapply_batch(M, (uint32_t)vj.size(), (const uint32_t*)(dv + op), pre.back(), (const uint32_t*)(dv + os),
+                         spre.back(), (const VapplyJob*)(dv + oj), s));
     }
     if (!tj.empty()) {
       uint32_t max_nk = 0;
@@ -257,6 +271,8 @@ void advance(Server& S) {
     std::vector<uint64_t> X;
   };
   std::vector<LiftPlan> lp;
+  std::vector<BalanceJob> bj;
+  std::vector<CopyJob> copies;
   for (auto& b : bal) {
     Request& r = *b.r;
     if (r.status != ZR_OK) continue;
@@ -274,16 +290,29 @@ void advance(Server& S) {
     const uint32_t D1N = (uint32_t)b.rhoN + 1, D1D = (uint32_t)b.rhoD + 1;
     uint64_t* valsN = A.alloc<uint64_t>((size_t)D1N * std::max<uint32_t>(tN, 1));
     uint64_t* valsD = A.alloc<uint64_t>((size_t)D1D * std::max<uint32_t>(tD, 1));
-    check(copy_u64(valsN, r.SN.coef, tN, s));
-    check(copy_u64(valsD, r.SD.coef, tD, s));
-    check(fill_i32(b.dst, 0, T1, s));
-    check(balance_rhs(M, b.T, b.nk, b.dX, b.cA, b.cB, b.dgA, b.dgB, b.nprev, b.dprev, tN, b.rhoN, valsN + tN, tN, tD,
-                      b.rhoD, valsD + tD, tD, b.dst, A.alloc<uint64_t>(T1), s));
-    check(fold_status(b.dst, b.T, r.d_status, ZR_EDEGEN, s));
+    // row 0 of the Newton input is the previous skeleton; the balancing of all
+    // requests runs in two launches below
+    copies.push_back(CopyJob{r.SN.coef, valsN, (size_t)tN * 8});
+    copies.push_back(CopyJob{r.SD.coef, valsD, (size_t)tD * 8});
+    bj.push_back(BalanceJob{b.T, tN, tD, b.rhoN, b.rhoD, b.dX, b.cA, b.cB, b.dgA, b.dgB, b.nprev, b.dprev,
+                            A.alloc<uint64_t>(T1), valsN + tN, tN, valsD + tD, tD, r.d_status});
     sj.push_back(SolveJob{tN, (uint32_t)b.rhoN, r.SN.mono, valsN + tN, r.d_status});
     sj.push_back(SolveJob{tD, (uint32_t)b.rhoD, r.SD.mono, valsD + tD, r.d_status});
     lp.push_back(LiftPlan{&r, false, b.kvar, D1N, valsN, std::vector<uint64_t>(b.X.begin(), b.X.begin() + D1N)});
     lp.push_back(LiftPlan{&r, true, b.kvar, D1D, valsD, std::vector<uint64_t>(b.X.begin(), b.X.begin() + D1D)});
+  }
+  if (!bj.empty()) {
+    batched_copy(copies, s);
+    std::vector<uint32_t> bpre{0}, rpre{0};
+    for (const BalanceJob& j : bj) {
+      bpre.push_back(bpre.back() + balance_beta_blocks(j.T));
+      rpre.push_back(rpre.back() + balance_rhs_blocks(j.tN, j.tD, j.rhoN, j.rhoD));
+    }
+    Blob bb;
+    const size_t oj = bb.add(bj), ob = bb.add(bpre), orh = bb.add(rpre);
+    char* db = bb.upload(A, s);
+    check(balance_batch(M, (uint32_t)bj.size(), (const uint32_t*)(db + ob), bpre.back(), (const uint32_t*)(db + orh),
+                        rpre.back(), (const BalanceJob*)(db + oj), s));
   }
   // polynomial requests: samples at the Zippel points, then the same jobs
   for (Request* rp : act) {
