@@ -42,7 +42,7 @@ INT8_OPS_PER_PRODUCT = 2 * 64
 # rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by the copy-probe calibration (0.5x
 # read, 1.0x write); see profiles/k_vs_mfma_n6_d30_t1e4_hbm_counters.md.  Valid
 # only for the kernel sources and solve variant those counters were taken on.
-DOTS_TRAFFIC = {"sources_sha16": "7944191bda489b83", "variant": "mfma", "bytes_per_launch": 53.43e6}
+DOTS_TRAFFIC = {"sources_sha16": "4175ec264de178b4", "variant": "mfma", "bytes_per_launch": 51.73e6}
 
 
 def _dots_sources_sha16() -> str:
