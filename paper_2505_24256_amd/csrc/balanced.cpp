@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "../../include/zippel.h"
+#include "batch.hpp"
 #include "driver.hpp"
 #include "field.hpp"
 #include "kernels.hpp"
@@ -155,24 +156,32 @@ static void reconstruct_balanced(const zr_params* params, zr_blackbox_fn bb, voi
       call_bb(bb, ctx, P, k, T, P.y.data(), X.data(), nk, F, s);
       uint64_t* cA = A.alloc<uint64_t>((size_t)(nk + 1) * std::max<uint32_t>(T, 1));
       uint64_t* cB = A.alloc<uint64_t>((size_t)(nk + 1) * std::max<uint32_t>(T, 1));
-      int32_t* dgA = A.alloc<int32_t>(std::max<uint32_t>(T, 1));
-      int32_t* dgB = A.alloc<int32_t>(std::max<uint32_t>(T, 1));
-      int32_t* dst = A.alloc<int32_t>(std::max<uint32_t>(T, 1));
+      const uint32_t T1 = std::max<uint32_t>(T, 1);
+      int32_t* dgA = A.alloc<int32_t>(3 * (size_t)T1);  // degrees of A, of B, slice statuses
+      int32_t* dgB = dgA + T1;
+      int32_t* dst = dgB + T1;
       const size_t sw = thiele_scratch_words(T, nk);
       uint64_t* scr = sw ? A.alloc<uint64_t>(sw) : nullptr;
       check(thiele_slices(P.M, T, nk, dX, F, cA, cB, dgA, dgB, dst, scr, s));
-      int32_t rhoN = 0, rhoD = 0;
-      check_slices(d2h_i32(dst, T, s), d2h_i32(dgA, T, s), d2h_i32(dgB, T, s), P.deg[kvar], P.deg_den[kvar], rhoN,
-                   rhoD);
       // previous numerator and denominator at the Zippel points y^i, i = 1..T
-      uint64_t* nprev = A.alloc<uint64_t>(std::max<uint32_t>(T, 1));
-      uint64_t* dprev = A.alloc<uint64_t>(std::max<uint32_t>(T, 1));
+      uint64_t* nprev = A.alloc<uint64_t>(T1);
+      uint64_t* dprev = A.alloc<uint64_t>(T1);
       const size_t ww = std::max(vapply_work_words(tN, T), vapply_work_words(tD, T));
       uint64_t* wk = A.alloc<uint64_t>(ww);
       check(vapply(P.M, tN, SN.mono, SN.coef, T, nprev, wk, ww, s));
       check(vapply(P.M, tD, SD.mono, SD.coef, T, dprev, wk, ww, s));
       counters().mulmods += (uint64_t)T * (tN + tD);
-      // balanced right-hand sides into the Newton value arrays
+      // one read-back of every slice's degrees and status
+      int32_t* h = host_words(3 * (size_t)T1);
+      check(hipMemcpyAsync(h, dgA, 3 * (size_t)T1 * 4, hipMemcpyDeviceToHost, s));
+      check(hipStreamSynchronize(s));
+      int32_t rhoN = 0, rhoD = 0;
+      check_slices(std::vector<int32_t>(h + 2 * (size_t)T1, h + 2 * (size_t)T1 + T),
+                   std::vector<int32_t>(h, h + T), std::vector<int32_t>(h + T1, h + T1 + T), P.deg[kvar],
+                   P.deg_den[kvar], rhoN, rhoD);
+      // balanced right-hand sides into the Newton value arrays; a slice without
+      // a balancing factor marks the reconstruction degenerate (read back with
+      // the lift's statuses)
       const uint32_t D1N = (uint32_t)rhoN + 1, D1D = (uint32_t)rhoD + 1;
       uint64_t* valsN = A.alloc<uint64_t>((size_t)D1N * std::max<uint32_t>(tN, 1));
       uint64_t* valsD = A.alloc<uint64_t>((size_t)D1D * std::max<uint32_t>(tD, 1));
@@ -180,17 +189,22 @@ static void reconstruct_balanced(const zr_params* params, zr_blackbox_fn bb, voi
       check(copy_u64(valsD, SD.coef, tD, s));
       check(fill_i32(dst, 0, T, s));
       check(balance_rhs(P.M, T, nk, dX, cA, cB, dgA, dgB, nprev, dprev, tN, rhoN, valsN + tN, tN, tD, rhoD,
-                        valsD + tD, tD, dst, A.alloc<uint64_t>(std::max<uint32_t>(T, 1)), s));
-      for (int32_t v : d2h_i32(dst, T, s))
-        if (v) throw Error(ZR_EDEGEN);
+                        valsD + tD, tD, dst, A.alloc<uint64_t>(T1), s));
+      check(fold_status(dst, T, d_status, ZR_EDEGEN, s));
       solve_stage(P, SN, valsN, (uint32_t)rhoN, s, d_status);
       solve_stage(P, SD, valsD, (uint32_t)rhoD, s, d_status);
-      std::vector<uint32_t> dn(P.nvars, 0), dd(P.nvars, 0);
-      dn[kvar] = D1N;
-      dd[kvar] = D1D;
-      StageConsts KN(P, A, dn, s), KD(P, A, dd, s);
-      lift_stage(P, kvar, SN, valsN, D1N, KN.W(kvar), KN.ypow(kvar), *kp, nN, s, d_status);
-      lift_stage(P, kvar, SD, valsD, D1D, KD.W(kvar), KD.ypow(kvar), *kp, nD, s, d_status);
+      // Newton matrices (built on the device) and the lifts of N and D, one read-back
+      uint64_t* cwN = A.alloc<uint64_t>(newton_W_words(D1N) / 2 + 2 + 2 * (size_t)D1N);
+      uint64_t* cwD = A.alloc<uint64_t>(newton_W_words(D1D) / 2 + 2 + 2 * (size_t)D1D);
+      const std::vector<ConstsJob> cj{
+          ConstsJob{D1N, X.data(), P.y[kvar], (uint32_t*)cwN, cwN + newton_W_words(D1N) / 2 + 1},
+          ConstsJob{D1D, X.data(), P.y[kvar], (uint32_t*)cwD, cwD + newton_W_words(D1D) / 2 + 1}};
+      batched_consts(P.M, cj, s);
+      const std::vector<LiftJob> lj{
+          LiftJob{kvar, D1N, &SN, valsN, cj[0].Wl, cj[0].ypow, d_status, &nN},
+          LiftJob{kvar, D1D, &SD, valsD, cj[1].Wl, cj[1].ypow, d_status, &nD}};
+      for (int32_t v : batched_lift(P.M, lj, *kp, s))
+        if (v) throw Error(v);
     }
     arenas.erase(arenas.begin());
     SN = nN;

@@ -87,6 +87,8 @@ struct StageConsts {
 };
 
 int32_t* host_scratch();
+// Pinned host words (at least n), thread-local, reused across calls.
+int32_t* host_words(size_t n);
 uint32_t lift_stage(const Params& P, uint32_t kvar, const Skeleton& S, const uint64_t* d_vals, uint32_t D1,
                     const uint32_t* d_W, const uint64_t* d_ypow, DevArena& keep, Skeleton& out, hipStream_t s,
                     int32_t* d_status);

@@ -724,7 +724,7 @@ __device__ __forceinline__ void vs_delta_body(const VsArgs& a, uint32_t l, const
   }
   const uint64_t w = zr_mul(M, m, delta);
   if (w == 0) {
-    atomicExch(status, -3);  // ZR_ESINGULAR
+    atomicCAS(status, 0, -3);  // ZR_ESINGULAR, unless an earlier step already failed
     winv[l] = 0;
     winv[a.t + l] = 0;
     return;

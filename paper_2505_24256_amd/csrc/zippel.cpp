@@ -424,6 +424,22 @@ uint32_t lift_stage(const Params& P, uint32_t kvar, const Skeleton& S, const uin
   return total;
 }
 
+int32_t* host_words(size_t n) {
+  static thread_local int32_t* buf = nullptr;
+  static thread_local size_t cap = 0;
+  if (n > cap) {
+    if (buf) check(hipHostFree(buf));
+    buf = nullptr;
+    cap = 0;
+    const size_t want = std::max<size_t>(n, 1 << 14);
+    void* p = nullptr;
+    check(hipHostMalloc(&p, want * 4, hipHostMallocDefault));
+    buf = (int32_t*)p;
+    cap = want;
+  }
+  return buf;
+}
+
 // Pinned host words for the per-stage size read-back.
 int32_t* host_scratch() {
   static thread_local int32_t* buf = nullptr;
