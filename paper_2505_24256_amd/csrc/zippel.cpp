@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "../../include/zippel.h"
+#include "batch.hpp"
 #include "driver.hpp"
 #include "field.hpp"
 #include "kernels.hpp"
@@ -345,9 +346,10 @@ StageConsts::StageConsts(const Params& P, DevArena& A, const std::vector<uint32_
       acc = zr_mul(P.M, acc, P.y[v]);
     }
   }
-  base = A.alloc<uint32_t>(host.size());
-  h2d(base, host.data(), host.size() * 4, s);
-  check(hipStreamSynchronize(s));
+  // through pinned staging, so the upload stays asynchronous
+  Blob b;
+  b.add(host);
+  base = (uint32_t*)b.upload(A, s);
 }
 
 // ---------------------------------------------------------------------------
