@@ -212,11 +212,12 @@ zr_status zippel_reconstruct_batch(uint32_t n, const zr_params* params, zr_black
 
 /* Dot-product pass of the one-system solve (§2.2, the O(t^2 R) sums):
  * 0 one wave per tile of right-hand sides, each running the synthetic
- * division chain with carry-free 64-bit multiply-accumulates; 1 a producer
- * wave runs the chain once per row block and publishes it through LDS to one
- * consumer wave per tile; 2 (default) the sums as exact int8 matrix products
- * on the matrix cores (signed base-256 digits of both factors, int32
- * accumulation).  Other values select the default.  Same results for all. */
+ * division chain with carry-free 64-bit multiply-accumulates; 1 (default) a
+ * producer wave runs the chain once per row block and publishes it through
+ * LDS to one consumer wave per tile (systems with at most 10 right-hand sides
+ * run as 0); 2 (opt-in) the sums as exact int8 matrix products on the matrix
+ * cores (signed base-256 digits of both factors, int32 accumulation).  Other
+ * values select the default.  Same results for all. */
 void zr_solve_variant(int variant);
 
 /* Graph mode of the batched paths (zippel_reconstruct_batch, the server,

@@ -396,12 +396,13 @@ def autotune(p: int, stream=None):
 
 
 SOLVE_VARIANTS = {"waves": 0, "producer_consumer": 1, "mfma": 2}
-DEFAULT_SOLVE_VARIANT = "mfma"
+DEFAULT_SOLVE_VARIANT = "producer_consumer"
 
 
 def solve_variant(variant=DEFAULT_SOLVE_VARIANT):
     """Select the dot-product pass of the one-system solve (zr_solve_variant):
-    "waves", "producer_consumer" or "mfma" (the default)."""
+    "waves", "producer_consumer" (the default; integer vector ALU) or "mfma"
+    (opt-in, int8 matrix cores)."""
     lib().zr_solve_variant(SOLVE_VARIANTS[variant])
 
 

@@ -9,7 +9,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libzippel_hip.so")
-SOURCES = ["kernels.hip", "balanced.hip", "batch.hip", "microbench.hip", "zippel.cpp", "balanced.cpp", "batch.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "kernels_ilp.hip", "balanced.hip", "batch.hip", "microbench.hip", "zippel.cpp", "balanced.cpp", "batch.cpp", "serve.cpp"]
 ARCH = os.environ.get("ZR_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # keep hipcc from forming packed fp32 instructions
@@ -18,10 +18,11 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 
 
 # Sources whose kernels are latency-bound chains at one wave per SIMD (the
-# matrix-core solve, the product tree): the
-# latency-aware scheduling strategy measured faster there (on batch.hip it
-# measured slower, and it crashes the compiler on balanced.hip).
-ILP_SCHED_SOURCES = ("kernels.hip",)
+# matrix-core solve, the product-tree convolution): LLVM's latency-aware
+# scheduling strategy measured faster there.  Elsewhere it raised register use
+# (the integer-VALU solve lost occupancy) or measured slower (batch.hip), and it
+# crashes the compiler on balanced.hip, so every other source keeps the default.
+ILP_SCHED_SOURCES = ("kernels_ilp.hip",)
 
 
 def build(verbose: bool = False) -> str:

@@ -32,9 +32,10 @@ static uint32_t dots_waves_per_cu(uint32_t RT);
 static uint32_t dots_pc_blocks_per_cu(uint32_t RT, uint32_t ntile);
 
 // Variant of the dot-product pass: one wave per tile (0), the
-// producer/consumer form (1) or the int8 matrix-core form (2, the default);
-// see zr_solve_variant.
-constexpr int kDefaultDotsVariant = 2;
+// producer/consumer form (1, the default; systems of at most kPcMinR
+// right-hand sides still take one wave per tile) or the opt-in int8
+// matrix-core form (2); see zr_solve_variant.
+constexpr int kDefaultDotsVariant = 1;
 static std::atomic<int> g_dots_variant{kDefaultDotsVariant};
 static bool dots_pc_enabled() { return g_dots_variant.load() == 1; }
 static bool dots_mf_enabled() { return g_dots_variant.load() == 2; }
@@ -154,12 +155,6 @@ __global__ void __launch_bounds__(64 * (1 + kPcMaxTiles)) k_vs_dots_pc(VsArgs a,
   vs_dots_pc_body<RT>(a, blockIdx.x, blockIdx.y, ntile, qbuf);
 }
 
-template <int NT, bool LAZY>
-__global__ void __launch_bounds__(64) k_vs_mfma(VsArgs a, const uint32_t* __restrict__ Dg, uint32_t tp, uint32_t RT) {
-  if (blockIdx.z == 0) vs_mfma_body<NT, true, LAZY>(a, Dg, tp, RT, blockIdx.x, blockIdx.y, 0);
-  else vs_mfma_body<NT, false, LAZY>(a, Dg, tp, RT, blockIdx.x, blockIdx.y, blockIdx.z);
-}
-
 __global__ void k_vs_delta(VsArgs a, const uint64_t* __restrict__ mLv, uint64_t* __restrict__ winv,
                            int32_t* __restrict__ status) {
   const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
@@ -183,16 +178,6 @@ static DotsKernel dots_kernel(uint32_t RT) {
       dots_ptr<12>(), dots_ptr<13>(), dots_ptr<14>(), dots_ptr<15>(), dots_ptr<16>(), dots_ptr<17>(),
       dots_ptr<18>(), dots_ptr<19>(), dots_ptr<20>()};
   return RT >= 1 && RT <= kMaxRT ? table[RT] : nullptr;
-}
-
-typedef void (*MfKernel)(VsArgs, const uint32_t*, uint32_t, uint32_t);
-static MfKernel mf_kernel(uint32_t NT, bool lazy) {
-  static const MfKernel table[2][kMfMaxNT + 1] = {
-      {nullptr, k_vs_mfma<1, false>, k_vs_mfma<2, false>, k_vs_mfma<3, false>, k_vs_mfma<4, false>,
-       k_vs_mfma<5, false>, k_vs_mfma<6, false>, k_vs_mfma<7, false>, k_vs_mfma<8, false>},
-      {nullptr, k_vs_mfma<1, true>, k_vs_mfma<2, true>, k_vs_mfma<3, true>, k_vs_mfma<4, true>, k_vs_mfma<5, true>,
-       k_vs_mfma<6, true>, k_vs_mfma<7, true>, k_vs_mfma<8, true>}};
-  return NT >= 1 && NT <= kMfMaxNT ? table[lazy ? 1 : 0][NT] : nullptr;
 }
 
 typedef void (*DotsPcKernel)(VsArgs, uint32_t);
@@ -281,11 +266,10 @@ hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, co
     }
   }
   if (P.mf) {
-    MfKernel km = mf_kernel(cdiv(P.RT, 2), M.p <= kMfLazyMaxP);
-    if (!km) return hipErrorInvalidValue;
     TimedLaunch tl("vs_dots", s);
-    hipLaunchKernelGGL(km, dim3(cdiv(t, kMfRows), P.Sd, P.ntile), dim3(64), 0, s, a, (const uint32_t*)VT, P.tp,
-                       P.RT);
+    const hipError_t e = launch_vs_mfma(cdiv(P.RT, 2), M.p <= kMfLazyMaxP, dim3(cdiv(t, kMfRows), P.Sd, P.ntile), s, a,
+                                        (const uint32_t*)VT, P.tp, P.RT);
+    if (e != hipSuccess) return e;
   } else if (P.pc) {
     DotsPcKernel kp = dots_pc_kernel(P.RT);
     if (!kp) return hipErrorInvalidValue;
@@ -316,14 +300,6 @@ __global__ void __launch_bounds__(64) k_master_small(zr_mod M, uint32_t t, const
                                                      uint64_t* __restrict__ out, uint4* __restrict__ limbs) {
   __shared__ uint64_t buf[128];
   master_small_body(M, t, blockIdx.x * 64, mono, out, limbs, buf);
-}
-
-__global__ void __launch_bounds__(64) k_master_conv(zr_mod M, uint32_t t, uint32_t half, uint32_t IC, uint32_t nic,
-                                                    const uint64_t* __restrict__ cur, const uint4* __restrict__ limbs,
-                                                    uint64_t* __restrict__ part, uint64_t* __restrict__ nxt,
-                                                    uint4* __restrict__ limbs_nxt) {
-  extern __shared__ uint64_t win[];  // 64 + IC + 8 words
-  master_conv_body(M, t, half, IC, nic, blockIdx.x * 64, blockIdx.y, cur, limbs, part, t, nxt, limbs_nxt, win);
 }
 
 __global__ void k_master_sum(zr_mod M, uint32_t t, uint32_t half, uint32_t nic, const uint64_t* __restrict__ cur,
@@ -359,8 +335,8 @@ hipError_t master_poly(const zr_mod& M, uint32_t t, const uint64_t* mono, uint64
     w ^= 1;
     const uint32_t IC = conv_ic(half, cdiv(t, 64));
     const uint32_t nic = cdiv(half, IC);
-    hipLaunchKernelGGL(k_master_conv, dim3(cdiv(t, 64), nic), dim3(64), (64 + IC + 8) * 8, s, M, t, half, IC, nic,
-                       bufs[r], limbs[r], part, bufs[w], limbs[w]);
+    launch_master_conv(dim3(cdiv(t, 64), nic), (64 + IC + 8) * 8, s, M, t, half, IC, nic, bufs[r], limbs[r], part,
+                       bufs[w], limbs[w]);
     if (nic > 1)
       hipLaunchKernelGGL(k_master_sum, dim3(cdiv(t, 256)), dim3(256), 0, s, M, t, half, nic, bufs[r], part, bufs[w],
                          limbs[w]);

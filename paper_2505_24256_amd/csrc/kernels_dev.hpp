@@ -276,30 +276,40 @@ using const_as = const __attribute__((address_space(4))) T*;
 // 64-byte group of a packed row as one vector (one scalar load)
 typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
 
-// One consumer step: q (already in registers) times row r held in cur; row
-// r - 1 is requested into nxt and the next step's q into qn before the
-// products, so that both have a whole step to arrive.
+// One consumer step: q (already in registers) times row r held in cur.  Row
+// rn and the next step's q are requested into nxt and qn right after the
+// first product of the step: the wait that the compiler places before that
+// first use of cur and q then covers only requests a whole step old, and the
+// sched barriers keep the scheduler from moving the requests down to their
+// own uses.
 template <int RT, int G>
 __device__ __forceinline__ void vs_pc_step(const zr_mod& M, Acc6 (&acc)[RT], const u32x16 (&cur)[G],
                                            u32x16 (&nxt)[G], uint64_t& q, const uint64_t* qnext,
-                                           const_as<u32x16> rows, uint32_t& r, uint32_t lo, uint32_t& since) {
-  const uint32_t rn = r > lo ? r - 1 : r;
+                                           const_as<u32x16> rows, uint32_t rn, uint32_t& since) {
+  const uint32_t q0 = (uint32_t)q, q1 = (uint32_t)(q >> 32);
+  acc6_mac(acc[0], q0, q1, cur[0][0], cur[0][1], cur[0][2]);
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int g = 0; g < G; ++g) nxt[g] = rows[(size_t)rn * G + g];
-  const uint64_t qn = qnext ? *qnext : 0;
-  const uint32_t q0 = (uint32_t)q, q1 = (uint32_t)(q >> 32);
+  const uint64_t qn = *qnext;
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int jj = 0; jj < RT; ++jj) {
+  for (int jj = 1; jj < RT; ++jj) {
     const int w0 = 3 * jj, w1 = 3 * jj + 1, w2 = 3 * jj + 2;
     acc6_mac(acc[jj], q0, q1, cur[w0 / 16][w0 % 16], cur[w1 / 16][w1 % 16], cur[w2 / 16][w2 % 16]);
   }
+  // Every word of the row stays live up to here, unused words included: a
+  // value of this step (such as the dead carry-out of a multiply) is then never
+  // given a register that a still pending row load writes, which would force
+  // a wait for that load.
+#pragma unroll
+  for (int g = 0; g < G; ++g) asm volatile("" ::"s"(cur[g]));
   if (++since == kFold) {
 #pragma unroll
     for (int j = 0; j < RT; ++j) acc6_fold(acc[j], M);
     since = 0;
   }
   q = qn;
-  r = rn;
 }
 
 template <int RT>
@@ -337,9 +347,14 @@ __device__ __forceinline__ void vs_dots_pc_body(const VsArgs& a, uint32_t rb, ui
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             if (r > lo + (uint32_t)u) {
+              // q and h kept in [0, 2p) (as in the chain pass); the consumers'
+              // column sums take any q below 2^64, Horner adds q reduced
               qbuf[it & 1][g8 * 8 + u][lane] = q;
-              h = zr_add(M, zr_shoup(M, h, m, mp), q);
-              q = zr_add(M, zr_shoup(M, q, m, mp), cur[u]);
+              const uint64_t qr = q >= M.p ? q - M.p : q;
+              const uint64_t ph = zr_shoup_lazy(M, h, m, mp), sh = ph + qr;
+              h = (sh < ph || sh >= M.p) ? sh - M.p : sh;
+              const uint64_t pq = zr_shoup_lazy(M, q, m, mp), sq = pq + cur[u];
+              q = (sq < pq || sq >= M.p) ? sq - M.p : sq;
             }
           }
           r = rn;
@@ -349,7 +364,7 @@ __device__ __forceinline__ void vs_dots_pc_body(const VsArgs& a, uint32_t rb, ui
       }
       __syncthreads();
     }
-    if (live) a.hpart[(size_t)c * a.t + l] = h;
+    if (live) a.hpart[(size_t)c * a.t + l] = h >= M.p ? h - M.p : h;
     return;
   }
   // consumer of tile wave - 1
@@ -363,7 +378,10 @@ __device__ __forceinline__ void vs_dots_pc_body(const VsArgs& a, uint32_t rb, ui
   for (int j = 0; j < RT; ++j) acc6_zero(acc[j]);
   const_as<u32x16> rows = (const_as<u32x16>)((const uint32_t*)a.VT + (size_t)tile * a.t * LDV);
   // two row buffers: while one feeds the products of step r the other receives
-  // row r-1, so each row's scalar loads have a whole step to arrive
+  // row r-1, so each row's scalar loads have a whole step to arrive.  Blocks
+  // hold an even number of steps except the last, so steps go in pairs (no
+  // branch between a request and its use) and a last odd step, if any, runs
+  // alone.
   uint32_t r = hi - 1;
   uint32_t since = 0;
   u32x16 b0[G], b1[G];
@@ -372,14 +390,22 @@ __device__ __forceinline__ void vs_dots_pc_body(const VsArgs& a, uint32_t rb, ui
   for (uint32_t it = 0; it <= nb; ++it) {
     if (it >= 1) {
       const uint32_t b = it - 1;
-      const uint32_t s_end = min(kQB, hi - lo - b * kQB);  // even except in the last block
-      uint64_t q = qbuf[b & 1][0][lane];
-      for (uint32_t s = 0; s < s_end; s += 2) {
-        vs_pc_step<RT, G>(M, acc, b0, b1, q, s + 1 < s_end ? &qbuf[b & 1][s + 1][lane] : nullptr, rows, r, lo,
-                          since);
-        if (s + 1 < s_end)
-          vs_pc_step<RT, G>(M, acc, b1, b0, q, s + 2 < s_end ? &qbuf[b & 1][s + 2][lane] : nullptr, rows, r, lo,
-                            since);
+      const uint32_t s_end = min(kQB, hi - lo - b * kQB);
+      const uint64_t* qb = &qbuf[b & 1][0][lane];
+      uint64_t q = qb[0];
+      uint32_t s = 0;
+      for (; s + 2 <= s_end; s += 2) {
+        // the q of step s_end (past the block) is read from the last slot and not used
+        vs_pc_step<RT, G>(M, acc, b0, b1, q, qb + 64 * (s + 1), rows, r > lo ? r - 1 : r, since);
+        r = r > lo ? r - 1 : r;
+        vs_pc_step<RT, G>(M, acc, b1, b0, q, qb + 64 * min(s + 2, kQB - 1), rows, r > lo ? r - 1 : r, since);
+        r = r > lo ? r - 1 : r;
+      }
+      if (s < s_end) {
+        vs_pc_step<RT, G>(M, acc, b0, b1, q, qb, rows, r > lo ? r - 1 : r, since);
+        r = r > lo ? r - 1 : r;
+#pragma unroll
+        for (int g = 0; g < G; ++g) b0[g] = b1[g];
       }
     }
     __syncthreads();
@@ -975,5 +1001,18 @@ __device__ __forceinline__ void expand_body(const zr_mod& M, uint32_t t, uint32_
   coef_new[pos] = c;
   mono_new[pos] = zr_shoup(M, mono_old[l], ypow[d], ypowp[d]);
 }
+
+}  // namespace zr
+
+namespace zr {
+
+// Host launchers of the kernels compiled with the latency-aware scheduler
+// (kernels_ilp.hip).  launch_vs_mfma returns hipErrorInvalidValue for NT
+// outside 1..kMfMaxNT.
+hipError_t launch_vs_mfma(uint32_t NT, bool lazy, dim3 grid, hipStream_t s, const VsArgs& a, const uint32_t* Dg,
+                          uint32_t tp, uint32_t RT);
+void launch_master_conv(dim3 grid, size_t shmem, hipStream_t s, const zr_mod& M, uint32_t t, uint32_t half,
+                        uint32_t IC, uint32_t nic, const uint64_t* cur, const uint4* limbs, uint64_t* part,
+                        uint64_t* nxt, uint4* limbs_nxt);
 
 }  // namespace zr

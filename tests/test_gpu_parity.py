@@ -236,14 +236,14 @@ def test_balanced_enorm(zr):
     assert ei.value.code == zr.ZR_ENORM
 
 
-def test_zippel_producer_consumer_pass(zr):
-    """The producer/consumer dot-product pass gives the same result as the
-    default (matrix-core) one (systems with 12 and 30 right-hand sides)."""
+def test_zippel_one_wave_pass(zr):
+    """The one-wave-per-tile dot-product pass gives the same result as the
+    default (producer/consumer) one (systems with 12 and 30 right-hand sides)."""
     for nvars, deg, nterms, seed in ((4, 12, 2000, 21), (3, 30, 3000, 33)):
         w = synth.poly_workload("pc", nvars, deg, nterms, seed, 1000 + seed, nprobes=2)
         base = zr.reconstruct(w.p, w.deg, _box(zr, w.hidden), sched=w.schedule)
         try:
-            zr.solve_variant("producer_consumer")
+            zr.solve_variant("waves")
             pc = zr.reconstruct(w.p, w.deg, _box(zr, w.hidden), sched=w.schedule)
         finally:
             zr.solve_variant()
