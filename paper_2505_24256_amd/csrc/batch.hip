@@ -658,9 +658,9 @@ void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs_in, hipStr
   std::vector<SolveJob> jobs;
   for (const auto& j : jobs_in) {
     if (!j.t || !j.R) continue;
-    if (j.t >= kBatchOwnSolveMinT && vsolve_uses_mfma()) {
-      // a large system fills the device on its own: the one-system solve, whose
-      // dot products run on the matrix cores (outside any graph capture)
+    if (j.t >= kBatchOwnSolveMinT && vsolve_beats_queue()) {
+      // a large system fills the device on its own: the one-system solve, with
+      // its faster dot-product pass (outside any graph capture)
       DevArena A(s);
       uint64_t* Mc = A.alloc<uint64_t>(j.t);
       uint64_t* tmp = A.alloc<uint64_t>(master_tmp_words(j.t));
@@ -668,6 +668,7 @@ void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs_in, hipStr
       const VsolvePlan P = vsolve_plan(j.t, j.R, device_cus());
       uint64_t* work = A.alloc<uint64_t>(vsolve_workspace_words(P));
       check(vsolve(M, P, j.mono, Mc, j.rhs, j.t, j.rhs, j.t, work, j.status, s));
+      count_solve(j.t, j.R);
       continue;
     }
     jobs.push_back(j);

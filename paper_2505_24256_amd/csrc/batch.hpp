@@ -58,8 +58,8 @@ struct SolveJob {
 
 // Master polynomials and solves of all jobs (enqueued on s, no host sync).
 // Systems of at least kBatchOwnSolveMinT unknowns go through the one-system
-// solve when its dot products run on the matrix cores; the others share the
-// persistent work-queue pass.
+// solve when its selected pass beats the queue's (vsolve_beats_queue); the
+// others share the persistent work-queue pass.
 constexpr uint32_t kBatchOwnSolveMinT = 8192;
 void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs, hipStream_t s);
 

@@ -25,8 +25,11 @@ struct VsolvePlan {
   uint32_t Sd;         // partial dot-product sums per row and right-hand side (chunk groups for mf)
 };
 VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus);
-// true when the one-system solve's dot products run on the matrix cores (solve variant 2)
-bool vsolve_uses_mfma();
+// true when the selected dot-product pass of the one-system solve is faster
+// than the batched work-queue pass on a system that fills the device alone
+// (the producer/consumer and matrix-core variants; the one-wave-per-tile
+// variant shares the queue pass's body)
+bool vsolve_beats_queue();
 
 // Workspace (device, uint64 elements) needed by vsolve for a plan.
 size_t vsolve_workspace_words(const VsolvePlan& P);
