@@ -41,9 +41,9 @@ INT8_OPS_PER_PRODUCT = 2 * 64
 
 # HBM bytes per launch of the dominant solve kernel on this workload, from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by the copy-probe calibration (0.5x
-# read, 1.0x write); see profiles/k_vs_mfma_n6_d30_t1e4_hbm_counters.md.  Valid
-# only for the kernel sources and solve variant those counters were taken on.
-DOTS_TRAFFIC = {"sources_sha16": "4175ec264de178b4", "variant": "mfma", "bytes_per_launch": 51.73e6}
+# read, 1.0x write); see profiles/k_vs_dots_pc_n6_d30_t1e4_hbm_counters.md.
+# Valid only for the kernel sources and solve variant those counters were taken on.
+DOTS_TRAFFIC = {"sources_sha16": "b71b037d85e8af65", "variant": "producer_consumer", "bytes_per_launch": 70.90e6}
 
 
 def _dots_sources_sha16() -> str:

@@ -256,6 +256,28 @@ __device__ __forceinline__ void vs_dots_body(const VsArgs& a, uint32_t rb, uint3
   }
 }
 
+// Shoup product x*w mod p in [0, 2p) for any 64-bit x (w < p, wp its Shoup
+// quotient floor(w 2^64 / p)), for the producer's chain.  The high half of
+// x*wp takes four 32x32->64 multiplies; the one carry out of the middle
+// column is found by a compare, so no partial sum has to be zero-extended.
+__device__ __forceinline__ uint64_t shoup_lazy_v(uint64_t x, uint64_t w, uint64_t wp, uint64_t p) {
+  const uint32_t x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32);
+  const uint32_t w0 = (uint32_t)wp, w1 = (uint32_t)(wp >> 32);
+  const uint64_t b = (uint64_t)x1 * w0 + __umulhi(x0, w0);  // < 2^64
+  const uint64_t s = (uint64_t)x0 * w1 + b;                  // mod 2^64
+  const uint64_t cy = s < b ? (1ull << 32) : 0;              // carry out of bit 64
+  const uint64_t qh = (uint64_t)x1 * w1 + (s >> 32) + cy;    // high half of x*wp
+  return x * w - qh * p;
+}
+
+// r + c reduced into [0, 2p) for r, c in [0, 2p), given cm = c - 2p mod 2^64:
+// r + c - 2p lies in [-2p, 2p), and r + cm carries out of bit 64 exactly
+// when it is not negative; otherwise 2p is added back.
+__device__ __forceinline__ uint64_t add_lazy2p(uint64_t r, uint64_t cm, uint64_t p2) {
+  const uint64_t t = r + cm;
+  return t + (t < r ? 0 : p2);
+}
+
 // Producer/consumer form of pass 2 for systems with several right-hand-side
 // tiles: wave 0 of the workgroup runs the chain and Horner once and publishes
 // q_{l,r} through LDS in blocks of kQB steps (double buffered); wave 1 + tile
@@ -333,6 +355,7 @@ __device__ __forceinline__ void vs_dots_pc_body(const VsArgs& a, uint32_t rb, ui
     uint64_t q = a.qstart ? a.qstart[(size_t)c * a.t + l] : 1 % M.p;
     uint64_t h = 0;
     const_as<uint64_t> Mc = (const_as<uint64_t>)a.Mc;
+    const uint64_t p2 = 2 * M.p;  // below 2^64 since p < 2^63
     uint32_t r = hi;  // the next step is r - 1
     uint64_t cur[8], nxt[8];
 #pragma unroll
@@ -347,14 +370,11 @@ __device__ __forceinline__ void vs_dots_pc_body(const VsArgs& a, uint32_t rb, ui
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             if (r > lo + (uint32_t)u) {
-              // q and h kept in [0, 2p) (as in the chain pass); the consumers'
-              // column sums take any q below 2^64, Horner adds q reduced
+              // q and h kept in [0, 2p); the consumers' column sums take any
+              // q below 2^64.  cur[u] - 2p is uniform (scalar unit).
               qbuf[it & 1][g8 * 8 + u][lane] = q;
-              const uint64_t qr = q >= M.p ? q - M.p : q;
-              const uint64_t ph = zr_shoup_lazy(M, h, m, mp), sh = ph + qr;
-              h = (sh < ph || sh >= M.p) ? sh - M.p : sh;
-              const uint64_t pq = zr_shoup_lazy(M, q, m, mp), sq = pq + cur[u];
-              q = (sq < pq || sq >= M.p) ? sq - M.p : sq;
+              h = add_lazy2p(shoup_lazy_v(h, m, mp, M.p), q - p2, p2);
+              q = add_lazy2p(shoup_lazy_v(q, m, mp, M.p), cur[u] - p2, p2);
             }
           }
           r = rn;
