@@ -97,6 +97,33 @@ __global__ void __launch_bounds__(64) k_b_dots(const BSolve* __restrict__ sys, c
   }
 }
 
+// Persistent producer/consumer pass: each workgroup (a producer wave and one
+// consumer wave per tile, as many as the class's widest system needs) pops
+// (system, row block, chunk) items until the queue is empty; every wave of the
+// workgroup takes the same item, so all of them reach the same barriers and
+// the same exit.  head must be zero at launch.
+template <int RT>
+__global__ void __launch_bounds__(64 * (1 + kPcMaxTiles))
+    k_b_dots_pc(const BSolve* __restrict__ sys, const uint4* __restrict__ items, uint32_t nitems,
+                uint32_t* __restrict__ head, const uint64_t* __restrict__ vt_base, uint64_t* __restrict__ part_base) {
+  __shared__ uint64_t qbuf[2][kQB][64];
+  __shared__ uint32_t next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(head, 1u);
+    __syncthreads();
+    const uint32_t it = __builtin_amdgcn_readfirstlane(next);
+    __syncthreads();  // every wave has read next before it is overwritten
+    if (it >= nitems) break;
+    const uint4 w = items[it];
+    const BSolve& b = sys[w.x];
+    VsArgs a = b.a;
+    a.VT = vt_base + b.vt_off;
+    a.spart = part_base + b.sp_off;
+    a.hpart = part_base + b.hp_off;
+    vs_dots_pc_body<RT>(a, w.y, w.z, b.ntile, qbuf);
+  }
+}
+
 __global__ void k_b_delta(uint32_t n, const uint32_t* __restrict__ prefix, const BSolve* __restrict__ sys) {
   const uint32_t s = seg_find(prefix, n, blockIdx.x);
   const BSolve& b = sys[s];
@@ -595,6 +622,33 @@ BDotsKernel bdots_kernel(uint32_t RT) {
   return RT >= 1 && RT <= kMaxRT ? table[RT] : nullptr;
 }
 
+typedef void (*BDotsPcKernel)(const BSolve*, const uint4*, uint32_t, uint32_t*, const uint64_t*, uint64_t*);
+template <int RT>
+BDotsPcKernel bdots_pc_ptr() {
+  return k_b_dots_pc<RT>;
+}
+BDotsPcKernel bdots_pc_kernel(uint32_t RT) {
+  static const BDotsPcKernel table[kPcRT + 1] = {
+      nullptr,           bdots_pc_ptr<1>(), bdots_pc_ptr<2>(), bdots_pc_ptr<3>(), bdots_pc_ptr<4>(), bdots_pc_ptr<5>(),
+      bdots_pc_ptr<6>(), bdots_pc_ptr<7>(), bdots_pc_ptr<8>(), bdots_pc_ptr<9>(), bdots_pc_ptr<10>()};
+  return RT >= 1 && RT <= kPcRT ? table[RT] : nullptr;
+}
+
+// Workgroups of the persistent producer/consumer pass resident per CU with
+// 1 + ntile waves each.
+uint32_t bdots_pc_blocks_per_cu(uint32_t RT, uint32_t ntile) {
+  static int cache[kPcRT + 1][kPcMaxTiles + 1] = {{0}};
+  if (RT < 1 || RT > kPcRT || ntile < 1 || ntile > kPcMaxTiles) return 1;
+  if (!cache[RT][ntile]) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bdots_pc_kernel(RT), 64 * (1 + ntile), 0) != hipSuccess ||
+        nb <= 0)
+      nb = 1;
+    cache[RT][ntile] = nb;
+  }
+  return (uint32_t)cache[RT][ntile];
+}
+
 BPackedKernel bpacked_kernel(uint32_t RT) {
   static const BPackedKernel table[kMaxRT + 1] = {
       nullptr,           bpacked_ptr<1>(),  bpacked_ptr<2>(),  bpacked_ptr<3>(),  bpacked_ptr<4>(),
@@ -630,18 +684,22 @@ struct Segs {
 // chunking only where a system's own work would otherwise outlast the
 // batch's share per wave slot.
 struct BPlan {
-  uint32_t t, R, RT, ntile, ldv, L, S, packed;
+  uint32_t t, R, RT, ntile, ldv, L, S, packed, pc;
 };
 
+// With the producer/consumer pass selected, systems of more than kPcMinR
+// right-hand sides that are not packed take its tiling (at most kPcRT per
+// consumer wave) and go to the persistent producer/consumer queue.
 static BPlan bplan(uint32_t t, uint32_t R, double cap, const Tuning& T) {
   BPlan P;
   P.t = t;
   P.R = R;
-  P.ntile = cdiv(R, kMaxRT);
-  P.RT = cdiv(R, P.ntile);
-  P.ldv = (3 * P.RT + 2 + 15) & ~15u;
   const BandTuning& bt = T.band[band_of(t)];
   P.packed = bt.packed && t < 64 ? 1 : 0;
+  P.pc = !P.packed && R > kPcMinR && cdiv(R, kPcRT) <= kPcMaxTiles && vsolve_uses_pc() ? 1 : 0;
+  P.ntile = P.pc ? cdiv(R, kPcRT) : cdiv(R, kMaxRT);
+  P.RT = cdiv(R, P.ntile);
+  P.ldv = (3 * P.RT + 2 + 15) & ~15u;
   uint32_t S = 1;
   if (!P.packed) {
     const double item = 64.0 * t * P.RT;  // one wave's work for an unsplit row block
@@ -787,6 +845,8 @@ void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs_in, hipStr
   for (uint32_t i = 0; i < n; ++i) order[plan[i].RT].push_back(i);
   std::vector<std::vector<uint2>> lanes(kMaxRT + 1);
   std::vector<uint32_t> max_tiles(kMaxRT + 1, 0);
+  std::vector<std::vector<uint4>> items_pc(kPcRT + 1);  // producer/consumer items per RT class
+  std::vector<uint32_t> pc_tiles(kPcRT + 1, 0);         // consumer waves per workgroup of the class
   for (uint32_t RT = 1; RT <= kMaxRT; ++RT) {
     auto& ord = order[RT];
     std::stable_sort(ord.begin(), ord.end(), [&](uint32_t x, uint32_t y) { return plan[x].L > plan[y].L; });
@@ -796,6 +856,12 @@ void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs_in, hipStr
       if (P.packed) {
         pk.push_back(i);
         max_tiles[RT] = std::max(max_tiles[RT], P.ntile);
+        continue;
+      }
+      if (P.pc) {
+        pc_tiles[RT] = std::max(pc_tiles[RT], P.ntile);
+        for (uint32_t c = 0; c < P.S; ++c)
+          for (uint32_t rb = 0; rb < cdiv(P.t, 64); ++rb) items_pc[RT].push_back(make_uint4(i, rb, c, 0));
         continue;
       }
       for (uint32_t c = 0; c < P.S; ++c)
@@ -833,7 +899,11 @@ void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs_in, hipStr
     if (!items[RT].empty()) o_items[RT] = blob.add(items[RT]);
     if (!lanes[RT].empty()) o_lanes[RT] = blob.add(lanes[RT]);
   }
-  std::vector<uint32_t> zeros(kMaxRT + 1, 0);
+  std::vector<size_t> o_items_pc(kPcRT + 1, 0);
+  for (uint32_t RT = 1; RT <= kPcRT; ++RT)
+    if (!items_pc[RT].empty()) o_items_pc[RT] = blob.add(items_pc[RT]);
+  // queue heads: [0, kMaxRT] one-wave items, [kMaxRT + 1, kMaxRT + 1 + kPcRT] producer/consumer items
+  std::vector<uint32_t> zeros(kMaxRT + 2 + kPcRT, 0);
   const size_t o_heads = blob.add(zeros);
   char* d = blob.upload(A, s);
   auto P32 = [&](size_t o) { return (const uint32_t*)(d + o); };
@@ -846,6 +916,10 @@ void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs_in, hipStr
   std::vector<uint32_t> grid(kMaxRT + 1, 0);  // persistent grid per class, queried before any capture
   for (uint32_t RT = 1; RT <= kMaxRT; ++RT)
     if (!items[RT].empty()) grid[RT] = std::min<uint32_t>((uint32_t)items[RT].size(), cus * bdots_waves_per_cu(RT));
+  std::vector<uint32_t> grid_pc(kPcRT + 1, 0);
+  for (uint32_t RT = 1; RT <= kPcRT; ++RT)
+    if (!items_pc[RT].empty())
+      grid_pc[RT] = std::min<uint32_t>((uint32_t)items_pc[RT].size(), cus * bdots_pc_blocks_per_cu(RT, pc_tiles[RT]));
   // (captured on a library stream, since the caller's may be the null stream,
   // which cannot be captured; the graph is then launched on the caller's)
   const bool graph = graphs_enabled();
@@ -877,6 +951,11 @@ void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs_in, hipStr
   }
   {
     TimedLaunch tl("batch_dots", ls);
+    for (uint32_t RT = 1; RT <= kPcRT; ++RT)
+      if (!items_pc[RT].empty())
+        hipLaunchKernelGGL(bdots_pc_kernel(RT), dim3(grid_pc[RT]), dim3(64 * (1 + pc_tiles[RT])), 0, ls, d_bs,
+                           (const uint4*)(d + o_items_pc[RT]), (uint32_t)items_pc[RT].size(),
+                           d_heads + kMaxRT + 1 + RT, (const uint64_t*)vt_base, part_base);
     for (uint32_t RT = 1; RT <= kMaxRT; ++RT) {
       if (!items[RT].empty()) {
         const uint32_t ni = (uint32_t)items[RT].size();

@@ -30,6 +30,8 @@ VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus);
 // (the producer/consumer and matrix-core variants; the one-wave-per-tile
 // variant shares the queue pass's body)
 bool vsolve_beats_queue();
+// true when the producer/consumer pass is selected (solve variant 1, the default)
+bool vsolve_uses_pc();
 
 // Workspace (device, uint64 elements) needed by vsolve for a plan.
 size_t vsolve_workspace_words(const VsolvePlan& P);
