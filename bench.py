@@ -282,6 +282,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-slots", type=int, default=256)
     ap.add_argument("--serve-budget-gib", type=int, default=16)
+    ap.add_argument("--time-all-kernels", action="store_true",
+                    help="bracket every named launch of the timed steps with HIP events (default: the dot-product pass only)")
     ap.add_argument("--solve-variant", default="producer_consumer", choices=["waves", "producer_consumer", "mfma"],
                     help="dot-product pass of the one-system solve (mfma: the opt-in int8 matrix-core pass)")
     args = ap.parse_args()
@@ -315,13 +317,24 @@ def main():
         print("bench.py: reconstruction does not match the hidden polynomial", file=sys.stderr)
         sys.exit(3)
     rec.replay(True)
+    # warm-up steps: every named launch timed, for the per-kernel breakdown
+    zr.timing(True)
+    zr.timing_reset()
     for _ in range(args.warmup):
         zr.lib().zr_recorder_rewind(rec.handle)
         zr.reconstruct(w.p, w.deg, rec, sched=w.schedule, stream=stream)
     cnt = zr.last_counters()
     torch.cuda.synchronize()
+    zr.timing(False)
+    kernels = {}
+    for name in ("master", "vs_pack", "vs_chain", "vs_scan", "vs_dots", "vs_finish", "newton", "scan", "expand"):
+        n, ms = zr.timing_get(name)
+        if n:
+            kernels[name] = {"launches": n, "ms_total": round(ms, 3)}
 
-    zr.timing(True)
+    # timed steps: HIP events around the dot-product launches only (events
+    # around every launch add host work between launches), unless asked
+    zr.timing(True, dots_only=not args.time_all_kernels)
     zr.timing_reset()
     lat = []
     torch.cuda.synchronize()
@@ -337,11 +350,6 @@ def main():
     exact = exact and bool(np.array_equal(e, w.hidden.exps) and np.array_equal(c, w.hidden.coefs))
 
     n_dots, ms_dots = zr.timing_get("vs_dots")
-    kernels = {}
-    for name in ("master", "vs_pack", "vs_chain", "vs_scan", "vs_dots", "vs_finish", "newton", "scan", "expand"):
-        n, ms = zr.timing_get(name)
-        if n:
-            kernels[name] = {"launches": n, "ms_total": round(ms, 3)}
     steps = args.steps
     mulmods = cnt["mulmods"] * steps
     value = mulmods / elapsed
@@ -424,7 +432,7 @@ def main():
         "mulmods_per_step": cnt["mulmods"],
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "kernels": kernels,
+        "kernels_warmup": {"steps": args.warmup, "per_kernel": kernels},
         "batch": batch,
         "serve": serve,
     }

@@ -306,7 +306,10 @@ void zr_recorder_set_replay(zr_recorder* rec, int replay);
 int zr_recorder_blackbox(void* rec, const zr_points* pts, uint64_t* d_vals, hipStream_t stream);
 
 /* Kernel timing: when enabled, the library brackets each launch of its named
- * kernels with HIP events on the launch stream and accumulates durations. */
+ * kernels with HIP events on the launch stream and accumulates durations.
+ * on = 1 times every named launch; on = 2 only the solve's dot-product pass
+ * ("vs_dots"), which keeps the event overhead out of the other launches;
+ * 0 turns timing off. */
 void zr_timing_enable(int on);
 void zr_timing_reset(void);
 /* Returns the number of timed launches of `kernel` and their total in ms. */

@@ -586,8 +586,10 @@ def thiele_slices(p: int, x, f, stream=None):
 # ---------------------------------------------------------------------------
 # timing and counters
 
-def timing(enable: bool = True):
-    lib().zr_timing_enable(1 if enable else 0)
+def timing(enable: bool = True, dots_only: bool = False):
+    """Kernel timing (zr_timing_enable): every named launch, or with
+    dots_only only the solve's dot-product launches ("vs_dots")."""
+    lib().zr_timing_enable((2 if dots_only else 1) if enable else 0)
 
 
 def timing_reset():

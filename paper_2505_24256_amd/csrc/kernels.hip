@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdlib.h>
+#include <string.h>
 
 #include <algorithm>
 #include <atomic>
@@ -571,7 +572,7 @@ hipError_t copy_u64(uint64_t* d, const uint64_t* src, size_t n, hipStream_t s) {
 
 struct TimingState {
   std::mutex mu;
-  bool on = false;
+  int on = 0;  // 0 off, 1 every named launch, 2 only the solve's dot-product pass ("vs_dots")
   struct Pending {
     std::string name;
     hipEvent_t e0, e1;
@@ -606,7 +607,7 @@ struct TimingState {
 static TimingState g_timing;
 
 TimedLaunch::TimedLaunch(const char* n, hipStream_t st) : name(n), s(st), e0(nullptr), e1(nullptr), on(false) {
-  if (!g_timing.on) return;
+  if (!g_timing.on || (g_timing.on == 2 && strcmp(n, "vs_dots") != 0)) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return;  // not in graphs
   on = true;
@@ -634,7 +635,7 @@ void zr_solve_variant(int variant) {
 
 void zr_timing_enable(int on) {
   std::lock_guard<std::mutex> g(zr::g_timing.mu);
-  zr::g_timing.on = on != 0;
+  zr::g_timing.on = on == 2 ? 2 : (on != 0 ? 1 : 0);
 }
 void zr_timing_reset(void) {
   std::lock_guard<std::mutex> g(zr::g_timing.mu);
