@@ -64,11 +64,34 @@ __device__ __forceinline__ uint32_t pack_word(size_t idx, uint32_t t, uint32_t R
   return out;
 }
 
+// Shoup product x*w mod p in [0, 2p) for any 64-bit x (w < p, wp its Shoup
+// quotient floor(w 2^64 / p)), for the producer's chain.  The high half of
+// x*wp takes four 32x32->64 multiplies; the one carry out of the middle
+// column is found by a compare, so no partial sum has to be zero-extended.
+__device__ __forceinline__ uint64_t shoup_lazy_v(uint64_t x, uint64_t w, uint64_t wp, uint64_t p) {
+  const uint32_t x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32);
+  const uint32_t w0 = (uint32_t)wp, w1 = (uint32_t)(wp >> 32);
+  const uint64_t b = (uint64_t)x1 * w0 + __umulhi(x0, w0);  // < 2^64
+  const uint64_t s = (uint64_t)x0 * w1 + b;                  // mod 2^64
+  const uint64_t cy = s < b ? (1ull << 32) : 0;              // carry out of bit 64
+  const uint64_t qh = (uint64_t)x1 * w1 + (s >> 32) + cy;    // high half of x*wp
+  return x * w - qh * p;
+}
+
+// r + c reduced into [0, 2p) for r, c in [0, 2p), given cm = c - 2p mod 2^64:
+// r + c - 2p lies in [-2p, 2p), and r + cm carries out of bit 64 exactly
+// when it is not negative; otherwise 2p is added back.
+__device__ __forceinline__ uint64_t add_lazy2p(uint64_t r, uint64_t cm, uint64_t p2) {
+  const uint64_t t = r + cm;
+  return t + (t < r ? 0 : p2);
+}
+
 // Pass 1 for row l, chunk c < S-1: chain only, from 0: B_c = sum_r M_r m^(r-lo).
 __device__ __forceinline__ void vs_chain_body(const VsArgs& a, uint32_t l, uint32_t c) {
   uint32_t lo, hi;
   chunk_range(a.t, a.L, c, lo, hi);
   const uint64_t m = a.mono[l], mp = a.mono_p[l];
+  const uint64_t p2 = 2 * a.M.p;  // below 2^64 since p < 2^63
   uint64_t x = 0;
   // M_r for r = hi-1 down to lo, eight at a time, the next eight fetched ahead
   uint32_t r = hi;
@@ -80,13 +103,10 @@ __device__ __forceinline__ void vs_chain_body(const VsArgs& a, uint32_t l, uint3
 #pragma unroll
     for (int u = 0; u < 8; ++u) nxt[u] = rn >= (uint32_t)u + 1 + lo ? a.Mc[rn - 1 - u] : 0;
     // x kept in [0, 2p): Shoup's product without its final correction, then
-    // one correction of the sum (its carry included)
+    // the sum reduced by one carry test (cur[u] - 2p is uniform)
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (r > lo + (uint32_t)u) {
-        const uint64_t pr = zr_shoup_lazy(a.M, x, m, mp), sm = pr + cur[u];
-        x = (sm < pr || sm >= a.M.p) ? sm - a.M.p : sm;
-      }
+      if (r > lo + (uint32_t)u) x = add_lazy2p(shoup_lazy_v(x, m, mp, a.M.p), cur[u] - p2, p2);
     r = rn;
 #pragma unroll
     for (int u = 0; u < 8; ++u) cur[u] = nxt[u];
@@ -200,6 +220,7 @@ __device__ __forceinline__ void vs_dots_body(const VsArgs& a, uint32_t rb, uint3
   uint32_t lo, hi;
   chunk_range(a.t, a.L, c, lo, hi);
   const zr_mod M = a.M;
+  const uint64_t p2 = 2 * M.p;  // below 2^64 since p < 2^63
   const uint64_t m = a.mono[l], mp = a.mono_p[l];
   uint64_t q = a.qstart ? a.qstart[(size_t)c * a.t + l] : 1 % M.p;
   uint64_t h = 0;
@@ -237,8 +258,9 @@ __device__ __forceinline__ void vs_dots_body(const VsArgs& a, uint32_t rb, uint3
       buf[g] = rows[(size_t)rn * G + g];
     }
     const uint64_t Mr = ((uint64_t)mhi << 32) | mlo;
-    if (horner) h = zr_add(M, zr_shoup(M, h, m, mp), q);
-    q = zr_add(M, zr_shoup(M, q, m, mp), Mr);
+    // q and h kept in [0, 2p) (the column sums take any q below 2^64)
+    if (horner) h = add_lazy2p(shoup_lazy_v(h, m, mp, M.p), q - p2, p2);
+    q = add_lazy2p(shoup_lazy_v(q, m, mp, M.p), Mr - p2, p2);
     if (++since == kFold) {
 #pragma unroll
       for (int j = 0; j < RT; ++j) acc6_fold(acc[j], M);
@@ -252,30 +274,8 @@ __device__ __forceinline__ void vs_dots_body(const VsArgs& a, uint32_t rb, uint3
 #pragma unroll
     for (int j = 0; j < RT; ++j)
       if (j0 + j < a.R) a.spart[((size_t)c * a.R + j0 + j) * a.t + l] = acc6_reduce(M, acc[j]);
-    if (horner) a.hpart[(size_t)c * a.t + l] = h;
+    if (horner) a.hpart[(size_t)c * a.t + l] = h >= M.p ? h - M.p : h;
   }
-}
-
-// Shoup product x*w mod p in [0, 2p) for any 64-bit x (w < p, wp its Shoup
-// quotient floor(w 2^64 / p)), for the producer's chain.  The high half of
-// x*wp takes four 32x32->64 multiplies; the one carry out of the middle
-// column is found by a compare, so no partial sum has to be zero-extended.
-__device__ __forceinline__ uint64_t shoup_lazy_v(uint64_t x, uint64_t w, uint64_t wp, uint64_t p) {
-  const uint32_t x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32);
-  const uint32_t w0 = (uint32_t)wp, w1 = (uint32_t)(wp >> 32);
-  const uint64_t b = (uint64_t)x1 * w0 + __umulhi(x0, w0);  // < 2^64
-  const uint64_t s = (uint64_t)x0 * w1 + b;                  // mod 2^64
-  const uint64_t cy = s < b ? (1ull << 32) : 0;              // carry out of bit 64
-  const uint64_t qh = (uint64_t)x1 * w1 + (s >> 32) + cy;    // high half of x*wp
-  return x * w - qh * p;
-}
-
-// r + c reduced into [0, 2p) for r, c in [0, 2p), given cm = c - 2p mod 2^64:
-// r + c - 2p lies in [-2p, 2p), and r + cm carries out of bit 64 exactly
-// when it is not negative; otherwise 2p is added back.
-__device__ __forceinline__ uint64_t add_lazy2p(uint64_t r, uint64_t cm, uint64_t p2) {
-  const uint64_t t = r + cm;
-  return t + (t < r ? 0 : p2);
 }
 
 // Producer/consumer form of pass 2 for systems with several right-hand-side

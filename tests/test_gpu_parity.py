@@ -51,6 +51,10 @@ def _rand_distinct(rng, p, t):
     [(300, 30), (1000, 33), (777, 40)],
     [(2500, 30)],
     [(40, 1), (97, 2), (5, 48), (129, 64)],
+    # producer/consumer queue: one class (10 right-hand sides per consumer
+    # wave) holding systems of 2, 3 and 6 tiles, beside a one-wave system
+    # (R = 10) and a class of narrower tiles (R = 11)
+    [(200, 19), (150, 30), (90, 10), (70, 11), (300, 60), (64, 20)],
 ])
 def test_vandermonde_batch_matches_oracle(zr, case):
     p = synth.make_prime()
