@@ -138,6 +138,23 @@ def batched_vs_plain(zr, synth, args, stream):
         zr.batch_graphs(False)
     exact = exact and all(not isinstance(r, Exception) and np.array_equal(r[0], w.hidden.exps) and
                           np.array_equal(r[1], w.hidden.coefs) for w, r in zip(ws, res))
+    # one more batched run with every named launch timed: where the batch's time goes
+    for r in recs:
+        zr.lib().zr_recorder_rewind(r.handle)
+    zr.timing(True)
+    zr.timing_reset()
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    zr.reconstruct_batch(p, items, stream=stream)
+    torch.cuda.synchronize()
+    t_timed = time.perf_counter() - ts
+    zr.timing(False)
+    breakdown = {}
+    for name in ("batch_master", "batch_pack", "batch_chain", "batch_dots", "batch_finish", "batch_newton",
+                 "batch_expand", "master", "vs_pack", "vs_chain", "vs_scan", "vs_dots", "vs_finish"):
+        k, ms = zr.timing_get(name)
+        if k:
+            breakdown[name] = {"launches": k, "ms_total": round(ms, 2)}
     _progress(f"batched {times}, with graphs {tg:.3f}; plain one at a time")
     # plain, one at a time, same recordings
     for r in recs:
@@ -166,6 +183,7 @@ def batched_vs_plain(zr, synth, args, stream):
                                                          "p99": round(float(np.percentile(lat, 99)) * 1e3, 3)}},
         "speedup": round(tp / tb, 3), "mulmods": cnt["mulmods"], "bit_exact": bool(exact),
         "band_choices": tuned, "setup_seconds": {"generate": round(t_gen, 1), "record": round(t_rec, 1)},
+        "timed_run": {"seconds": round(t_timed, 3), "per_kernel": breakdown},
     }
 
 

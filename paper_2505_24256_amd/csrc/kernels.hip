@@ -40,7 +40,7 @@ constexpr int kDefaultDotsVariant = 1;
 static std::atomic<int> g_dots_variant{kDefaultDotsVariant};
 static bool dots_pc_enabled() { return g_dots_variant.load() == 1; }
 static bool dots_mf_enabled() { return g_dots_variant.load() == 2; }
-bool vsolve_beats_queue() { return dots_pc_enabled() || dots_mf_enabled(); }
+bool vsolve_beats_queue() { return dots_mf_enabled(); }
 bool vsolve_uses_pc() { return dots_pc_enabled(); }
 
 // Widest tile of the one-wave-per-tile pass: 16 right-hand sides keep two

@@ -26,9 +26,10 @@ struct VsolvePlan {
 };
 VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus);
 // true when the selected dot-product pass of the one-system solve is faster
-// than the batched work-queue pass on a system that fills the device alone
-// (the producer/consumer and matrix-core variants; the one-wave-per-tile
-// variant shares the queue pass's body)
+// than the batched work-queue pass on a system that fills the device alone:
+// the matrix-core variant (the one-wave-per-tile and producer/consumer
+// variants have persistent queue forms with the same bodies, where large
+// systems also share the batched product trees and mostly need no chunking)
 bool vsolve_beats_queue();
 // true when the producer/consumer pass is selected (solve variant 1, the default)
 bool vsolve_uses_pc();
