@@ -86,34 +86,6 @@ __device__ __forceinline__ uint64_t add_lazy2p(uint64_t r, uint64_t cm, uint64_t
   return t + (t < r ? 0 : p2);
 }
 
-// Pass 1 for row l, chunk c < S-1: chain only, from 0: B_c = sum_r M_r m^(r-lo).
-__device__ __forceinline__ void vs_chain_body(const VsArgs& a, uint32_t l, uint32_t c) {
-  uint32_t lo, hi;
-  chunk_range(a.t, a.L, c, lo, hi);
-  const uint64_t m = a.mono[l], mp = a.mono_p[l];
-  const uint64_t p2 = 2 * a.M.p;  // below 2^64 since p < 2^63
-  uint64_t x = 0;
-  // M_r for r = hi-1 down to lo, eight at a time, the next eight fetched ahead
-  uint32_t r = hi;
-  uint64_t cur[8], nxt[8];
-#pragma unroll
-  for (int u = 0; u < 8; ++u) cur[u] = r >= (uint32_t)u + 1 + lo ? a.Mc[r - 1 - u] : 0;
-  while (r > lo) {
-    const uint32_t rn = r > lo + 8 ? r - 8 : lo;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) nxt[u] = rn >= (uint32_t)u + 1 + lo ? a.Mc[rn - 1 - u] : 0;
-    // x kept in [0, 2p): Shoup's product without its final correction, then
-    // the sum reduced by one carry test (cur[u] - 2p is uniform)
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (r > lo + (uint32_t)u) x = add_lazy2p(shoup_lazy_v(x, m, mp, a.M.p), cur[u] - p2, p2);
-    r = rn;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) cur[u] = nxt[u];
-  }
-  a.Bc[(size_t)c * a.t + l] = x >= a.M.p ? x - a.M.p : x;
-}
-
 // Per-row scan over chunks: qstart[0] = 1, qstart[c] = m^L qstart[c-1] + B_{c-1}.
 __device__ __forceinline__ void vs_scan_body(const VsArgs& a, uint32_t l, uint64_t* __restrict__ qstart,
                                              uint64_t* __restrict__ mL_out) {
@@ -294,6 +266,48 @@ constexpr uint32_t kPcMaxTiles = 6;  // consumer waves per workgroup (at most)
 // workgroup barriers (which otherwise count as possible writers).
 template <class T>
 using const_as = const __attribute__((address_space(4))) T*;
+
+// Pass 1 for row l, chunk c < S-1: B_c = sum_{lo <= r < hi} M_r m^(r-lo), the
+// chain over the chunk started from 0, evaluated by baby steps and giant
+// steps.  With r - lo = K j + i (0 <= i < K),
+//   B_c = sum_j (m^K)^j s_j,   s_j = sum_i M_(lo+Kj+i) m^i:
+// the K powers m^i are made once per row and chunk (K Shoup products); each
+// s_j is an exact six-column sum of K products of the uniform M_r (22-bit
+// limbs, scalar) with the lane's powers, reduced once; the outer sum is Horner
+// in m^K.  About ten vector instructions per step instead of a Shoup product
+// and a reduction per step.
+constexpr int kChainK = 32;  // K: below kFold, so a block's columns never fold
+
+__device__ __forceinline__ void vs_chain_body(const VsArgs& a, uint32_t l, uint32_t c) {
+  uint32_t lo, hi;
+  chunk_range(a.t, a.L, c, lo, hi);
+  const zr_mod M = a.M;
+  const uint64_t m = a.mono[l], mp = a.mono_p[l];
+  const_as<uint64_t> Mc = (const_as<uint64_t>)a.Mc;  // uniform: the chunk is the block's
+  uint64_t pw[kChainK];
+  pw[0] = 1 % M.p;
+#pragma unroll
+  for (int i = 1; i < kChainK; ++i) pw[i] = zr_shoup(M, pw[i - 1], m, mp);
+  const uint64_t mK = zr_shoup(M, pw[kChainK - 1], m, mp), mKp = zr_shoup_pre(M, mK);
+  // s_j of the block starting at base: the top block may be partial (guarded
+  // loads), every other block is full
+  auto block = [&](uint32_t base, bool guard) {
+    Acc6 acc;
+    acc6_zero(acc);
+#pragma unroll
+    for (int i = 0; i < kChainK; ++i) {
+      const uint64_t Mr = (!guard || base + i < hi) ? Mc[base + i] : 0;
+      acc6_mac(acc, (uint32_t)pw[i], (uint32_t)(pw[i] >> 32), (uint32_t)(Mr & 0x3FFFFF),
+               (uint32_t)((Mr >> 22) & 0x3FFFFF), (uint32_t)(Mr >> 44));
+    }
+    return acc6_reduce(M, acc);
+  };
+  const uint32_t nfull = (hi - lo) / kChainK;
+  uint64_t y = 0;
+  if (lo + nfull * kChainK < hi) y = block(lo + nfull * kChainK, true);
+  for (uint32_t j = nfull; j-- > 0;) y = zr_add(M, zr_shoup(M, y, mK, mKp), block(lo + j * kChainK, false));
+  a.Bc[(size_t)c * a.t + l] = y;
+}
 
 // 64-byte group of a packed row as one vector (one scalar load)
 typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
