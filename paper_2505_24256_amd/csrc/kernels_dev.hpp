@@ -970,7 +970,7 @@ __device__ __forceinline__ void master_sum_body(const zr_mod& M, uint32_t t, uin
 // ---- Newton lift (eq. 1) ----------------------------------------------------------
 // g[d][l] = sum_i W[d][i] vals[i][l] for the 64 terms of row block rb and the
 // kNewtonDB coefficients d0..; Wl holds W as limbs [i][d][3].
-constexpr int kNewtonDB = 8;
+constexpr int kNewtonDB = 2;  // two coefficients per lane: enough waves to fill the device at t = 10^4
 
 __device__ __forceinline__ void newton_body(const zr_mod& M, uint32_t t, uint32_t D1, uint32_t rb, uint32_t d0,
                                             const uint64_t* __restrict__ vals, const uint32_t* __restrict__ Wl,
