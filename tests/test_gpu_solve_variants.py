@@ -98,17 +98,19 @@ def test_solve_singular_and_empty(zr, variant):
     assert st == 0 and got.size == 0
 
 
+@pytest.mark.parametrize("variant", ["producer_consumer", "mfma"])
 @pytest.mark.parametrize("t,R", [(10_000, 30), (20_000, 40)])
-def test_solve_large_sampled_rows(zr, t, R):
+def test_solve_large_sampled_rows(zr, variant, t, R):
     """Full-size systems (the n = 6 stage size and a larger one) with the
-    matrix-core pass: rows sampled and solved one by one by the oracle."""
+    default and the matrix-core pass: rows sampled and solved one by one by
+    the oracle."""
     p = synth.make_prime()
     g = synth.SplitMix64(t + R)
     m = g.uniform_block(1, p, t)
     assert len(set(int(x) for x in m)) == t
     rhs = g.uniform_block(0, p, t * R).reshape(R, t)
-    zr.solve_variant("mfma")
-    _note(f"solve mfma t={t} R={R}")
+    zr.solve_variant(variant)
+    _note(f"solve {variant} t={t} R={R}")
     got, st = zr.vandermonde_solve(p, m, rhs)
     assert st == 0
     rng = random.Random(t)
