@@ -46,6 +46,14 @@ INT8_OPS_PER_PRODUCT = 2 * 64
 DOTS_TRAFFIC = {"sources_sha16": "fd9e81cb21b229f1", "variant": "producer_consumer", "bytes_per_launch": 70.90e6}
 
 
+def _system_sizes(w):
+    """Sizes t of the Vandermonde systems of a reconstruction: the number of
+    distinct exponent prefixes of the hidden polynomial before each added
+    variable (stages 2..n)."""
+    e = np.asarray(w.hidden.exps)
+    return [int(len(np.unique(e[:, :k], axis=0))) for k in range(1, e.shape[1])]
+
+
 def _dots_sources_sha16() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -437,11 +445,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u64 mod p (63-bit prime), 128/192-bit integer intermediates",
+        "dtype": "u64",
+        "arithmetic": "residues mod a 63-bit prime in u64, exact 128/192-bit integer intermediates",
         "data": "synthetic",
         "config": {"workload": "plain polynomial Zippel, n=6, per-variable degree<=30, t=10^4 terms, uniform "
                                "distinct exponents, coefficients uniform mod a seeded 63-bit prime",
-                   "p": w.p, "stage_sizes": None, "parallelism": "single GPU"},
+                   "p": w.p, "system_sizes": _system_sizes(w), "right_hand_sides": int(w.deg[0]),
+                   "parallelism": "single GPU"},
         "reconstructions_per_s": round(steps / elapsed, 3),
         "vandermonde_terms_per_s": round(cnt["vsolve_terms"] * steps / elapsed, 1),
         "latency_ms": {"p50": round(statistics.median(lat) * 1e3, 3),
