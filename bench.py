@@ -43,7 +43,7 @@ INT8_OPS_PER_PRODUCT = 2 * 64
 # rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by the copy-probe calibration (0.5x
 # read, 1.0x write); see profiles/k_vs_dots_pc_n6_d30_t1e4_hbm_counters.md.
 # Valid only for the kernel sources and solve variant those counters were taken on.
-DOTS_TRAFFIC = {"sources_sha16": "fd9e81cb21b229f1", "variant": "producer_consumer", "bytes_per_launch": 70.90e6}
+DOTS_TRAFFIC = {"sources_sha16": "9c07805449d74c8d", "variant": "producer_consumer", "bytes_per_launch": 74.80e6}
 
 
 def _system_sizes(w):

@@ -89,7 +89,19 @@ VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
   uint32_t S;
   if (P.pc) {
     const uint32_t slots = std::max<uint32_t>(1, num_cus) * dots_pc_blocks_per_cu(P.RT, P.ntile);
-    S = std::max<uint32_t>(1, cdiv(4ull * slots, (uint64_t)row_blocks));
+    const uint32_t S0 = std::max<uint32_t>(1, cdiv(4ull * slots, (uint64_t)row_blocks));
+    // equal chunks make equal workgroups, which run in rounds of `slots`:
+    // among the chunk counts around S0 take the one whose last round is fullest
+    S = S0;
+    double best = 2.0;
+    for (uint32_t s = std::max<uint32_t>(1, S0 - S0 / 4); s <= S0 + S0 / 4; ++s) {
+      const uint64_t w = (uint64_t)row_blocks * s, rounds = (w + slots - 1) / slots;
+      const double idle = (double)(rounds * slots - w) / (double)w;
+      if (idle < best) {
+        best = idle;
+        S = s;
+      }
+    }
   } else {
     const uint32_t slots = std::max<uint32_t>(1, num_cus) * dots_waves_per_cu(P.RT);
     S = std::max<uint32_t>(1, cdiv(4ull * slots, (uint64_t)row_blocks * P.ntile));
