@@ -150,3 +150,25 @@ def test_reconstruct_mfma_config2_full(zr):
     _note("config2 full reconstruction, matrix-core pass")
     e, c = zr.reconstruct(w.p, w.deg, synth.DeviceBlackBox(w.hidden, nthreads=16), sched=w.schedule)
     assert np.array_equal(e, w.hidden.exps) and np.array_equal(c, w.hidden.coefs)
+
+
+def test_timing_dots_only(zr):
+    """zr_timing_enable(2) brackets only the solve's dot-product launches;
+    zr_timing_enable(1) every named launch."""
+    p = synth.make_prime()
+    m, rhs = _system(p, 700, 12, 3)
+    zr.solve_variant()
+    try:
+        zr.timing(True, dots_only=True)
+        zr.timing_reset()
+        got, st = zr.vandermonde_solve(p, m, rhs)
+        n_dots, ms_dots = zr.timing_get("vs_dots")
+        n_pack, _ = zr.timing_get("vs_pack")
+        assert st == 0 and n_dots == 1 and ms_dots > 0 and n_pack == 0
+        zr.timing(True)
+        zr.timing_reset()
+        zr.vandermonde_solve(p, m, rhs)
+        assert zr.timing_get("vs_dots")[0] == 1 and zr.timing_get("vs_pack")[0] == 1
+    finally:
+        zr.timing(False)
+    assert np.array_equal(got, oracle.vandermonde_solve(p, m, rhs))
