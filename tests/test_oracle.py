@@ -12,6 +12,7 @@ from sympy.functions.combinatorial.numbers import stirling
 
 import oracle
 import synth
+from balanced_cases import LimitBox, fallback_case
 
 P63 = (1 << 63) - 25          # largest prime below 2^63
 P61 = (1 << 61) - 1           # Mersenne prime
@@ -474,3 +475,51 @@ def test_blackbox_matches_bigint_evaluation():
                     want = (want + term) % p
                 assert int(vals[jj * 5 + ii]) == want
                 assert oracle.poly_eval(p, w.hidden.exps, w.hidden.coefs, pt) == want
+
+
+# ---------------------------------------------------------------- balancing-factor fallback (§2.2)
+#
+# The balancing factor of slice i is beta_i = N_{k-1}(y^i) / A_i(c_k), and
+# D_{k-1}(y^i) / B_i(c_k) when the numerator side vanishes.  These cases are
+# built from the schedule so that the numerator side vanishes exactly, which a
+# random input does with probability about deg/p.
+
+@pytest.mark.parametrize("seed", [4, 5, 6])
+def test_balanced_beta_fallback_slice(seed):
+    """Slice 1 takes the denominator-side factor; the result is still P/Q."""
+    p, dn, dd, sched, num, den = fallback_case(seed)
+    (en, cn), (ed, cd) = oracle.balanced_zippel(p, dn, dd, sched, synth.BlackBox(num, den))
+    assert np.array_equal(en, num.exps) and np.array_equal(cn, num.coefs)
+    assert np.array_equal(ed, den.exps) and np.array_equal(cd, den.coefs)
+
+
+def test_balanced_beta_fallback_every_slice():
+    """A zero numerator: N_{k-1} = 0 and A_i = 0 on every slice, so every
+    factor comes from the denominator side; 0/Q in lowest terms is 0/1."""
+    p = synth.make_prime()
+    rw = synth.rational_workload(3, 6, 5, 6, 17)
+    zero = synth.SparsePoly(p, 3, np.zeros((0, 3), dtype=np.uint16), np.zeros(0, dtype=np.uint64))
+    (en, cn), (ed, cd) = oracle.balanced_zippel(p, rw.deg_num, rw.deg_den, rw.schedule,
+                                               synth.BlackBox(zero, rw.den))
+    assert len(cn) == 0 and en.shape == (0, 3)
+    assert np.array_equal(ed, np.zeros((1, 3), dtype=np.uint16)) and list(cd) == [1]
+
+
+def test_balanced_both_sides_vanish_is_edegen():
+    """P and Q vanish together at (y1, c2), the anchor node of slice 1 at stage 2:
+    both balancing factors of that slice vanish.  Slice 1 has lost the common
+    factor x2 - c2 (its reduced fraction is the constant -y1 c2), so its
+    degrees differ from the other slices' and the stage reports EDEGEN; a
+    black box that evaluates P/Q without reducing fails there instead."""
+    p, dn, dd, sched, num, den = fallback_case(4, both_vanish=True)
+    y1, c2 = int(sched.y[0]), int(sched.anchor[1])
+    box = LimitBox(num, den, (-y1 * c2) % p)
+    with pytest.raises(oracle.OracleError) as ei:
+        oracle.balanced_zippel(p, dn, dd, sched, box.eval)
+    assert ei.value.code == oracle.EDEGEN
+    with pytest.raises(oracle.OracleError) as ei:
+        oracle.balanced_zippel(p, dn, dd, sched, synth.BlackBox(num, den))
+    assert ei.value.code == oracle.EBLACKBOX
+    # stage 1 alone (x2 at its anchor) is a regular fraction
+    (en, cn), (ed, cd) = oracle.balanced_zippel(p, dn, dd, sched, box.eval, last_stage=1)
+    assert len(cn) > 0 and len(cd) > 0
