@@ -1,13 +1,23 @@
 #!/usr/bin/env python
-"""Benchmark of the plain polynomial Zippel reconstruction on one MI355X.
+"""Benchmark of the Zippel reconstruction's hot path on one MI355X.
 
-Workload: synthetic sparse polynomial, n = 6 variables, per-variable degree
-<= 30, t = 10^4 terms with uniform distinct exponents, coefficients uniform
-mod a seeded 63-bit prime (hidden-polynomial seed 2, schedule seed 1002).
-One step = one full reconstruction (6 stages; Vandermonde systems of size up
-to 10^4 with 30 right-hand sides each, Newton lifts, expansions, 2 probes).
-The black box's samples are computed once on the host, recorded on the device
-and replayed (a device-to-device copy per stage) inside the timed region.
+Headline workload: the final stage of a large plain polynomial Zippel
+reconstruction, the quantity the paper times (§3.1, Table 3: the
+reconstruction over the last variable, 125k-4.8m skeleton terms).  Hidden
+sparse polynomial in n = 8 variables, per-variable degree <= 40, t = 5*10^5
+terms with uniform distinct exponents, coefficients uniform mod a seeded
+63-bit prime (hidden-polynomial seed 3, schedule seed 1003).  One step =
+stage 8 from the stage-7 result f(x_1..x_7, c_8): one transposed Vandermonde
+system of 5*10^5 unknowns with 40 right-hand sides (master polynomial,
+synthetic-division dot products, inverse and scaling), the Newton lift of
+every term over 41 nodes, the expansion into the final skeleton, and the two
+probe checks.  The black box's samples are computed once on the device,
+recorded and replayed (a device-to-device copy per call) inside the timed
+region.
+
+Further legs, reported under their own keys: the n = 6, t = 10^4 whole
+reconstruction; 4096 batched reconstructions against one at a time; served
+rational requests with Poisson arrivals.
 
 Prints one JSON line.  ``--microbench`` instead prints the throughput probes
 used for the roofline (see include/zippel_microbench.h).
@@ -16,6 +26,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import statistics
 import sys
@@ -35,15 +46,14 @@ if ROOT not in sys.path:
 CU, SIMD, LANES, CLOCK_GHZ = 256, 4, 16, 2.4
 MUL32_PEAK_TOPS = CU * SIMD * LANES * CLOCK_GHZ * 1e9 / 1e12
 MUL32_PER_MULMOD = 4
-# MI355X dense int8 matrix-core peak (no sparsity)
-INT8_PEAK_TOPS = 5000.0
-INT8_OPS_PER_PRODUCT = 2 * 64
 
-# HBM bytes per launch of the dominant solve kernel on this workload, from
-# rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by the copy-probe calibration (0.5x
-# read, 1.0x write); see profiles/k_vs_dots_pc_n6_d30_t1e4_hbm_counters.md.
-# Valid only for the kernel sources and solve variant those counters were taken on.
-DOTS_TRAFFIC = {"sources_sha16": "9c07805449d74c8d", "variant": "producer_consumer", "bytes_per_launch": 74.80e6}
+# HBM bytes per launch of the dominant solve kernel on the headline workload,
+# from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by the copy-probe calibration
+# (profiles/k_vs_dots_pc_n8_d40_t5e5_hbm_counters.md).  Valid only for the
+# kernel sources the counters were taken on (None: not measured for them).
+DOTS_TRAFFIC = {"sources_sha16": None, "bytes_per_launch": None}
+
+HEADLINE_STAGE = 8  # the last variable of the n = 8 workload
 
 
 def _system_sizes(w):
@@ -241,8 +251,8 @@ def served(zr, synth, args, stream):
             now = time.perf_counter() - t0
             while sub < len(ws) and arrivals[sub] <= now:
                 w = ws[sub]
-                rid = srv.submit(w.deg_num, recs[sub], sched=w.schedule, deg_den=w.deg_den,
-                                 expected_terms=max(w.num.nterms, w.den.nterms))
+                # no size hint: the server sizes each request from the skeletons it has reached
+                rid = srv.submit(w.deg_num, recs[sub], sched=w.schedule, deg_den=w.deg_den)
                 ids[rid] = sub
                 sub += 1
             st = srv.stats()
@@ -293,25 +303,157 @@ def served(zr, synth, args, stream):
     }
 
 
+def headline(zr, synth, args, stream):
+    """The final stage of the n = 8, t = 5*10^5 reconstruction (see the module
+    docstring): recording run, warm-up steps with every named launch timed,
+    then the timed steps with HIP events around the dot-product launches."""
+    import torch
+    t0 = time.perf_counter()
+    w = synth.config_workload(3)
+    k = HEADLINE_STAGE
+    start = synth.stage_result(w.hidden, w.schedule.anchor, k - 1)
+    _progress(f"headline workload generated in {time.perf_counter() - t0:.1f} s: stage {k} from a "
+              f"{len(start[1])}-term skeleton")
+    rec = zr.Recorder(synth.DeviceBlackBox(w.hidden, nthreads=args.cpu_threads))
+
+    def step():
+        zr.lib().zr_recorder_rewind(rec.handle)
+        return zr.reconstruct(w.p, w.deg, rec, sched=w.schedule, stream=stream, first_stage=k, start=start)
+
+    # recording run (device black box): also checks the result
+    t0 = time.perf_counter()
+    e, c = zr.reconstruct(w.p, w.deg, rec, sched=w.schedule, stream=stream, first_stage=k, start=start)
+    exact = bool(np.array_equal(e, w.hidden.exps) and np.array_equal(c, w.hidden.coefs))
+    _progress(f"recorded in {time.perf_counter() - t0:.1f} s; bit exact {exact}")
+    if not exact:
+        print("bench.py: the final stage does not reproduce the hidden polynomial", file=sys.stderr)
+        sys.exit(3)
+    rec.replay(True)
+    zr.timing(True)
+    zr.timing_reset()
+    for i in range(args.warmup):
+        step()
+        _progress(f"warm-up step {i + 1}/{args.warmup}")
+    cnt = zr.last_counters()
+    torch.cuda.synchronize()
+    zr.timing(False)
+    kernels = {}
+    for name in ("mono", "master", "vs_pack", "vs_chain", "vs_scan", "vs_dots", "vs_finish", "newton", "scan",
+                 "expand"):
+        n, ms = zr.timing_get(name)
+        if n:
+            kernels[name] = {"launches": n, "ms_total": round(ms, 3)}
+    zr.timing(True, dots_only=True)
+    zr.timing_reset()
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        e, c = step()
+        lat.append(time.perf_counter() - ts)
+        _progress(f"step {i + 1}/{args.steps}: {lat[-1] * 1e3:.1f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    zr.timing(False)
+    exact = exact and bool(np.array_equal(e, w.hidden.exps) and np.array_equal(c, w.hidden.coefs))
+    n_dots, ms_dots = zr.timing_get("vs_dots")
+    return {"w": w, "start": start, "cnt": cnt, "elapsed": elapsed, "lat": lat, "exact": exact,
+            "n_dots": n_dots, "ms_dots": ms_dots, "kernels": kernels}
+
+
+def config2_leg(zr, synth, args, stream):
+    """Whole reconstruction of the n = 6, per-variable degree 30, t = 10^4
+    polynomial (six stages, systems up to 10^4 unknowns with 30 right-hand
+    sides), samples recorded once and replayed."""
+    import torch
+    w = synth.config_workload(2)
+    rec = zr.Recorder(synth.DeviceBlackBox(w.hidden, nthreads=args.cpu_threads))
+    e, c = zr.reconstruct(w.p, w.deg, rec, sched=w.schedule, stream=stream)
+    exact = bool(np.array_equal(e, w.hidden.exps) and np.array_equal(c, w.hidden.coefs))
+    rec.replay(True)
+    for _ in range(2):
+        zr.lib().zr_recorder_rewind(rec.handle)
+        zr.reconstruct(w.p, w.deg, rec, sched=w.schedule, stream=stream)
+    cnt = zr.last_counters()
+    zr.timing(True, dots_only=True)
+    zr.timing_reset()
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.config2_steps):
+        ts = time.perf_counter()
+        zr.lib().zr_recorder_rewind(rec.handle)
+        e, c = zr.reconstruct(w.p, w.deg, rec, sched=w.schedule, stream=stream)
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    zr.timing(False)
+    exact = exact and bool(np.array_equal(e, w.hidden.exps) and np.array_equal(c, w.hidden.coefs))
+    n_dots, ms_dots = zr.timing_get("vs_dots")
+    steps = args.config2_steps
+    alu = cnt["solve_mulmods"] * steps * MUL32_PER_MULMOD / (ms_dots / 1e3) / 1e12 if ms_dots else 0.0
+    return {"workload": "plain polynomial Zippel, whole reconstruction, n=6, per-variable degree<=30, t=10^4",
+            "system_sizes": _system_sizes(w), "right_hand_sides": int(w.deg[0]),
+            "mulmod_per_s": round(cnt["mulmods"] * steps / el, 1), "ms_per_reconstruction": round(el / steps * 1e3, 3),
+            "reconstructions_per_s": round(steps / el, 3),
+            "latency_ms": {"p50": round(statistics.median(lat) * 1e3, 3),
+                           "p99": round(float(np.percentile(lat, 99)) * 1e3, 3)},
+            "solve_kernel": {"kernel": "k_vs_dots_pc", "achieved_TOPs": round(alu, 3),
+                             "frac_of_derived_peak": round(alu / MUL32_PEAK_TOPS, 4),
+                             "avg_launch_ms": round(ms_dots / n_dots, 4) if n_dots else None},
+            "mulmods_per_reconstruction": cnt["mulmods"], "steps": steps, "bit_exact": exact}
+
+
+def cpu_baseline(zr, synth, args, stream, W_step):
+    """The oracle's transposed Vandermonde solve (master polynomial, synthetic
+    division and dot products, inverse and scaling; unsigned __int128 products
+    reduced with %) on a bounded sample of the headline's operation mix: one
+    system of t = 2*10^4 random distinct monomial values with 40 right-hand
+    sides.  Its cost grows as t^2 like the headline's, so its mulmod/s is
+    the comparable rate; the full step's oracle time is extrapolated from it."""
+    import oracle
+    nthr = max(1, min(args.cpu_threads, os.cpu_count() or 1))
+    t, R = args.cpu_sample_t, 40
+    p = synth.make_prime()
+    g = synth.SplitMix64(77)
+    m = g.uniform_block(1, p, t)
+    assert len(set(int(x) for x in m)) == t
+    rhs = g.uniform_block(0, p, t * R).reshape(R, t)
+    tc = time.perf_counter()
+    want = oracle.vandermonde_solve(p, m, rhs, nthreads=nthr)
+    tcpu = time.perf_counter() - tc
+    got, st = zr.vandermonde_solve(p, m, rhs, stream=stream)
+    W = R * t * t + 2 * t * (t - 1) + t * (t - 1) // 2 + t * (R + 3)
+    rate = W / tcpu
+    return {"value": round(rate, 1), "unit": "mulmod/s", "cores": nthr, "kind": "oracle",
+            "sample": f"the oracle's transposed Vandermonde solve of one t={t}, R={R} system with random distinct "
+                      "monomial values (the headline step's operation mix at a size the oracle finishes in seconds; "
+                      "cost grows as t^2 in both); unsigned __int128 products reduced with %, OpenMP over rows",
+            "seconds": round(tcpu, 2), "matches_gpu": bool(st == 0 and np.array_equal(got, want)),
+            "extrapolated_step_seconds": round(W_step / rate, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--microbench", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=16)
+    ap.add_argument("--cpu-sample-t", type=int, default=20_000)
+    ap.add_argument("--no-config2", action="store_true", help="skip the n = 6, t = 10^4 whole reconstruction")
+    ap.add_argument("--config2-steps", type=int, default=10)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain measurement")
     ap.add_argument("--batch-instances", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--no-serve", action="store_true", help="skip the served-form measurement")
-    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-slots", type=int, default=256)
     ap.add_argument("--serve-budget-gib", type=int, default=16)
-    ap.add_argument("--time-all-kernels", action="store_true",
-                    help="bracket every named launch of the timed steps with HIP events (default: the dot-product pass only)")
-    ap.add_argument("--solve-variant", default="producer_consumer", choices=["waves", "producer_consumer", "mfma"],
-                    help="dot-product pass of the one-system solve (mfma: the opt-in int8 matrix-core pass)")
+    ap.add_argument("--solve-variant", default="producer_consumer", choices=["waves", "producer_consumer"],
+                    help="dot-product pass of the one-system solve")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; the reconstruction of independent instances would "
@@ -331,111 +473,48 @@ def main():
         print(json.dumps({"microbench": microbench(zr)}), flush=True)
         return
 
-    w = synth.config_workload(2)
-    cache = CachingBox(synth.BlackBox(w.hidden, nthreads=args.cpu_threads))
-    rec = zr.Recorder(zr.HostBlackBox(cache.eval, w.hidden.nvars))
     stream = torch.cuda.current_stream()
-
-    # recording run: also checks the result against the hidden polynomial
-    e, c = zr.reconstruct(w.p, w.deg, rec, sched=w.schedule, stream=stream)
-    exact = bool(np.array_equal(e, w.hidden.exps) and np.array_equal(c, w.hidden.coefs))
-    if not exact:
-        print("bench.py: reconstruction does not match the hidden polynomial", file=sys.stderr)
-        sys.exit(3)
-    rec.replay(True)
-    # warm-up steps: every named launch timed, for the per-kernel breakdown
-    zr.timing(True)
-    zr.timing_reset()
-    for _ in range(args.warmup):
-        zr.lib().zr_recorder_rewind(rec.handle)
-        zr.reconstruct(w.p, w.deg, rec, sched=w.schedule, stream=stream)
-    cnt = zr.last_counters()
-    torch.cuda.synchronize()
-    zr.timing(False)
-    kernels = {}
-    for name in ("master", "vs_pack", "vs_chain", "vs_scan", "vs_dots", "vs_finish", "newton", "scan", "expand"):
-        n, ms = zr.timing_get(name)
-        if n:
-            kernels[name] = {"launches": n, "ms_total": round(ms, 3)}
-
-    # timed steps: HIP events around the dot-product launches only (events
-    # around every launch add host work between launches), unless asked
-    zr.timing(True, dots_only=not args.time_all_kernels)
-    zr.timing_reset()
-    lat = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        zr.lib().zr_recorder_rewind(rec.handle)
-        e, c = zr.reconstruct(w.p, w.deg, rec, sched=w.schedule, stream=stream)
-        lat.append(time.perf_counter() - ts)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    zr.timing(False)
-    exact = exact and bool(np.array_equal(e, w.hidden.exps) and np.array_equal(c, w.hidden.coefs))
-
-    n_dots, ms_dots = zr.timing_get("vs_dots")
-    steps = args.steps
+    H = headline(zr, synth, args, stream)
+    w, cnt, steps, elapsed = H["w"], H["cnt"], args.steps, H["elapsed"]
+    t_sys = len(H["start"][1])
+    R = int(w.deg[HEADLINE_STAGE - 1])
     mulmods = cnt["mulmods"] * steps
     value = mulmods / elapsed
-    solve_alg = cnt["solve_mulmods"] * steps          # R t^2 + 2 t (t-1) per system: what vs_dots computes
+    n_dots, ms_dots = H["n_dots"], H["ms_dots"]
+    solve_alg = cnt["solve_mulmods"] * steps          # R t^2 + 2 t (t-1): what the dot-product pass computes
     achieved_mulmod_s = solve_alg / (ms_dots / 1e3) if ms_dots else 0.0
     alu = achieved_mulmod_s * MUL32_PER_MULMOD / 1e12
     traffic = (DOTS_TRAFFIC["bytes_per_launch"]
-               if _dots_sources_sha16() == DOTS_TRAFFIC["sources_sha16"] and DOTS_TRAFFIC["variant"] == args.solve_variant
+               if DOTS_TRAFFIC["sources_sha16"] == _dots_sources_sha16() and args.solve_variant == "producer_consumer"
                else None)
-    common = {"traffic": traffic, "traffic_unit": "bytes per launch (HBM, rocprofv3 counters, calibrated)",
-              "launches_per_step": n_dots // steps if steps else 0,
-              "avg_launch_ms": round(ms_dots / n_dots, 4) if n_dots else None}
     # measured ceiling of the 32x32->64-bit multiply: the v_mad_u64_u32 probe
     # (independent streams at full occupancy), run here on the same GPU
     mad_ms, mad_ops = zr.microbench("mad_u64_u32", blocks=2048, iters=4096)
     mad_peak = mad_ops / mad_ms / 1e9 if mad_ms > 0 else None
-    if args.solve_variant == "mfma":
-        # the R t^2 dot products run on the int8 matrix cores: one 63x63-bit
-        # product is 64 digit products (8 x 8 signed base-256 digits), two ops each
-        dots = cnt["dot_products"] * steps
-        achieved = dots * INT8_OPS_PER_PRODUCT / (ms_dots / 1e3) / 1e12 if ms_dots else 0.0
-        roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": INT8_PEAK_TOPS,
-                    "unit": "TOP/s (int8 MFMA ops; one 64x64-bit product = 64 digit products = 128 ops)",
-                    "frac": round(achieved / INT8_PEAK_TOPS, 4), **common, "kernel": "k_vs_mfma",
-                    "alu_equivalent": {"achieved": round(alu, 3), "peak": round(MUL32_PEAK_TOPS, 3),
-                                       "frac": round(alu / MUL32_PEAK_TOPS, 4),
-                                       "unit": "TOP/s of 32x32-bit multiplies at 4 per modular product (whole solve work)"}}
-    else:
-        roofline = {"bound": "alu", "achieved": round(alu, 3), "peak": round(MUL32_PEAK_TOPS, 3),
-                    "unit": "TOP/s (32x32-bit multiplies; one 64x64-bit modular product or multiply-accumulate = 4)",
-                    "frac": round(alu / MUL32_PEAK_TOPS, 4), **common,
-                    "kernel": "k_vs_dots_pc" if args.solve_variant == "producer_consumer" else "k_vs_dots"}
-    roofline["measured_mul32_peak"] = {
-        "value": round(mad_peak, 3) if mad_peak else None, "unit": "TOP/s",
-        "probe": "v_mad_u64_u32, 8 independent chains per lane, 2048 x 256 threads, this GPU, this run",
-        "frac": round(alu / mad_peak, 4) if mad_peak else None}
+    roofline = {"bound": "alu", "achieved": round(alu, 3), "peak": round(MUL32_PEAK_TOPS, 3),
+                "unit": "TOP/s (32x32-bit multiplies; one 64x64-bit modular product or multiply-accumulate = 4)",
+                "frac": round(alu / MUL32_PEAK_TOPS, 4), "traffic": traffic,
+                "traffic_unit": "bytes per launch (HBM, rocprofv3 counters, calibrated)",
+                "kernel": "k_vs_dots_pc" if args.solve_variant == "producer_consumer" else "k_vs_dots",
+                "launches_per_step": n_dots // steps if steps else 0,
+                "avg_launch_ms": round(ms_dots / n_dots, 3) if n_dots else None,
+                "work_per_launch": "4 (R t^2 + 2 t (t-1)) 32x32-bit multiplies, t = %d, R = %d" % (t_sys, R),
+                "measured_mul32_peak": {
+                    "value": round(mad_peak, 3) if mad_peak else None, "unit": "TOP/s",
+                    "probe": "v_mad_u64_u32, 8 independent chains per lane, 2048 x 256 threads, this GPU, this run",
+                    "frac": round(alu / mad_peak, 4) if mad_peak else None}}
+    _progress("headline measured")
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        nthr = max(1, min(args.cpu_threads, os.cpu_count() or 1))
-        tc = time.perf_counter()
-        oe, oc = oracle.zippel(w.p, w.deg, w.schedule, cache.eval, nthreads=nthr)
-        tcpu = time.perf_counter() - tc
-        same = bool(np.array_equal(oe, e) and np.array_equal(oc, c))
-        cpu = {"value": round(cnt["mulmods"] / tcpu, 1), "unit": "mulmod/s", "cores": nthr, "kind": "oracle",
-               "sample": "one full reconstruction of the same workload (all 6 stages) with the black box's "
-                         "samples served from the host cache; unsigned __int128 products reduced with %",
-               "seconds": round(tcpu, 2), "matches_gpu": same}
-
-    batch = None
-    _progress("plain configuration measured")
-    if not args.no_batch:
-        batch = batched_vs_plain(zr, synth, args, stream)
-    serve = None
-    if not args.no_serve:
-        serve = served(zr, synth, args, stream)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(zr, synth, args, stream, cnt["mulmods"])
+    _progress("cpu baseline done")
+    c2 = None if args.no_config2 else config2_leg(zr, synth, args, stream)
+    _progress("n=6 leg done")
+    batch = None if args.no_batch else batched_vs_plain(zr, synth, args, stream)
+    serve = None if args.no_serve else served(zr, synth, args, stream)
 
     out = {
-        "metric": "mulmod/s (algorithmic modular products per second, whole reconstruction)",
+        "metric": "mulmod/s (algorithmic modular products per second, final Zippel stage of a 5*10^5-term "
+                  "reconstruction, bit-exact)",
         "value": round(value, 1),
         "unit": "mulmod/s",
         "n_gpus": 1,
@@ -448,19 +527,21 @@ def main():
         "dtype": "u64",
         "arithmetic": "residues mod a 63-bit prime in u64, exact 128/192-bit integer intermediates",
         "data": "synthetic",
-        "config": {"workload": "plain polynomial Zippel, n=6, per-variable degree<=30, t=10^4 terms, uniform "
-                               "distinct exponents, coefficients uniform mod a seeded 63-bit prime",
-                   "p": w.p, "system_sizes": _system_sizes(w), "right_hand_sides": int(w.deg[0]),
+        "config": {"workload": "plain polynomial Zippel, n=8, per-variable degree<=40, t=5*10^5 terms, uniform "
+                               "distinct exponents, coefficients uniform mod a seeded 63-bit prime; step = the final "
+                               "stage (x_8) from the stage-7 result",
+                   "p": w.p, "system_size": t_sys, "right_hand_sides": R, "final_terms": int(w.hidden.nterms),
                    "parallelism": "single GPU"},
-        "reconstructions_per_s": round(steps / elapsed, 3),
+        "stages_per_s": round(steps / elapsed, 4),
         "vandermonde_terms_per_s": round(cnt["vsolve_terms"] * steps / elapsed, 1),
-        "latency_ms": {"p50": round(statistics.median(lat) * 1e3, 3),
-                       "p99": round(float(np.percentile(lat, 99)) * 1e3, 3)},
-        "bit_exact": exact,
+        "latency_ms": {"p50": round(statistics.median(H["lat"]) * 1e3, 3),
+                       "p99": round(float(np.percentile(H["lat"], 99)) * 1e3, 3)},
+        "bit_exact": H["exact"],
         "mulmods_per_step": cnt["mulmods"],
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "kernels_warmup": {"steps": args.warmup, "per_kernel": kernels},
+        "kernels_warmup": {"steps": args.warmup, "per_kernel": H["kernels"]},
+        "config2": c2,
         "batch": batch,
         "serve": serve,
     }

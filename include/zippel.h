@@ -113,6 +113,12 @@ typedef struct {
   uint32_t nprobes;          /* random-point checks of the final result (0 = off) */
   const uint64_t* probes;    /* [nprobes][nvars] or NULL (then derived from seed) */
   uint32_t last_stage;       /* 0 = all; L stops after stage L and returns f(x_1..x_L, anchors) */
+  uint32_t first_stage;      /* 0 or 1: start at stage 1.  k >= 2 (polynomial path only): resume at
+                                stage k from `start`, the result of stage k-1 of the same schedule */
+  const zr_poly* start;      /* first_stage = k >= 2: f(x_1..x_{k-1}, anchors) as zippel_reconstruct
+                                returns it with last_stage = k-1 (host; exponents of x_k..x_n zero,
+                                e_v <= deg[v], terms distinct and lexicographically ascending,
+                                coefficients < p); otherwise ignored.  Copied before the call returns. */
 } zr_params;
 
 /* Number of nodes beyond the anchor that the balanced path needs for a variable
@@ -210,15 +216,14 @@ zr_status vandermonde_solve_batch(size_t nsys, uint64_t p, const uint64_t* d_sys
 zr_status zippel_reconstruct_batch(uint32_t n, const zr_params* params, zr_blackbox_fn bb, void* const* ctx,
                                    hipStream_t stream, zr_poly* out, int32_t* status);
 
-/* Dot-product pass of the one-system solve (§2.2, the O(t^2 R) sums):
- * 0 one wave per tile of right-hand sides, each running the synthetic
- * division chain with carry-free 64-bit multiply-accumulates; 1 (default) a
- * producer wave runs the chain once per row block and publishes it through
- * LDS to one consumer wave per tile (systems with at most 10 right-hand sides
- * run as 0); 2 (opt-in) the sums as exact int8 matrix products on the matrix
- * cores (signed base-256 digits of both factors, int32 accumulation).  Other
- * values select the default.  Same results for all. */
-void zr_solve_variant(int variant);
+/* Dot-product pass of the one-system solve (§2.2, the O(t^2 R) sums), both on
+ * the integer vector ALU: 0 one wave per tile of right-hand sides, each
+ * running the synthetic division chain with carry-free 64-bit
+ * multiply-accumulates; 1 (default) a producer wave runs the chain once per
+ * row block and publishes it through LDS to one consumer wave per tile
+ * (systems with at most 10 right-hand sides run as 0).  Same results for
+ * both.  Any other value returns ZR_EINVAL and leaves the choice unchanged. */
+zr_status zr_solve_variant(int variant);
 
 /* Graph mode of the batched paths (zippel_reconstruct_batch, the server,
  * vandermonde_solve_batch): with on != 0 each stage's device-side solve
@@ -249,8 +254,11 @@ zr_status zr_tuning_set(const zr_band_choice* table);
 /* Served form.  Reconstruction requests arrive over time (the coefficients of a
  * modular reduction stream out one by one, Introduction); the server admits
  * them first come, first served while a slot is free and the sum of the
- * admitted requests' estimated device footprints stays within hbm_budget bytes
- * (a request above the budget still runs when nothing else is active).  Each
+ * active requests' estimated device footprints stays within hbm_budget bytes
+ * (a request above the budget still runs when nothing else is active).  A
+ * request's estimate covers its next stage and is recomputed after every step
+ * from the sizes of the skeletons it has reached, so requests are admitted by
+ * what they hold now, not by a guess of their final size.  Each
  * zr_server_step advances every active request by one stage, batching the
  * stage's Vandermonde solves, Newton matrices and lifts of all of them into one
  * launch sequence, so requests admitted at a step boundary share the device
@@ -262,7 +270,7 @@ typedef struct zr_server zr_server;
 
 typedef struct {
   uint64_t submitted, admitted, completed, failed, steps;
-  uint64_t footprint, peak_footprint;  /* bytes of admitted requests (estimates) */
+  uint64_t footprint, peak_footprint;  /* bytes of the active requests' next stages (estimates) */
   uint64_t active, pending, peak_active;
 } zr_server_stats;
 
@@ -271,9 +279,11 @@ zr_status zr_server_create(zr_server** srv, uint64_t p, uint64_t hbm_budget, uin
 void zr_server_destroy(zr_server* srv);
 /* Queue a request: polynomial (balanced = 0) or rational (balanced = 1) with
  * the parameters of zippel_reconstruct / zippel_balanced_reconstruct (copied;
- * params may be released on return).  expected_terms sizes the footprint
- * estimate (0: the degree bounds' monomial count).  The black box is called
- * with ctx from zr_server_step.  *id receives the request's handle. */
+ * params may be released on return).  expected_terms caps the skeleton size
+ * that a footprint estimate assumes for the stage ahead (0: the degree bounds'
+ * monomial count).  The black box is called with ctx from zr_server_step.
+ * *id receives the request's handle.  Resumption (first_stage >= 2) is not
+ * served: ZR_EINVAL. */
 zr_status zr_server_submit(zr_server* srv, const zr_params* params, int balanced, uint64_t expected_terms,
                            zr_blackbox_fn bb, void* ctx, uint64_t* id);
 /* Admit what fits, advance every active request by one stage, retire the

@@ -58,7 +58,8 @@ class ZrParams(ctypes.Structure):
     _fields_ = [("p", ctypes.c_uint64), ("nvars", ctypes.c_uint32), ("deg", ctypes.c_void_p),
                 ("deg_den", ctypes.c_void_p), ("seed", ctypes.c_uint64), ("y", ctypes.c_void_p),
                 ("anchor", ctypes.c_void_p), ("nodes", ctypes.c_void_p), ("nnodes", ctypes.c_void_p),
-                ("nprobes", ctypes.c_uint32), ("probes", ctypes.c_void_p), ("last_stage", ctypes.c_uint32)]
+                ("nprobes", ctypes.c_uint32), ("probes", ctypes.c_void_p), ("last_stage", ctypes.c_uint32),
+                ("first_stage", ctypes.c_uint32), ("start", ctypes.c_void_p)]
 
 
 class ZrBandChoice(ctypes.Structure):
@@ -114,7 +115,6 @@ def lib():
                                                vp]
         L.zr_autotune.argtypes = [u64, vp, ctypes.POINTER(ZrBandChoice)]
         L.zr_solve_variant.argtypes = [i32]
-        L.zr_solve_variant.restype = None
         L.zr_batch_graphs.argtypes = [i32]
         L.zr_batch_graphs.restype = None
         L.zr_server_create.argtypes = [ctypes.POINTER(vp), u64, u64, u32, vp]
@@ -315,9 +315,23 @@ def _box_args(box):
 
 
 def reconstruct(p: int, deg: Sequence[int], box, sched=None, seed: int = 0, nprobes: Optional[int] = None,
-                last_stage: int = 0, stream=None):
-    """Polynomial Zippel on the GPU.  Returns (exps [nterms][nvars] uint16, coefs uint64)."""
+                last_stage: int = 0, stream=None, first_stage: int = 0, start=None):
+    """Polynomial Zippel on the GPU.  Returns (exps [nterms][nvars] uint16, coefs uint64).
+
+    With first_stage = k >= 2 the reconstruction resumes at stage k from
+    start = (exps, coefs), the result of stage k-1 (what this function returns
+    with last_stage = k-1 on the same schedule)."""
     h = _ParamsHolder(p, deg, None, sched, seed, nprobes, last_stage)
+    if first_stage > 1:
+        if start is None:
+            raise ValueError("first_stage >= 2 needs the previous stage's result as start=(exps, coefs)")
+        h.start_exps = np.ascontiguousarray(np.asarray(start[0], dtype=np.uint16).reshape(-1, len(deg)))
+        h.start_coefs = _u64(start[1])
+        h.start = ZrPoly(len(deg), len(h.start_coefs),
+                         h.start_exps.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
+                         h.start_coefs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+        h.s.first_stage = first_stage
+        h.s.start = ctypes.cast(ctypes.pointer(h.start), ctypes.c_void_p)
     out = ZrPoly()
     fn, ctx = _box_args(box)
     st = lib().zippel_reconstruct(ctypes.byref(h.s), fn, ctx, _stream(stream), ctypes.byref(out))
@@ -395,15 +409,16 @@ def autotune(p: int, stream=None):
     return [(t.packed, t.min_chunk) for t in tab]
 
 
-SOLVE_VARIANTS = {"waves": 0, "producer_consumer": 1, "mfma": 2}
+SOLVE_VARIANTS = {"waves": 0, "producer_consumer": 1}
 DEFAULT_SOLVE_VARIANT = "producer_consumer"
 
 
 def solve_variant(variant=DEFAULT_SOLVE_VARIANT):
     """Select the dot-product pass of the one-system solve (zr_solve_variant):
-    "waves", "producer_consumer" (the default; integer vector ALU) or "mfma"
-    (opt-in, int8 matrix cores)."""
-    lib().zr_solve_variant(SOLVE_VARIANTS[variant])
+    "waves" or "producer_consumer" (the default), both on the integer vector ALU."""
+    st = lib().zr_solve_variant(SOLVE_VARIANTS[variant])
+    if st != ZR_OK:
+        raise ZippelError(st, "zr_solve_variant")
 
 
 def batch_graphs(on: bool):

@@ -80,6 +80,7 @@ static void reconstruct_batch(uint32_t n, const zr_params* params, zr_blackbox_f
   for (uint32_t i = 0; i < n; ++i) {
     try {
       P[i].reset(new Params(&params[i], false));
+      if (P[i]->first > 1) throw Error(ZR_EINVAL);  // resumption is a one-reconstruction feature
       st[i] = ZR_OK;
     } catch (const Error& e) {
       st[i] = e.code;
@@ -312,6 +313,20 @@ zr_status vandermonde_solve_batch(size_t nsys, uint64_t p, const uint64_t* d_sys
     return ZR_OK;
   } catch (const Error& e) {
     return (zr_status)e.code;
+  } catch (const std::bad_alloc&) {
+    note_error("host allocation failed");
+    return ZR_ENOMEM;
+  } catch (...) {
+    note_error("unexpected exception");
+    return ZR_EDEVICE;
+  }
+}
+
+// Whole-batch failure: no outputs, every instance carries the error.
+static void fail_all(uint32_t n, zr_poly* out, int32_t* status, int code) {
+  for (uint32_t i = 0; i < n; ++i) {
+    zr_poly_free(&out[i]);
+    status[i] = code;
   }
 }
 
@@ -324,11 +339,16 @@ zr_status zippel_reconstruct_batch(uint32_t n, const zr_params* params, zr_black
     reconstruct_batch(n, params, bb, ctx, stream, out, status);
     return ZR_OK;
   } catch (const Error& e) {
-    for (uint32_t i = 0; i < n; ++i) {
-      zr_poly_free(&out[i]);
-      status[i] = e.code;
-    }
+    fail_all(n, out, status, e.code);
     return (zr_status)e.code;
+  } catch (const std::bad_alloc&) {
+    note_error("host allocation failed");
+    fail_all(n, out, status, ZR_ENOMEM);
+    return ZR_ENOMEM;
+  } catch (...) {
+    note_error("unexpected exception");
+    fail_all(n, out, status, ZR_EDEVICE);
+    return ZR_EDEVICE;
   }
 }
 
@@ -339,6 +359,12 @@ zr_status zr_autotune(uint64_t p, hipStream_t stream, zr_band_choice* table) {
     autotune(zr_mod_make(p), stream);
   } catch (const Error& e) {
     return (zr_status)e.code;
+  } catch (const std::bad_alloc&) {
+    note_error("host allocation failed");
+    return ZR_ENOMEM;
+  } catch (...) {
+    note_error("unexpected exception");
+    return ZR_EDEVICE;
   }
   if (table) zr_tuning_get(table);
   return ZR_OK;

@@ -124,11 +124,15 @@ __global__ void __launch_bounds__(64 * (1 + kPcMaxTiles))
   }
 }
 
-__global__ void k_b_delta(uint32_t n, const uint32_t* __restrict__ prefix, const BSolve* __restrict__ sys) {
+// one block of kDeltaBlock rows of one system (the row segments are counted
+// in blocks of 256 = kDeltaBlock rows)
+__global__ void __launch_bounds__(kDeltaBlock) k_b_delta(uint32_t n, const uint32_t* __restrict__ prefix,
+                                                         const BSolve* __restrict__ sys) {
+  __shared__ uint64_t sh[kDeltaBlock / 64 + 1];
   const uint32_t s = seg_find(prefix, n, blockIdx.x);
   const BSolve& b = sys[s];
-  const uint32_t l = (blockIdx.x - prefix[s]) * blockDim.x + threadIdx.x;
-  if (l < b.a.t) vs_delta_body(b.a, l, b.mL, b.winv, b.status);
+  const uint32_t l = (blockIdx.x - prefix[s]) * kDeltaBlock + threadIdx.x;
+  vs_delta_block(b.a, l, b.mL, b.winv, b.status, sh);
 }
 
 __global__ void k_b_scale(uint32_t n, const uint32_t* __restrict__ prefix, const BSolve* __restrict__ sys) {
@@ -716,19 +720,6 @@ void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs_in, hipStr
   std::vector<SolveJob> jobs;
   for (const auto& j : jobs_in) {
     if (!j.t || !j.R) continue;
-    if (j.t >= kBatchOwnSolveMinT && vsolve_beats_queue()) {
-      // a large system fills the device on its own: the one-system solve, with
-      // its faster dot-product pass (outside any graph capture)
-      DevArena A(s);
-      uint64_t* Mc = A.alloc<uint64_t>(j.t);
-      uint64_t* tmp = A.alloc<uint64_t>(master_tmp_words(j.t));
-      check(master_poly(M, j.t, j.mono, Mc, tmp, s));
-      const VsolvePlan P = vsolve_plan(j.t, j.R, device_cus());
-      uint64_t* work = A.alloc<uint64_t>(vsolve_workspace_words(P));
-      check(vsolve(M, P, j.mono, Mc, j.rhs, j.t, j.rhs, j.t, work, j.status, s));
-      count_solve(j.t, j.R);
-      continue;
-    }
     jobs.push_back(j);
   }
   if (jobs.empty()) return;
@@ -822,7 +813,7 @@ void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs_in, hipStr
     pack.add(cdiv(std::max<size_t>(P.ntile * t * P.ldv, t), 256));
     chain.add(S > 1 ? (size_t)cdiv(t, 256) * (S - 1) : 0);
     scan.add(S > 1 ? cdiv(t, 256) : 0);
-    rows.add(cdiv(t, 256));
+    rows.add(cdiv(t, kDeltaBlock));
     scale.add((size_t)cdiv(t, 256) * P.R);
   }
   // conv levels
@@ -970,7 +961,7 @@ void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs_in, hipStr
   }
   {
     TimedLaunch tl("batch_finish", ls);
-    hipLaunchKernelGGL(k_b_delta, dim3(rows.total()), dim3(256), 0, ls, n, P32(o_rows), d_bs);
+    hipLaunchKernelGGL(k_b_delta, dim3(rows.total()), dim3(kDeltaBlock), 0, ls, n, P32(o_rows), d_bs);
     hipLaunchKernelGGL(k_b_scale, dim3(scale.total()), dim3(256), 0, ls, n, P32(o_scale), d_bs);
   }
   if (graph) {

@@ -56,11 +56,8 @@ struct SolveJob {
   int32_t* status;
 };
 
-// Master polynomials and solves of all jobs (enqueued on s, no host sync).
-// Systems of at least kBatchOwnSolveMinT unknowns go through the one-system
-// solve when its selected pass beats the queue's (vsolve_beats_queue); the
-// others share the persistent work-queue pass.
-constexpr uint32_t kBatchOwnSolveMinT = 8192;
+// Master polynomials and solves of all jobs (enqueued on s, no host sync),
+// all systems through the persistent work-queue pass.
 void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs, hipStream_t s);
 
 // Newton matrices and powers of y_k for many (nodes, y_k) sets at once:

@@ -48,6 +48,8 @@ struct Params {
   uint64_t p;
   zr_mod M;
   uint32_t nvars, last, nprobes;
+  uint32_t first;            // first stage to run (1, or k >= 2 with the stage-(k-1) skeleton in `start`)
+  const zr_poly* start = nullptr;
   std::vector<uint32_t> deg, deg_den, need, nnodes;
   std::vector<uint64_t> y, anchor, nodes, probes;
   std::vector<size_t> node_off;
@@ -96,6 +98,9 @@ void check_probes(const Params& P, zr_blackbox_fn bb, void* ctx, const Skeleton&
                   hipStream_t s);
 void solve_stage(const Params& P, const Skeleton& S, uint64_t* vals, uint32_t R, hipStream_t s, int32_t* d_status);
 void download(const Skeleton& S, hipStream_t s, zr_poly* out);
+// Upload the caller's stage-(P.first - 1) skeleton (P.start) and compute its
+// monomial values from the power tables of K.
+void upload_start(const Params& P, const StageConsts& K, DevArena& keep, Skeleton& S, hipStream_t s);
 
 // balanced path pieces shared with the server
 void check_slices(const std::vector<int32_t>& st, const std::vector<int32_t>& dA, const std::vector<int32_t>& dB,

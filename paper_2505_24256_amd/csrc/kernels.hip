@@ -12,6 +12,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "../../include/zippel.h"
 #include "field.hpp"
 #include "kernels.hpp"
 #include "kernels_dev.hpp"
@@ -32,15 +33,12 @@ namespace zr {
 static uint32_t dots_waves_per_cu(uint32_t RT);
 static uint32_t dots_pc_blocks_per_cu(uint32_t RT, uint32_t ntile);
 
-// Variant of the dot-product pass: one wave per tile (0), the
+// Variant of the dot-product pass: one wave per tile (0) or the
 // producer/consumer form (1, the default; systems of at most kPcMinR
-// right-hand sides still take one wave per tile) or the opt-in int8
-// matrix-core form (2); see zr_solve_variant.
+// right-hand sides still take one wave per tile); see zr_solve_variant.
 constexpr int kDefaultDotsVariant = 1;
 static std::atomic<int> g_dots_variant{kDefaultDotsVariant};
 static bool dots_pc_enabled() { return g_dots_variant.load() == 1; }
-static bool dots_mf_enabled() { return g_dots_variant.load() == 2; }
-bool vsolve_beats_queue() { return dots_mf_enabled(); }
 bool vsolve_uses_pc() { return dots_pc_enabled(); }
 
 // Widest tile of the one-wave-per-tile pass: 16 right-hand sides keep two
@@ -51,28 +49,6 @@ VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
   VsolvePlan P;
   P.t = t;
   P.R = R;
-  P.mf = 0;
-  P.tp = 0;
-  if (R > 0 && dots_mf_enabled()) {
-    // int8 matrix-core pass: waves of 16 rows x four chunks x up to 16
-    // right-hand sides; about four rounds of one wave per SIMD, chunks of at
-    // least 64 steps (four K-blocks) and at most kMfMaxL
-    P.mf = 1;
-    P.pc = 0;
-    P.ntile = cdiv(R, 2 * kMfMaxNT);
-    P.RT = cdiv(R, P.ntile);
-    P.ldv = 0;
-    P.tp = ((t + 15) & ~15u) + 16;  // 16 zero bytes after every plane
-    const uint32_t rblocks = std::max<uint32_t>(1, cdiv(t, kMfRows));
-    const uint32_t slots = std::max<uint32_t>(1, num_cus) * 4;
-    const uint32_t G = std::max<uint32_t>(1, cdiv(4ull * slots, (uint64_t)rblocks * P.ntile));  // work items per row block and tile
-    uint32_t L = std::max<uint32_t>(std::min<uint32_t>(64, P.tp), (cdiv(t, 4 * kMfCh * G) + 15) & ~15u);
-    L = std::min<uint32_t>(L, kMfMaxL);
-    P.L = L;
-    P.S = std::max<uint32_t>(1, cdiv(t, L));
-    P.Sd = cdiv(P.S, 4 * kMfCh);
-    return P;
-  }
   const uint32_t row_blocks = std::max<uint32_t>(1, cdiv(t, 64));
   // Above kPcMinR right-hand sides the chain runs once per row block in a
   // producer wave (k_vs_dots_pc) and consumer waves take tiles of at most
@@ -114,26 +90,14 @@ VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
   return P;
 }
 
-// workspace layout (64-bit words): right-hand sides (VT [ntile][t][ldv/2], or
-//                   the digit planes [R][8][tp] bytes) | mono_p [t] | Bc [S][t] |
-//                   qstart [S][t] | mL [t] | spart [Sd][R][t] | hpart [S][t] | winv [2t]
-static size_t vsolve_rhs_words(const VsolvePlan& P) {
-  return P.mf ? (size_t)P.R * P.tp : (size_t)P.ntile * P.t * (P.ldv / 2);
-}
+// workspace layout (64-bit words): right-hand sides VT [ntile][t][ldv/2] |
+//                   mono_p [t] | Bc [S][t] | qstart [S][t] | mL [t] |
+//                   spart [Sd][R][t] | hpart [S][t] | winv [2t]
+static size_t vsolve_rhs_words(const VsolvePlan& P) { return (size_t)P.ntile * P.t * (P.ldv / 2); }
 
 size_t vsolve_workspace_words(const VsolvePlan& P) {
   const size_t t = P.t, S = P.S;
   return vsolve_rhs_words(P) + t + 2 * S * t + t + P.Sd * (size_t)P.R * t + S * t + 2 * t + 64;
-}
-
-// Digit planes of the right-hand sides and Shoup constants of the monomials.
-__global__ void k_pack_digits(uint32_t t, uint32_t tp, uint32_t R, const uint64_t* __restrict__ rhs, size_t ld_rhs,
-                              uint32_t* __restrict__ Dg, const uint64_t* __restrict__ mono,
-                              uint64_t* __restrict__ mono_p, zr_mod M) {
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t per = tp / 4;
-  if (idx < (size_t)R * per) pack_digits_body(t, tp, M.p, (uint32_t)(idx / per), (uint32_t)(idx % per), rhs, ld_rhs, Dg);
-  if (idx < t) mono_p[idx] = zr_shoup_pre(M, mono[idx]);
 }
 
 // Packed right-hand sides [ntile][t][ldv] and Shoup constants of the monomials.
@@ -169,10 +133,10 @@ __global__ void __launch_bounds__(64 * (1 + kPcMaxTiles)) k_vs_dots_pc(VsArgs a,
   vs_dots_pc_body<RT>(a, blockIdx.x, blockIdx.y, ntile, qbuf);
 }
 
-__global__ void k_vs_delta(VsArgs a, const uint64_t* __restrict__ mLv, uint64_t* __restrict__ winv,
-                           int32_t* __restrict__ status) {
-  const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l < a.t) vs_delta_body(a, l, mLv, winv, status);
+__global__ void __launch_bounds__(kDeltaBlock) k_vs_delta(VsArgs a, const uint64_t* __restrict__ mLv,
+                                                           uint64_t* __restrict__ winv, int32_t* __restrict__ status) {
+  __shared__ uint64_t sh[kDeltaBlock / 64 + 1];
+  vs_delta_block(a, blockIdx.x * kDeltaBlock + threadIdx.x, mLv, winv, status, sh);
 }
 
 __global__ void k_vs_scale(VsArgs a, const uint64_t* __restrict__ winv, uint64_t* __restrict__ out, size_t ld_out) {
@@ -258,12 +222,7 @@ hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, co
   a.Bc = Bc;
   a.spart = spart;
   a.hpart = hpart;
-  if (P.mf) {
-    const size_t total = std::max<size_t>((size_t)P.R * (P.tp / 4), t);
-    TimedLaunch tl("vs_pack", s);
-    hipLaunchKernelGGL(k_pack_digits, dim3(cdiv(total, 256)), dim3(256), 0, s, P.t, P.tp, P.R, rhs, ld_rhs,
-                       (uint32_t*)VT, mono, mono_p, M);
-  } else {
+  {
     const size_t total = std::max<size_t>(P.ntile * t * P.ldv, t);  // 32-bit words
     TimedLaunch tl("vs_pack", s);
     hipLaunchKernelGGL(k_pack, dim3(cdiv(total, 256)), dim3(256), 0, s, P.t, P.R, P.RT, P.ntile, P.ldv, rhs, ld_rhs,
@@ -279,12 +238,7 @@ hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, co
       hipLaunchKernelGGL(k_vs_scan, dim3(cdiv(t, 256)), dim3(256), 0, s, a, qstart, mL);
     }
   }
-  if (P.mf) {
-    TimedLaunch tl("vs_dots", s);
-    const hipError_t e = launch_vs_mfma(cdiv(P.RT, 2), M.p <= kMfLazyMaxP, dim3(cdiv(t, kMfRows), P.Sd, P.ntile), s, a,
-                                        (const uint32_t*)VT, P.tp, P.RT);
-    if (e != hipSuccess) return e;
-  } else if (P.pc) {
+  if (P.pc) {
     DotsPcKernel kp = dots_pc_kernel(P.RT);
     if (!kp) return hipErrorInvalidValue;
     TimedLaunch tl("vs_dots", s);
@@ -298,7 +252,7 @@ hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, co
   {
     TimedLaunch tl("vs_finish", s);
     uint64_t* winv = hpart + S * t;
-    hipLaunchKernelGGL(k_vs_delta, dim3(cdiv(t, 256)), dim3(256), 0, s, a, mL, winv, status);
+    hipLaunchKernelGGL(k_vs_delta, dim3(cdiv(t, kDeltaBlock)), dim3(kDeltaBlock), 0, s, a, mL, winv, status);
     hipLaunchKernelGGL(k_vs_scale, dim3(cdiv(t, 256), P.R), dim3(256), 0, s, a, winv, out, ld_out);
   }
   return hipGetLastError();
@@ -546,6 +500,27 @@ hipError_t poly_eval_point(const zr_mod& M, uint32_t t, uint32_t nvars, const ui
 }
 
 // ============================================================================
+// Monomial values of a skeleton from per-variable power tables.
+// ============================================================================
+
+__global__ void k_mono(zr_mod M, uint32_t t, uint32_t nv, const uint16_t* __restrict__ exps, uint32_t ld,
+                       const uint64_t* __restrict__ tabs, MonoTables T, uint64_t* __restrict__ mono) {
+  const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= t) return;
+  uint64_t m = 1 % M.p;
+  for (uint32_t v = 0; v < nv; ++v) m = zr_mul(M, m, tabs[T.off[v] + exps[(size_t)v * ld + l]]);
+  mono[l] = m;
+}
+
+hipError_t mono_values(const zr_mod& M, uint32_t t, uint32_t nv, const uint16_t* exps, uint32_t ld,
+                       const uint64_t* tabs, const MonoTables& T, uint64_t* mono, hipStream_t s) {
+  if (t == 0) return hipSuccess;
+  if (nv > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mono, dim3(cdiv(t, 256)), dim3(256), 0, s, M, t, nv, exps, ld, tabs, T, mono);
+  return hipGetLastError();
+}
+
+// ============================================================================
 // helpers
 // ============================================================================
 
@@ -641,8 +616,10 @@ TimedLaunch::~TimedLaunch() {
 }  // namespace zr
 
 extern "C" {
-void zr_solve_variant(int variant) {
-  zr::g_dots_variant.store(variant >= 0 && variant <= 2 ? variant : zr::kDefaultDotsVariant);
+zr_status zr_solve_variant(int variant) {
+  if (variant != 0 && variant != 1) return ZR_EINVAL;
+  zr::g_dots_variant.store(variant);
+  return ZR_OK;
 }
 
 void zr_timing_enable(int on) {

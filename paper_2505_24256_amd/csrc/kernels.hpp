@@ -20,17 +20,9 @@ struct VsolvePlan {
   uint32_t RT, ntile;  // right-hand sides per tile (even), number of tiles
   uint32_t ldv;        // row stride (32-bit words) of one packed row of a tile
   uint32_t pc;         // 1: producer/consumer pass (chain once per row block, one wave per tile)
-  uint32_t mf;         // 1: int8 matrix-core pass (digit planes of the right-hand sides, padded length tp)
-  uint32_t tp;
-  uint32_t Sd;         // partial dot-product sums per row and right-hand side (chunk groups for mf)
+  uint32_t Sd;         // partial dot-product sums per row and right-hand side (= S)
 };
 VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus);
-// true when the selected dot-product pass of the one-system solve is faster
-// than the batched work-queue pass on a system that fills the device alone:
-// the matrix-core variant (the one-wave-per-tile and producer/consumer
-// variants have persistent queue forms with the same bodies, where large
-// systems also share the batched product trees and mostly need no chunking)
-bool vsolve_beats_queue();
 // true when the producer/consumer pass is selected (solve variant 1, the default)
 bool vsolve_uses_pc();
 
@@ -77,6 +69,14 @@ constexpr uint32_t kPolyEvalBlocks = 64;
 hipError_t poly_eval_point(const zr_mod& M, uint32_t t, uint32_t nvars, const uint16_t* exps, uint32_t ld,
                            const uint64_t* coef, const uint64_t* tab, uint32_t ldtab, uint64_t* result,
                            uint64_t* partial, hipStream_t s);
+
+// Monomial values m_l = prod_{v < nv} y_v^{e_{l,v}} of a skeleton: exps SoA
+// [..][ld] uint16; the powers y_v^d of variable v at tabs[off[v] + d].
+struct MonoTables {
+  uint32_t off[64];
+};
+hipError_t mono_values(const zr_mod& M, uint32_t t, uint32_t nv, const uint16_t* exps, uint32_t ld,
+                       const uint64_t* tabs, const MonoTables& T, uint64_t* mono, hipStream_t s);
 
 // ---- small helpers -----------------------------------------------------------
 hipError_t fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);

@@ -452,346 +452,75 @@ __device__ __forceinline__ void vs_dots_pc_body(const VsArgs& a, uint32_t rb, ui
   }
 }
 
-// ---- dot-product pass on the int8 matrix cores ---------------------------------
-// The dot products s_l^(j) = sum_r q_{l,r} v^(j)_{r+1} of a block of rows are
-// the product of Q (rows l, steps r; generated by the chain) with V (steps r,
-// right-hand sides j).  Both factors are written in signed base-256 digits:
-// shifted into (-p/2, p/2], a value x is sum_{a<8} x_a 256^a with every x_a in
-// [-128, 127].  For each digit a of q and b of v the sums sum_r q_a v_b are
-// exact int32 matrix products (|q_a v_b| <= 2^14), and
-//     s = sum_{a,b} 256^(a+b) sum_r q_a v_b,
-// reduced mod p once per work item.  One wave owns 16 rows (the M side of
-// v_mfma_i32_16x16x64_i8), four consecutive chunks of r (one per quarter of
-// the wave: K = 4 x 16 steps per block) and NT column tiles of 16 = two
-// right-hand sides x eight digits b (the N side).  The eight digits a of the
-// wave's q values are eight A operands, so every B fragment feeds eight
-// products and the accumulators are acc[a][n].
-constexpr uint32_t kMfRows = 16;
-constexpr uint32_t kMfMaxNT = 8;       // 16 right-hand sides per wave
-constexpr uint32_t kMfMaxL = 16384;    // chunk length bound: 1024 K-blocks, |sums| < 2^30
-typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+// Inverses of the values w of a block's kDeltaBlock threads by Montgomery's
+// simultaneous inversion: with P<_i and P>_i the products of the w of the
+// threads before and after thread i, 1/w_i = P<_i P>_i / (product of all), so
+// the block pays one inversion and a few products per thread instead of one
+// inversion per thread.  The products within a wave are shuffle scans; the
+// four wave totals meet in LDS.  Threads with use = false or w = 0 enter the
+// products as 1 and get 0.  Every thread of the block must call it.
+constexpr uint32_t kDeltaBlock = 256;
 
-// The eight signed base-256 digits of x in [0, p), as the bytes of a word:
-// x' = x or x - p (|x'| < 2^62), then byte a of ((x' + C) xor C) with
-// C = sum_{a<7} 128 * 256^a is the digit x_a (a < 7) and the top byte the top
-// digit, both read as signed bytes.
-__device__ __forceinline__ uint64_t sdigits(uint64_t x, uint64_t p) {
-  constexpr uint64_t C = 0x0080808080808080ull;
-  const uint64_t xb = x > (p >> 1) ? x - p : x;
-  return (xb + C) ^ C;
-}
-
-// y_a = bytes a of (x0, x1, x2, x3): a 4 x 4 byte transpose in eight byte permutes.
-__device__ __forceinline__ void transpose4(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3, uint32_t& y0,
-                                           uint32_t& y1, uint32_t& y2, uint32_t& y3) {
-  const uint32_t a = __builtin_amdgcn_perm(x1, x0, 0x05010400u);  // x0.0 x1.0 x0.1 x1.1
-  const uint32_t b = __builtin_amdgcn_perm(x1, x0, 0x07030602u);  // x0.2 x1.2 x0.3 x1.3
-  const uint32_t c = __builtin_amdgcn_perm(x3, x2, 0x05010400u);
-  const uint32_t d = __builtin_amdgcn_perm(x3, x2, 0x07030602u);
-  y0 = __builtin_amdgcn_perm(c, a, 0x05040100u);
-  y1 = __builtin_amdgcn_perm(c, a, 0x07060302u);
-  y2 = __builtin_amdgcn_perm(d, b, 0x05040100u);
-  y3 = __builtin_amdgcn_perm(d, b, 0x07060302u);
-}
-
-// Digit planes Dg[j][b][tp] (bytes): Dg[j][b][rr] = digit b of v^(j)_{t-rr}
-// (right-hand side j at step r = t-1-rr, so that consecutive steps of the
-// descending chain are consecutive bytes), zero for rr >= t; tp is a multiple
-// of 16 with at least 16 zero bytes at the end of every plane.  Work item
-// (j, rr4): four bytes rr = 4 rr4 .. 4 rr4 + 3 of every plane of j.
-__device__ __forceinline__ void pack_digits_body(uint32_t t, uint32_t tp, uint64_t p, uint32_t j, uint32_t rr4,
-                                                 const uint64_t* __restrict__ rhs, size_t ld_rhs,
-                                                 uint32_t* __restrict__ Dg) {
-  uint64_t d[4];
+__device__ __forceinline__ uint64_t block_inverse(const zr_mod& M, uint64_t w, bool use, uint64_t* sh) {
+  constexpr uint32_t NW = kDeltaBlock / 64;
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t one = 1 % M.p;
+  const bool part = use && w != 0;
+  uint64_t pre = part ? w : one, suf = pre;  // inclusive prefix / suffix products within the wave
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const uint32_t rr = 4 * rr4 + k;
-    d[k] = rr < t ? sdigits(rhs[(size_t)j * ld_rhs + (t - 1 - rr)], p) : 0;
+  for (uint32_t d = 1; d < 64; d <<= 1) {
+    const uint64_t a = __shfl_up(pre, d), b = __shfl_down(suf, d);
+    if (lane >= d) pre = zr_mul(M, pre, a);
+    if (lane + d < 64) suf = zr_mul(M, suf, b);
   }
-  uint32_t y[8];
-  transpose4((uint32_t)d[0], (uint32_t)d[1], (uint32_t)d[2], (uint32_t)d[3], y[0], y[1], y[2], y[3]);
-  transpose4((uint32_t)(d[0] >> 32), (uint32_t)(d[1] >> 32), (uint32_t)(d[2] >> 32), (uint32_t)(d[3] >> 32), y[4],
-             y[5], y[6], y[7]);
-#pragma unroll
-  for (int b = 0; b < 8; ++b) Dg[((size_t)j * 8 + b) * (tp / 4) + rr4] = y[b];
+  uint64_t epre = __shfl_up(pre, 1), esuf = __shfl_down(suf, 1);
+  if (lane == 0) epre = one;
+  if (lane == 63) esuf = one;
+  if (lane == 63) sh[wave] = pre;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t all = one;
+    for (uint32_t q = 0; q < NW; ++q) all = zr_mul(M, all, sh[q]);
+    sh[NW] = zr_inv(M, all);
+  }
+  __syncthreads();
+  uint64_t other = sh[NW];
+  for (uint32_t q = 0; q < NW; ++q)
+    if (q != wave) other = zr_mul(M, other, sh[q]);
+  return part ? zr_mul(M, zr_mul(M, epre, esuf), other) : 0;
 }
 
-// x mod p for a signed 128-bit x with |x| < 2^126
-__device__ __forceinline__ uint64_t smod128(const zr_mod& M, __int128 x) {
-  const bool neg = x < 0;
-  const zr_u128 u = neg ? (zr_u128)0 - (zr_u128)x : (zr_u128)x;
-  const uint64_t r = zr_mod128(M, (uint64_t)(u >> 64), (uint64_t)u);
-  return neg && r ? M.p - r : r;
-}
-
-// Chains per lane: a wave owns kMfCh chunk groups (4 kMfCh chunks) of its
-// rows; each lane runs kMfCh independent synthetic-division chains, which
-// the compiler interleaves (one chain alone is a serial dependency that leaves
-// the SIMD idle between instructions), and all of them accumulate into the
-// same products (same rows, same right-hand sides).
-constexpr int kMfCh = 2;
-
-// v of lane S of this lane's row of 16 (the quarter of the wave): DPP row
-// broadcast, no memory access.
-template <int S>
-__device__ __forceinline__ uint64_t row_bcast(uint64_t v) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)v, 0x150 + S, 0xF, 0xF, false);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(v >> 32), 0x150 + S, 0xF, 0xF, false);
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// The master coefficient M_r that lane `row` of a quarter holds for block kb:
-// the one of step 16 kb + row of the chunk [hi - len, hi) (M_0 past the end).
-__device__ __forceinline__ uint64_t mf_load_mr(const uint64_t* __restrict__ Mc, uint32_t kb, uint32_t row,
-                                               uint32_t hi, uint32_t len) {
-  const uint32_t pos = 16 * kb + row;
-  return Mc[pos < len ? hi - 1 - pos : 0];
-}
-
-// Largest p for the lazy chain: q is kept in [0, 2p) (one conditional
-// subtraction per step instead of two) and its digits are those of q - p, in
-// (-p, p), which the eight signed base-256 digits cover for p up to this bound.
-constexpr uint64_t kMfLazyMaxP = 0x7F7F7F7F7F7F7F7Full;
-
-// Sixteen chain steps, from position 16 kb, of each of the lane's kMfCh
-// chains (chunk k of length len[k]), the chains advanced together step by
-// step so that their instructions interleave: the digits of q_{l,r} for those
-// steps (zero past a chunk's end) as the eight A operands of each chain, and
-// q (and Horner's h) advanced.  M_r of step s comes from lane s of the quarter
-// (mw[k], loaded by mf_load_mr).  Branch-free.  LAZY: q and h in [0, 2p)
-// (Shoup's product without its final correction, then one correction of the
-// sum, carry included); cmp = C - p mod 2^64.  FULL: no step of the block
-// lies past a chunk's end (no selects).
-template <bool HORNER, bool LAZY, bool FULL>
-__device__ __forceinline__ void mf_chain_block(const zr_mod& M, uint64_t m, uint64_t mp, uint32_t kb,
-                                               const uint32_t (&len)[kMfCh], const uint64_t (&mw)[kMfCh],
-                                               uint64_t cmp, uint64_t (&q)[kMfCh], uint64_t (&h)[kMfCh],
-                                               i32x4 (&A)[kMfCh][8]) {
-  constexpr uint64_t C = 0x0080808080808080ull;
-  uint32_t dlo[kMfCh][16], dhi[kMfCh][16];
-  auto step = [&](auto S) {
-    constexpr int s = decltype(S)::value;
-#pragma unroll
-    for (int k = 0; k < kMfCh; ++k) {
-      const bool on = FULL || 16 * kb + s < len[k];  // FULL: the block lies inside every chunk
-      const uint64_t Mr = row_bcast<s>(mw[k]);
-      // computed for every lane, then selected (no branch)
-      const uint64_t dq = LAZY ? (q[k] + cmp) ^ C : sdigits(q[k], M.p);
-      const uint64_t d = on ? dq : 0;
-      if (HORNER) {
-        uint64_t hn;
-        if (LAZY) {
-          const uint64_t r = zr_shoup_lazy(M, h[k], m, mp), u = r + q[k];
-          hn = (u < r || u >= 2 * M.p) ? u - 2 * M.p : u;
-        } else {
-          hn = zr_add(M, zr_shoup(M, h[k], m, mp), q[k]);
-        }
-        h[k] = on ? hn : h[k];
-      }
-      uint64_t qn;
-      if (LAZY) {
-        const uint64_t r = zr_shoup_lazy(M, q[k], m, mp), u = r + Mr;
-        qn = (u < r || u >= M.p) ? u - M.p : u;
-      } else {
-        qn = zr_add(M, zr_shoup(M, q[k], m, mp), Mr);
-      }
-      q[k] = on ? qn : q[k];
-      dlo[k][s] = (uint32_t)d;
-      dhi[k][s] = (uint32_t)(d >> 32);
-    }
-  };
-  step(std::integral_constant<int, 0>{});
-  step(std::integral_constant<int, 1>{});
-  step(std::integral_constant<int, 2>{});
-  step(std::integral_constant<int, 3>{});
-  step(std::integral_constant<int, 4>{});
-  step(std::integral_constant<int, 5>{});
-  step(std::integral_constant<int, 6>{});
-  step(std::integral_constant<int, 7>{});
-  step(std::integral_constant<int, 8>{});
-  step(std::integral_constant<int, 9>{});
-  step(std::integral_constant<int, 10>{});
-  step(std::integral_constant<int, 11>{});
-  step(std::integral_constant<int, 12>{});
-  step(std::integral_constant<int, 13>{});
-  step(std::integral_constant<int, 14>{});
-  step(std::integral_constant<int, 15>{});
-#pragma unroll
-  for (int k = 0; k < kMfCh; ++k)
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      uint32_t y0, y1, y2, y3;
-      transpose4(dlo[k][4 * w], dlo[k][4 * w + 1], dlo[k][4 * w + 2], dlo[k][4 * w + 3], y0, y1, y2, y3);
-      A[k][0][w] = (int32_t)y0;
-      A[k][1][w] = (int32_t)y1;
-      A[k][2][w] = (int32_t)y2;
-      A[k][3][w] = (int32_t)y3;
-      transpose4(dhi[k][4 * w], dhi[k][4 * w + 1], dhi[k][4 * w + 2], dhi[k][4 * w + 3], y0, y1, y2, y3);
-      A[k][4][w] = (int32_t)y0;
-      A[k][5][w] = (int32_t)y1;
-      A[k][6][w] = (int32_t)y2;
-      A[k][7][w] = (int32_t)y3;
-    }
-}
-
-// Work item (row block rb, group pair gg, tile): rows 16 rb .. 16 rb + 15,
-// chunk groups kMfCh gg .. kMfCh gg + kMfCh - 1 (group g = chunks 4g .. 4g+3,
-// one per quarter of the wave), right-hand sides tile*RT .. tile*RT + RT - 1
-// (RT <= 2 NT).  Writes spart[gg][j][l] and, with HORNER (tile 0), hpart[c][l]
-// of its chunks.
-template <int NT, bool HORNER, bool LAZY>
-__device__ __forceinline__ void vs_mfma_body(const VsArgs& a, const uint32_t* __restrict__ Dg, uint32_t tp,
-                                             uint32_t RT, uint32_t rb, uint32_t gg, uint32_t tile) {
-  const uint32_t lane = threadIdx.x & 63;
-  const uint32_t row = lane & 15, qd = lane >> 4;
-  const uint32_t l0 = rb * kMfRows + row;
-  const uint32_t l = l0 < a.t ? l0 : a.t - 1;
+// Combine chunks, part 1 for the rows of one block (l = row of this thread,
+// live when l < t): delta = sum_c m^{lo_c} H_c by Horner over the chunk
+// partials, w = m delta, and the inverses of the block's w (one inversion per
+// block) with their Shoup constants into winv[2t]; a zero w marks the system
+// singular.  Every thread of the block must call it (it holds barriers).
+__device__ __forceinline__ void vs_delta_block(const VsArgs& a, uint32_t l, const uint64_t* __restrict__ mLv,
+                                               uint64_t* __restrict__ winv, int32_t* __restrict__ status,
+                                               uint64_t* sh) {
   const zr_mod M = a.M;
-  const uint64_t m = a.mono[l], mp = a.mono_p[l];
-  uint32_t c[kMfCh], hi[kMfCh], len[kMfCh];
-  bool has[kMfCh];
-  uint64_t q[kMfCh], h[kMfCh];
-#pragma unroll
-  for (int k = 0; k < kMfCh; ++k) {
-    c[k] = 4 * (kMfCh * gg + k) + qd;
-    has[k] = c[k] < a.S;
-    uint32_t lo = 0, hh = 0;
-    if (has[k]) chunk_range(a.t, a.L, c[k], lo, hh);
-    hi[k] = hh;
-    len[k] = hh - lo;
-    q[k] = (has[k] && a.qstart) ? a.qstart[(size_t)c[k] * a.t + l] : 1 % M.p;
-    h[k] = 0;
-  }
-  uint32_t lo0, hi0;
-  chunk_range(a.t, a.L, 4 * kMfCh * gg, lo0, hi0);  // the first chunk of the item is its longest
-  const uint32_t nkb = (hi0 - lo0 + 15) / 16;
-  // K-blocks that lie inside every chunk of the item (the same on all lanes)
-  uint32_t nfull = nkb;
-  for (uint32_t cc = 4 * kMfCh * gg; cc < 4 * kMfCh * (gg + 1); ++cc) {
-    uint32_t clo = 0, chi = 0;
-    if (cc < a.S) chunk_range(a.t, a.L, cc, clo, chi);
-    nfull = std::min<uint32_t>(nfull, (chi - clo) / 16);
-  }
-  i32x4 acc[8][NT];
-#pragma unroll
-  for (int x = 0; x < 8; ++x)
-#pragma unroll
-    for (int n = 0; n < NT; ++n) acc[x][n] = i32x4{0, 0, 0, 0};
-  // B fragments: lane column -> (right-hand side 2n + jl of the tile, digit b);
-  // a fragment past a chunk's end is 0 (its load reads the plane's start)
-  const uint32_t col = lane & 15, jl = col >> 3, b = col & 7;
-  const uint32_t* base[NT];
-  bool bok[NT];
-#pragma unroll
-  for (int n = 0; n < NT; ++n) {
-    const uint32_t jt = 2 * n + jl, j = tile * RT + jt;
-    bok[n] = jt < RT && j < a.R;
-    base[n] = Dg + ((size_t)(bok[n] ? j : 0) * 8 + b) * (tp / 4);
-  }
-  // a fragment that is out of range is read from the 16 zero bytes that end
-  // every plane (no select on the loaded value: the load is not waited for
-  // until its products)
-  const uint32_t* zero16 = Dg + (tp - 16) / 4;
-  auto load_b = [&](uint32_t kb, i32x4 (&B)[kMfCh][NT]) {
-#pragma unroll
-    for (int k = 0; k < kMfCh; ++k) {
-      const bool kin = 16 * kb < len[k];
-#pragma unroll
-      for (int n = 0; n < NT; ++n) {
-        const bool ok = bok[n] && kin;
-        B[k][n] = *(const i32x4*)(ok ? base[n] + ((size_t)c[k] * a.L + 16 * kb) / 4 : zero16);
+  const bool live = l < a.t;
+  uint64_t w = 0;
+  if (live) {
+    const uint64_t m = a.mono[l];
+    uint64_t delta = a.hpart[l];
+    if (a.S > 1) {
+      const uint64_t mL = mLv[l], mLp = zr_shoup_pre(M, mL);
+      const uint32_t len_last = a.t - (a.S - 1) * a.L;
+      const uint64_t mlast = zr_pow(M, m, len_last);
+      for (uint32_t c = 1; c < a.S; ++c) {
+        const uint64_t hc = a.hpart[(size_t)c * a.t + l];
+        delta = (c + 1 < a.S) ? zr_add(M, zr_shoup(M, delta, mL, mLp), hc) : zr_add(M, zr_mul(M, delta, mlast), hc);
       }
     }
-  };
-  const uint64_t cmp = 0x0080808080808080ull - M.p;
-  // Pipeline: block kb's products at the top of iteration kb, then the loads
-  // of block kb+1's right-hand sides (consumed one iteration later) and the
-  // chains of block kb+1, whose master coefficients were loaded an iteration
-  // earlier still.
-  i32x4 A[kMfCh][8], B[kMfCh][NT];
-  uint64_t mw[kMfCh], mwn[kMfCh];
-#pragma unroll
-  for (int k = 0; k < kMfCh; ++k) mw[k] = mf_load_mr(a.Mc, 0, row, hi[k], len[k]);
-  load_b(0, B);
-#pragma unroll
-  for (int k = 0; k < kMfCh; ++k) mwn[k] = mf_load_mr(a.Mc, 1, row, hi[k], len[k]);
-  if (nfull > 0) mf_chain_block<HORNER, LAZY, true>(M, m, mp, 0, len, mw, cmp, q, h, A);
-  else mf_chain_block<HORNER, LAZY, false>(M, m, mp, 0, len, mw, cmp, q, h, A);
-#pragma unroll
-  for (int k = 0; k < kMfCh; ++k) mw[k] = mwn[k];
-  for (uint32_t kb = 0; kb < nkb; ++kb) {
-#pragma unroll
-    for (int k = 0; k < kMfCh; ++k)
-#pragma unroll
-      for (int n = 0; n < NT; ++n)
-#pragma unroll
-        for (int x = 0; x < 8; ++x)
-          acc[x][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[k][x], B[k][n], acc[x][n], 0, 0, 0);
-    load_b(kb + 1, B);
-#pragma unroll
-    for (int k = 0; k < kMfCh; ++k) mwn[k] = mf_load_mr(a.Mc, kb + 2, row, hi[k], len[k]);
-    // keep the loads ahead of the chains
-    __builtin_amdgcn_sched_barrier(0);
-    if (kb + 1 < nfull) mf_chain_block<HORNER, LAZY, true>(M, m, mp, kb + 1, len, mw, cmp, q, h, A);
-    else mf_chain_block<HORNER, LAZY, false>(M, m, mp, kb + 1, len, mw, cmp, q, h, A);
-#pragma unroll
-    for (int k = 0; k < kMfCh; ++k) mw[k] = mwn[k];
+    w = zr_mul(M, m, delta);
+    if (w == 0) atomicCAS(status, 0, -3);  // ZR_ESINGULAR, unless an earlier step already failed
   }
-  // lane holds C[4 qd + i][col] of every (x, n); the digits b of one right-hand
-  // side sit in the eight lanes that differ in bits 0..2
-  const uint64_t wb = zr_mod128(M, 0, (uint64_t)1 << (8 * b));
-#pragma unroll
-  for (int n = 0; n < NT; ++n) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      __int128 sx = 0;
-#pragma unroll
-      for (int x = 0; x < 8; ++x) sx += (__int128)acc[x][n][i] * ((__int128)1 << (8 * x));
-      uint64_t v = zr_mul(M, smod128(M, sx), wb);
-      v = zr_add(M, v, __shfl_xor(v, 1, 64));
-      v = zr_add(M, v, __shfl_xor(v, 2, 64));
-      v = zr_add(M, v, __shfl_xor(v, 4, 64));
-      const uint32_t orow = rb * kMfRows + 4 * qd + i;
-      const uint32_t jt = 2 * n + jl, j = tile * RT + jt;
-      if (b == 0 && orow < a.t && jt < RT && j < a.R) a.spart[((size_t)gg * a.R + j) * a.t + orow] = v;
-      // one output at a time: keeps the 128-bit temporaries of the others out of registers
-      __builtin_amdgcn_sched_barrier(0);
-    }
+  const uint64_t wi = block_inverse(M, w, live, sh);
+  if (live) {
+    winv[l] = wi;
+    winv[a.t + l] = wi ? zr_shoup_pre(M, wi) : 0;
   }
-  if (HORNER && l0 < a.t) {
-#pragma unroll
-    for (int k = 0; k < kMfCh; ++k)
-      if (has[k]) a.hpart[(size_t)c[k] * a.t + l0] = (LAZY && h[k] >= M.p) ? h[k] - M.p : h[k];
-  }
-}
-
-// Combine chunks, part 1 for row l: delta = sum_c m^{lo_c} H_c by Horner over
-// the chunk partials, w = m delta, and its inverse (with Shoup constant) into
-// winv[2t]; a zero w marks the system singular.
-__device__ __forceinline__ void vs_delta_body(const VsArgs& a, uint32_t l, const uint64_t* __restrict__ mLv,
-                                              uint64_t* __restrict__ winv, int32_t* __restrict__ status) {
-  const zr_mod M = a.M;
-  const uint64_t m = a.mono[l];
-  uint64_t delta = a.hpart[l];
-  if (a.S > 1) {
-    const uint64_t mL = mLv[l], mLp = zr_shoup_pre(M, mL);
-    const uint32_t len_last = a.t - (a.S - 1) * a.L;
-    const uint64_t mlast = zr_pow(M, m, len_last);
-    for (uint32_t c = 1; c < a.S; ++c) {
-      const uint64_t hc = a.hpart[(size_t)c * a.t + l];
-      delta = (c + 1 < a.S) ? zr_add(M, zr_shoup(M, delta, mL, mLp), hc) : zr_add(M, zr_mul(M, delta, mlast), hc);
-    }
-  }
-  const uint64_t w = zr_mul(M, m, delta);
-  if (w == 0) {
-    atomicCAS(status, 0, -3);  // ZR_ESINGULAR, unless an earlier step already failed
-    winv[l] = 0;
-    winv[a.t + l] = 0;
-    return;
-  }
-  const uint64_t wi = zr_inv(M, w);
-  winv[l] = wi;
-  winv[a.t + l] = zr_shoup_pre(M, wi);
 }
 
 // Combine chunks, part 2 for row l and right-hand side j:
@@ -1040,11 +769,8 @@ __device__ __forceinline__ void expand_body(const zr_mod& M, uint32_t t, uint32_
 
 namespace zr {
 
-// Host launchers of the kernels compiled with the latency-aware scheduler
-// (kernels_ilp.hip).  launch_vs_mfma returns hipErrorInvalidValue for NT
-// outside 1..kMfMaxNT.
-hipError_t launch_vs_mfma(uint32_t NT, bool lazy, dim3 grid, hipStream_t s, const VsArgs& a, const uint32_t* Dg,
-                          uint32_t tp, uint32_t RT);
+// Host launcher of the product-tree convolution, compiled with the
+// latency-aware scheduler (kernels_ilp.hip).
 void launch_master_conv(dim3 grid, size_t shmem, hipStream_t s, const zr_mod& M, uint32_t t, uint32_t half,
                         uint32_t IC, uint32_t nic, const uint64_t* cur, const uint4* limbs, uint64_t* part,
                         uint64_t* nxt, uint4* limbs_nxt);

@@ -35,8 +35,9 @@ struct Request {
   std::unique_ptr<Params> P;
   zr_blackbox_fn bb = nullptr;
   void* ctx = nullptr;
-  uint64_t footprint = 0;
-  uint32_t k = 0;  // stages done
+  uint64_t footprint = 0;  // estimate for the next stage (stage_footprint)
+  uint64_t cap = 0;        // bound on any skeleton's size used by the estimate
+  uint32_t k = 0;          // stages done
   Skeleton SN, SD;
   std::shared_ptr<DevArena> arena;  // holds SN, SD
   int32_t* d_status = nullptr;
@@ -46,24 +47,34 @@ struct Request {
   uint64_t admitted_step = 0, finished_step = 0;
 };
 
-// Footprint model: per term of a skeleton, the value table [D+1][t], the
-// Newton output of the same size, the solve's packed rows and partial sums
-// (about 2(D+1) words) and the skeleton itself; the balanced path doubles it
-// (numerator and denominator) and adds the per-slice Thiele tables.
-uint64_t footprint_of(const Params& P, bool balanced, uint64_t expected_terms) {
-  uint64_t tmax = expected_terms;
-  if (!tmax) {
-    tmax = 1;
-    for (uint32_t v = 0; v < P.nvars; ++v) {
-      tmax *= (uint64_t)P.deg[v] + 1;
-      if (tmax > ((uint64_t)1 << 32)) break;
-    }
+// Footprint model of a request's next stage (stage k + 1 after k stages
+// done), from its live skeleton sizes.  Per term of a skeleton of t terms and
+// D1 nodes of the new variable: the value table [D1][t], the Newton output of
+// the same size and the solve's packed rows and partial sums (about 2 D1 words
+// in all), and the skeleton itself; plus the next skeleton, at most t D1
+// terms, capped by `cap` (the caller's expected final size, or the degree
+// bounds' monomial count), at four words a term.  The balanced path has a
+// numerator and a denominator and adds the per-slice Thiele tables (samples and
+// two coefficient tables of nk + 1 rows for T = max(tN, tD) slices).
+uint64_t monomial_count(const Params& P) {
+  uint64_t c = 1;
+  for (uint32_t v = 0; v < P.nvars; ++v) {
+    c *= (uint64_t)P.deg[v] + 1;
+    if (c > ((uint64_t)1 << 32)) return (uint64_t)1 << 32;
   }
-  uint64_t R = 1;
-  for (uint32_t v = 0; v < P.nvars; ++v) R = std::max<uint64_t>(R, (uint64_t)P.need[v] + 1);
-  uint64_t words = tmax * (4 * R + 12);
-  if (balanced) words = 2 * words + tmax * 4 * R;
-  return 8 * words;
+  return c;
+}
+
+uint64_t stage_footprint(const Params& P, bool balanced, uint32_t k, uint64_t tN, uint64_t tD, uint64_t cap) {
+  if (k >= P.last) return 0;
+  const uint64_t D1 = (uint64_t)P.need[k] + 1;
+  auto words = [&](uint64_t t) {
+    t = std::max<uint64_t>(t, 1);
+    return t * (4 * D1 + 12) + std::min(t * D1, cap) * 4;
+  };
+  if (!balanced) return 8 * words(tN);
+  const uint64_t T = std::max<uint64_t>(std::max(tN, tD), 1);
+  return 8 * (words(tN) + words(tD) + 3 * (D1 + 1) * T);
 }
 
 }  // namespace
@@ -76,6 +87,7 @@ struct Server {
   uint32_t max_active;
   uint64_t next_id = 1, steps = 0;
   std::unique_ptr<DevArena> status_arena;
+  std::vector<int32_t*> free_status;  // status words of retired requests, reused by new ones
   std::deque<Request*> pending;
   std::vector<Request*> active;
   std::map<uint64_t, Request*> done;
@@ -114,7 +126,12 @@ void finish(Server& S, Request& r) {
   r.finished = true;
   r.finished_step = S.steps;
   r.arena.reset();
+  // every device use of the status word has been read back by now; a later
+  // request clears it on the same stream before its first use
+  S.free_status.push_back(r.d_status);
+  r.d_status = nullptr;
   S.used -= r.footprint;
+  r.footprint = 0;
   S.stats.completed += 1;
   if (r.status != ZR_OK) S.stats.failed += 1;
 }
@@ -420,13 +437,19 @@ zr_status zr_server_submit(zr_server* srv, const zr_params* params, int balanced
   try {
     std::unique_ptr<Request> r(new Request());
     r->P.reset(new Params(params, balanced != 0));
-    if (r->P->p != S.p) return ZR_EINVAL;
+    if (r->P->p != S.p || r->P->first > 1) return ZR_EINVAL;
     r->balanced = balanced != 0;
     r->bb = bb;
     r->ctx = ctx;
-    r->footprint = footprint_of(*r->P, r->balanced, expected_terms);
+    r->cap = expected_terms ? expected_terms : monomial_count(*r->P);
+    r->footprint = stage_footprint(*r->P, r->balanced, 0, 1, 1, r->cap);
     r->id = S.next_id++;
-    r->d_status = S.status_arena->alloc<int32_t>(1);
+    if (!S.free_status.empty()) {
+      r->d_status = S.free_status.back();
+      S.free_status.pop_back();
+    } else {
+      r->d_status = S.status_arena->alloc<int32_t>(1);
+    }
     check(fill_i32(r->d_status, 0, 1, S.s));
     *id = r->id;
     S.pending.push_back(r.release());
@@ -468,10 +491,15 @@ zr_status zr_server_step(zr_server* srv, uint32_t* n_active, uint32_t* n_pending
           S.done[r->id] = r;
           ++fin;
         } else {
+          // the next stage's estimate from the skeletons just built
+          S.used -= r->footprint;
+          r->footprint = stage_footprint(*r->P, r->balanced, r->k, r->SN.t, r->SD.t, r->cap);
+          S.used += r->footprint;
           keep.push_back(r);
         }
       }
       S.active.swap(keep);
+      S.stats.peak_footprint = std::max(S.stats.peak_footprint, S.used);
     }
   } catch (const Error& e) {
     return (zr_status)e.code;

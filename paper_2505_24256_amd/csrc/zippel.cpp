@@ -245,6 +245,22 @@ Params::Params(const zr_params* P, bool balanced) {
   }
   for (uint64_t x : probes)
     if (x >= p) throw Error(ZR_EINVAL);
+  // resumption from a stage's result: shape, bounds, order and values
+  first = P->first_stage <= 1 ? 1 : P->first_stage;
+  if (first > 1) {
+    start = P->start;
+    if (balanced || first > last || !start || start->nvars != nvars || start->nterms >= ((uint64_t)1 << 31) ||
+        (start->nterms && (!start->exps || !start->coeffs)))
+      throw Error(ZR_EINVAL);
+    const uint32_t kv = first - 1;  // variables x_1..x_{k-1} are reached
+    for (uint64_t l = 0; l < start->nterms; ++l) {
+      const uint16_t* e = start->exps + l * nvars;
+      if (start->coeffs[l] >= p) throw Error(ZR_EINVAL);
+      for (uint32_t v = 0; v < nvars; ++v)
+        if (v < kv ? e[v] > deg[v] : e[v] != 0) throw Error(ZR_EINVAL);
+      if (l > 0 && !std::lexicographical_compare(e - nvars, e, e, e + nvars)) throw Error(ZR_EINVAL);
+    }
+  }
 }
 
 std::vector<uint64_t> Params::node_list(uint32_t v, uint32_t count) const {
@@ -501,6 +517,22 @@ void download(const Skeleton& S, hipStream_t s, zr_poly* out) {
     for (uint32_t v = 0; v < S.nvars; ++v) out->exps[(size_t)l * S.nvars + v] = soa[(size_t)v * S.t + l];
 }
 
+void upload_start(const Params& P, const StageConsts& K, DevArena& keep, Skeleton& S, hipStream_t s) {
+  const uint32_t t = (uint32_t)P.start->nterms, nv = P.nvars, kv = P.first - 1;
+  S.alloc(keep, nv, t);
+  if (t == 0) return;
+  std::vector<uint16_t> soa((size_t)nv * t);
+  for (uint32_t l = 0; l < t; ++l)
+    for (uint32_t v = 0; v < nv; ++v) soa[(size_t)v * t + l] = P.start->exps[(size_t)l * nv + v];
+  h2d(S.exps, soa.data(), soa.size() * 2, s);
+  h2d(S.coef, P.start->coeffs, (size_t)t * 8, s);
+  MonoTables T{};
+  const uint64_t* tabs = (const uint64_t*)K.base;
+  for (uint32_t v = 0; v < kv; ++v) T.off[v] = (uint32_t)(K.yoff[v] / 2);
+  check(mono_values(P.M, t, kv, S.exps, t, tabs, T, S.mono, s));
+  // the host arrays above are pageable: the copies have completed on return
+}
+
 // ---------------------------------------------------------------------------
 // polynomial Zippel
 
@@ -521,9 +553,14 @@ static void reconstruct_poly(const zr_params* params, zr_blackbox_fn bb, void* c
   check(fill_u64(root.coef, 1 % P.p, 1, s));
   check(fill_u64((uint64_t*)root.exps, 0, (P.nvars * 2 + 7) / 8, s));
   uint32_t D1 = D1s[0];
-  std::vector<uint64_t> X = P.node_list(0, D1);
+  std::vector<uint64_t> X;
   Skeleton cur;
-  {
+  if (P.first > 1) {
+    DevArena* kp = new DevArena(s);
+    arenas.emplace_back(kp);
+    upload_start(P, K, *kp, cur, s);
+  } else {
+    X = P.node_list(0, D1);
     DevArena A(s);
     uint64_t* vals = A.alloc<uint64_t>(D1);
     call_bb(bb, ctx, P, 1, 1, P.y.data(), X.data(), D1, vals, s);
@@ -531,8 +568,9 @@ static void reconstruct_poly(const zr_params* params, zr_blackbox_fn bb, void* c
     arenas.emplace_back(kp);
     lift_stage(P, 0, root, vals, D1, K.W(0), K.ypow(0), *kp, cur, s, d_status);
   }
-  g_counters.stages = 1;
-  for (uint32_t k = 2; k <= P.last; ++k) {
+  const uint32_t k0 = P.first > 1 ? P.first : 2;
+  g_counters.stages = k0 - 1;
+  for (uint32_t k = k0; k <= P.last; ++k) {
     const uint32_t kvar = k - 1;
     const uint32_t R = P.deg[kvar];
     D1 = D1s[kvar];

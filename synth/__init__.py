@@ -381,6 +381,30 @@ def config_workload(idx: int, nprobes: int = 2) -> PolyWorkload:
     return poly_workload(name, n, d, t, idx, 1000 + idx, nprobes)
 
 
+def stage_result(poly: SparsePoly, anchor, L: int):
+    """f(x_1..x_L, anchor_{L+1}..anchor_n) of a hidden polynomial: the known
+    answer of reconstruction stage L.  Exponents beyond L set to 0, terms with
+    equal prefixes summed mod p, zero sums dropped, lexicographic order.
+    Returns (exps [nterms][nvars] uint16, coefs uint64)."""
+    p = poly.p
+    c = poly.coefs.astype(object)
+    for v in range(L, poly.nvars):
+        tab = [1]
+        for _ in range(int(poly.exps[:, v].max()) if poly.nterms else 0):
+            tab.append(tab[-1] * int(anchor[v]) % p)
+        tab = np.array(tab, dtype=object)
+        c = c * tab[poly.exps[:, v].astype(np.int64)] % p
+    if poly.nterms == 0:
+        return np.zeros((0, poly.nvars), dtype=np.uint16), np.zeros(0, dtype=np.uint64)
+    pre = poly.exps[:, :L]
+    starts = np.flatnonzero(np.r_[True, np.any(pre[1:] != pre[:-1], axis=1)])
+    sums = np.add.reduceat(c, starts) % p
+    keep = np.array([int(x) != 0 for x in sums], dtype=bool)
+    e = np.zeros((int(keep.sum()), poly.nvars), dtype=np.uint16)
+    e[:, :L] = pre[starts[keep]]
+    return e, np.array([int(x) for x in sums[keep]], dtype=np.uint64)
+
+
 def batch_workload(count: int = 4096, seed: int = 4, tmin: int = 10, tmax: int = 20_000, deg: int = 30,
                    nmin: int = 3, nmax: int = 8, nprobes: int = 2, p: Optional[int] = None) -> List[PolyWorkload]:
     """Many independent instances sharing p: n uniform in [nmin, nmax], t

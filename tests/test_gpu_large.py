@@ -39,23 +39,7 @@ def cfg3():
 
 
 def projection(poly, anchor, L):
-    """f(x_1..x_L, anchor_{L+1}..anchor_n): exponents beyond L set to 0, terms
-    with equal prefixes summed mod p, zero sums dropped (lexicographic order)."""
-    p = poly.p
-    c = poly.coefs.astype(object)
-    for v in range(L, poly.nvars):
-        tab = [1]
-        for _ in range(int(poly.exps[:, v].max())):
-            tab.append(tab[-1] * int(anchor[v]) % p)
-        tab = np.array(tab, dtype=object)
-        c = c * tab[poly.exps[:, v].astype(np.int64)] % p
-    pre = poly.exps[:, :L]
-    starts = np.flatnonzero(np.r_[True, np.any(pre[1:] != pre[:-1], axis=1)])
-    sums = np.add.reduceat(c, starts) % p
-    keep = np.array([int(s) != 0 for s in sums], dtype=bool)
-    e = np.zeros((int(keep.sum()), poly.nvars), dtype=np.uint16)
-    e[:, :L] = pre[starts[keep]]
-    return e, np.array([int(s) for s in sums[keep]], dtype=np.uint64)
+    return synth.stage_result(poly, anchor, L)
 
 
 def test_config3_first_stages_match_oracle(zr, cfg3):

@@ -253,3 +253,52 @@ def test_zippel_one_wave_pass(zr):
             zr.solve_variant()
         assert np.array_equal(base[0], pc[0]) and np.array_equal(base[1], pc[1])
         assert np.array_equal(pc[0], w.hidden.exps) and np.array_equal(pc[1], w.hidden.coefs)
+
+
+# ---------------------------------------------------------------- resumption from a stage's result
+
+@pytest.mark.parametrize("nvars,deg,nterms,seed,k", [(3, 10, 50, 1, 2), (3, 10, 50, 1, 3), (4, 12, 900, 23, 3),
+                                                     (5, 8, 2000, 31, 5)])
+def test_resume_from_oracle_stage(zr, nvars, deg, nterms, seed, k):
+    """Stages k..n run from the oracle's stage-(k-1) result equal the
+    oracle's whole reconstruction (and the hidden polynomial)."""
+    w = synth.poly_workload("resume", nvars, deg, nterms, seed, 1000 + seed, nprobes=2)
+    box = synth.BlackBox(w.hidden)
+    start = oracle.zippel(w.p, w.deg, w.schedule, box, last_stage=k - 1)
+    _note(f"resume at stage {k}: n={nvars} t={nterms}, start of {len(start[1])} terms")
+    e, c = zr.reconstruct(w.p, w.deg, _box(zr, w.hidden), sched=w.schedule, first_stage=k, start=start)
+    oe, oc = oracle.zippel(w.p, w.deg, w.schedule, box)
+    assert np.array_equal(e, oe) and np.array_equal(c, oc)
+    assert np.array_equal(e, w.hidden.exps) and np.array_equal(c, w.hidden.coefs)
+    # stopping early after resuming: stage L's result
+    if k < nvars:
+        e, c = zr.reconstruct(w.p, w.deg, _box(zr, w.hidden), sched=w.schedule, first_stage=k, start=start,
+                              last_stage=k)
+        oe, oc = oracle.zippel(w.p, w.deg, w.schedule, box, last_stage=k)
+        assert np.array_equal(e, oe) and np.array_equal(c, oc)
+
+
+def test_resume_rejects_bad_start(zr):
+    w = synth.config_workload(1)
+    box = _box(zr, w.hidden)
+    e, c = oracle.zippel(w.p, w.deg, w.schedule, synth.BlackBox(w.hidden), last_stage=1)
+    bad = []
+    e2 = e.copy()
+    e2[0, 1] = 1  # an exponent of a variable not reached yet
+    bad.append((2, (e2, c)))
+    bad.append((2, (e[::-1].copy(), c[::-1].copy())))  # not ascending
+    c2 = c.copy()
+    c2[0] = w.p  # coefficient out of range
+    bad.append((2, (e, c2)))
+    e3 = e.copy()
+    e3[-1, 0] = w.deg[0] + 1  # beyond the degree bound
+    bad.append((2, (e3, c)))
+    bad.append((5, (e, c)))  # beyond the last stage
+    for k, st in bad:
+        with pytest.raises(zr.ZippelError) as ei:
+            zr.reconstruct(w.p, w.deg, box, sched=w.schedule, first_stage=k, start=st)
+        assert ei.value.code == zr.ZR_EINVAL
+    # an empty start skeleton is a valid (zero) polynomial at stage 1
+    z = (np.zeros((0, 3), np.uint16), np.zeros(0, np.uint64))
+    e, c = zr.reconstruct(w.p, w.deg, box, sched=w.schedule, first_stage=2, start=z, nprobes=0)
+    assert len(c) == 0

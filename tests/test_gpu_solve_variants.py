@@ -1,12 +1,10 @@
 """GPU parity of the one-system transposed Vandermonde solve (§1, §2.2) for
-every form of its dot-product pass: one wave per right-hand-side tile, the
-producer/consumer form and the int8 matrix-core form (signed base-256 digits,
-exact int32 sums).  Each solve goes through zr_vandermonde_solve and is
-compared with the oracle's solve bit for bit; sizes straddle the row blocks
-(16, 64), the chunk groups and the right-hand-side tiles (1, 2, 15, 16, 17,
-30, 33, 40), and the values include the edges of the field and small primes.
-Whole reconstructions with the matrix-core pass are checked against the
-oracle and the hidden polynomial."""
+both forms of its dot-product pass on the integer vector ALU: one wave per
+right-hand-side tile, and the producer/consumer form.  Each solve goes
+through zr_vandermonde_solve and is compared with the oracle's solve bit for
+bit; sizes straddle the row blocks (64), the chunks and the right-hand-side
+tiles (1, 2, 15, 16, 17, 30, 33, 40), and the values include the edges of the
+field and small primes."""
 import random
 import sys
 
@@ -18,7 +16,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = ["waves", "producer_consumer", "mfma"]
+VARIANTS = ["waves", "producer_consumer"]
 
 
 def _note(msg):
@@ -62,7 +60,7 @@ def test_solve_matches_oracle(zr, variant, t, R):
 
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_solve_field_edges(zr, variant):
-    """Largest prime below 2^63, values at 0, 1, p-1, p/2 +- 1 (the digit split's turning point)."""
+    """Largest prime below 2^63, values at 0, 1, p-1, p/2 +- 1."""
     p = (1 << 63) - 25
     h = p // 2
     m = np.array([1, 2, p - 1, p - 2, 1 << 62, 3, h, h + 1, h + 2, h - 1] + list(range(5, 75)), dtype=np.uint64)
@@ -98,12 +96,11 @@ def test_solve_singular_and_empty(zr, variant):
     assert st == 0 and got.size == 0
 
 
-@pytest.mark.parametrize("variant", ["producer_consumer", "mfma"])
+@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("t,R", [(10_000, 30), (20_000, 40)])
 def test_solve_large_sampled_rows(zr, variant, t, R):
-    """Full-size systems (the n = 6 stage size and a larger one) with the
-    default and the matrix-core pass: rows sampled and solved one by one by
-    the oracle."""
+    """Full-size systems (the n = 6 stage size and a larger one) with both
+    passes: rows sampled and solved one by one by the oracle."""
     p = synth.make_prime()
     g = synth.SplitMix64(t + R)
     m = g.uniform_block(1, p, t)
@@ -119,37 +116,17 @@ def test_solve_large_sampled_rows(zr, variant, t, R):
     assert np.array_equal(got[:, rows], want)
 
 
-def _box(zr, hidden):
-    b = synth.BlackBox(hidden)
-    return zr.HostBlackBox(b.eval, hidden.nvars)
-
-
-def test_reconstruct_mfma_config1_every_stage(zr):
-    w = synth.config_workload(1)
-    zr.solve_variant("mfma")
-    for L in range(1, 4):
-        e, c = zr.reconstruct(w.p, w.deg, _box(zr, w.hidden), sched=w.schedule, last_stage=L)
-        oe, oc = oracle.zippel(w.p, w.deg, w.schedule, synth.BlackBox(w.hidden), last_stage=L)
-        assert np.array_equal(e, oe) and np.array_equal(c, oc)
-
-
-@pytest.mark.parametrize("nvars,deg,nterms,seed", [(4, 12, 2000, 21), (3, 40, 700, 9), (3, 30, 3000, 33)])
-def test_reconstruct_mfma_matches_oracle(zr, nvars, deg, nterms, seed):
-    w = synth.poly_workload("mf", nvars, deg, nterms, seed, 1000 + seed, nprobes=2)
-    zr.solve_variant("mfma")
-    e, c = zr.reconstruct(w.p, w.deg, _box(zr, w.hidden), sched=w.schedule)
-    oe, oc = oracle.zippel(w.p, w.deg, w.schedule, synth.BlackBox(w.hidden))
-    assert np.array_equal(e, oe) and np.array_equal(c, oc)
-    assert np.array_equal(e, w.hidden.exps) and np.array_equal(c, w.hidden.coefs)
-
-
-def test_reconstruct_mfma_config2_full(zr):
-    """n = 6, per-variable degree 30, 10^4 terms: equals the hidden polynomial."""
-    w = synth.config_workload(2)
-    zr.solve_variant("mfma")
-    _note("config2 full reconstruction, matrix-core pass")
-    e, c = zr.reconstruct(w.p, w.deg, synth.DeviceBlackBox(w.hidden, nthreads=16), sched=w.schedule)
-    assert np.array_equal(e, w.hidden.exps) and np.array_equal(c, w.hidden.coefs)
+def test_unknown_variant_rejected(zr):
+    """Only the two integer vector ALU passes exist; any other value is an
+    argument error that leaves the selection unchanged."""
+    zr.solve_variant("waves")
+    assert zr.lib().zr_solve_variant(2) == zr.ZR_EINVAL
+    assert zr.lib().zr_solve_variant(-1) == zr.ZR_EINVAL
+    p = synth.make_prime()
+    m, rhs = _system(p, 40, 3, 4)
+    got, st = zr.vandermonde_solve(p, m, rhs)
+    assert st == 0 and np.array_equal(got, oracle.vandermonde_solve(p, m, rhs))
+    zr.solve_variant()
 
 
 def test_timing_dots_only(zr):
