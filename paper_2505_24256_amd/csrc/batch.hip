@@ -692,16 +692,17 @@ struct BPlan {
 };
 
 // With the producer/consumer pass selected, systems of more than kPcMinR
-// right-hand sides that are not packed take its tiling (at most kPcRT per
-// consumer wave) and go to the persistent producer/consumer queue.
+// right-hand sides that are not packed take its tiling (pc_tiles_for: at most
+// kPcRT per consumer wave, workgroups of a multiple of four waves) and go to
+// the persistent producer/consumer queue.
 static BPlan bplan(uint32_t t, uint32_t R, double cap, const Tuning& T) {
   BPlan P;
   P.t = t;
   P.R = R;
   const BandTuning& bt = T.band[band_of(t)];
   P.packed = bt.packed && t < 64 ? 1 : 0;
-  P.pc = !P.packed && R > kPcMinR && cdiv(R, kPcRT) <= kPcMaxTiles && vsolve_uses_pc() ? 1 : 0;
-  P.ntile = P.pc ? cdiv(R, kPcRT) : cdiv(R, kMaxRT);
+  P.pc = !P.packed && R > kPcMinR && pc_tiles_for(R) && vsolve_uses_pc() ? 1 : 0;
+  P.ntile = P.pc ? pc_tiles_for(R) : cdiv(R, kMaxRT);
   P.RT = cdiv(R, P.ntile);
   P.ldv = (3 * P.RT + 2 + 15) & ~15u;
   uint32_t S = 1;

@@ -52,10 +52,11 @@ VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
   const uint32_t row_blocks = std::max<uint32_t>(1, cdiv(t, 64));
   // Above kPcMinR right-hand sides the chain runs once per row block in a
   // producer wave (k_vs_dots_pc) and consumer waves take tiles of at most
-  // kPcRT; the unit of the launch is then a workgroup of 1 + ntile waves.
-  P.pc = (R > kPcMinR && cdiv(R, kPcRT) <= kPcMaxTiles && dots_pc_enabled()) ? 1 : 0;
+  // kPcRT; the unit of the launch is then a workgroup of 1 + ntile waves, a
+  // multiple of four (pc_tiles_for).
+  P.pc = (R > kPcMinR && pc_tiles_for(R) && dots_pc_enabled()) ? 1 : 0;
   if (P.pc) {
-    P.ntile = cdiv(R, kPcRT);
+    P.ntile = pc_tiles_for(R);
     P.RT = cdiv(R, P.ntile);
   } else {
     P.ntile = R == 0 ? 1 : cdiv(R, kPlanRT);

@@ -19,7 +19,7 @@ import ctypes
 import math
 import os
 from dataclasses import dataclass, field
-from typing import List, Optional, Sequence
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -412,16 +412,28 @@ def batch_workload(count: int = 4096, seed: int = 4, tmin: int = 10, tmax: int =
     degree bound `deg`; instance i uses hidden-polynomial seed seed*10^6 + i and
     schedule seed seed*10^6 + 500000 + i."""
     p = make_prime() if p is None else p
+    return [batch_instance(i, n, t, seed, deg, nprobes, p)
+            for i, (n, t) in enumerate(batch_shapes(count, seed, tmin, tmax, deg, nmin, nmax))]
+
+
+def batch_shapes(count: int = 4096, seed: int = 4, tmin: int = 10, tmax: int = 20_000, deg: int = 30,
+                 nmin: int = 3, nmax: int = 8) -> List[Tuple[int, int]]:
+    """(n, t) of each instance of batch_workload, without building the polynomials."""
     g = SplitMix64(seed * 7919 + 1)
     out = []
-    for i in range(count):
+    for _ in range(count):
         n = nmin + int(g.uniform(0, nmax - nmin + 1))
         u = g.next() / 2.0 ** 64
         t = int(round(math.exp(math.log(tmin) + u * (math.log(tmax) - math.log(tmin)))))
-        t = max(1, min(t, (deg + 1) ** n))
-        out.append(poly_workload(f"b{i}", n, deg, t, seed * 1_000_000 + i, seed * 1_000_000 + 500_000 + i,
-                                 nprobes, p))
+        out.append((n, max(1, min(t, (deg + 1) ** n))))
     return out
+
+
+def batch_instance(i: int, n: int, t: int, seed: int = 4, deg: int = 30, nprobes: int = 2,
+                   p: Optional[int] = None) -> PolyWorkload:
+    """Instance i of batch_workload (with its (n, t) from batch_shapes)."""
+    return poly_workload(f"b{i}", n, deg, t, seed * 1_000_000 + i, seed * 1_000_000 + 500_000 + i, nprobes,
+                         make_prime() if p is None else p)
 
 
 def rational_workload(nvars: int, total_deg: int, tnum: int, tden: int, seed: int,
