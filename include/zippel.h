@@ -182,6 +182,25 @@ zr_status zr_thiele_slices(uint64_t p, uint32_t T, uint32_t nk, const uint64_t* 
 zr_status zr_vandermonde_solve(uint64_t p, uint32_t t, uint32_t R, const uint64_t* d_mono, const uint64_t* d_rhs,
                                uint64_t* d_out, int32_t* d_status, hipStream_t stream);
 
+/* zr_vandermonde_solve for callers that cannot allocate device memory (code
+ * under stream capture, serving loops that forbid hipMalloc): same arguments,
+ * same results, same kernels, but the master polynomial and the solve's
+ * workspace live in one fixed 64 MiB device array inside the library (one per
+ * GPU, held until the process ends) instead of memory from the allocator.  The
+ * call allocates nothing and launches no memset: its status word is cleared by
+ * a kernel, and every workspace word is written before it is read, so nothing
+ * left by an earlier call is used.
+ *   Size limit: a system whose workspace does not fit the array (at R = 40,
+ *   t above about 60 000; the dot-product pass runs in fewer chunks before
+ *   that) returns ZR_EINVAL before any device work, with the reason in
+ *   zr_last_error().
+ *   Every call on one GPU uses that GPU's one array: calls that overlap on the
+ *   same GPU (other streams, other threads) race and must be serialised by the
+ *   caller.  The first call on a device looks the array's address up once. */
+zr_status zr_vandermonde_solve_noalloc(uint64_t p, uint32_t t, uint32_t R, const uint64_t* d_mono,
+                                       const uint64_t* d_rhs, uint64_t* d_out, int32_t* d_status,
+                                       hipStream_t stream);
+
 /* Batched transposed Vandermonde solve (the O(t^2) step of §1 and §2.2, many
  * systems and right-hand sides at once).  System s has t_s unknowns and R_s
  * right-hand sides; for each right-hand side j it solves

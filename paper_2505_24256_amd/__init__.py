@@ -29,7 +29,7 @@ EXPORTS = [
     "zr_microbench", "zippel_reconstruct_batch", "zr_autotune", "zr_tuning_get", "zr_tuning_set",
     "zr_server_create", "zr_server_destroy", "zr_server_submit", "zr_server_step", "zr_server_poll",
     "zr_server_get_stats", "zr_batch_graphs", "zr_solve_variant", "zr_thiele_slices",
-    "zr_vandermonde_solve",
+    "zr_vandermonde_solve", "zr_vandermonde_solve_noalloc",
 ]
 MB_KINDS = {"mad_u64_u32": 0, "mul_lo_u32": 1, "mul_hi_u32": 2, "add_u32": 3, "mac192": 4, "shoup": 5, "copy": 6}
 
@@ -111,6 +111,7 @@ def lib():
         L.vandermonde_solve_batch.argtypes = [sz, u64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.zr_thiele_slices.argtypes = [u64, u32, u32, vp, vp, vp, vp, vp, vp, vp, vp]
         L.zr_vandermonde_solve.argtypes = [u64, u32, u32, vp, vp, vp, vp, vp]
+        L.zr_vandermonde_solve_noalloc.argtypes = [u64, u32, u32, vp, vp, vp, vp, vp]
         L.zippel_reconstruct_batch.argtypes = [u32, ctypes.POINTER(ZrParams), vp, vp, vp, ctypes.POINTER(ZrPoly),
                                                vp]
         L.zr_autotune.argtypes = [u64, vp, ctypes.POINTER(ZrBandChoice)]
@@ -569,6 +570,14 @@ def vandermonde_solve(p: int, m, rhs, stream=None):
     torch.cuda.synchronize()
     out = d_o.cpu().numpy().view(np.uint64)[:R * t].reshape(R, t)
     return out, int(d_s.cpu().item())
+
+
+def vandermonde_solve_noalloc(p: int, d_mono, d_rhs, d_out, d_status, t: int, R: int, stream=None) -> int:
+    """zr_vandermonde_solve_noalloc on caller-owned device tensors (d_mono [t],
+    d_rhs and d_out [R][t] of int64 holding the u64 values, d_status int32 [1]).
+    Asynchronous on `stream`; returns the call's status."""
+    return int(lib().zr_vandermonde_solve_noalloc(p, t, R, d_mono.data_ptr(), d_rhs.data_ptr(), d_out.data_ptr(),
+                                                  d_status.data_ptr(), _stream(stream)))
 
 
 def thiele_slices(p: int, x, f, stream=None):
