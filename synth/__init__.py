@@ -241,6 +241,67 @@ def random_poly(p: int, nvars: int, deg: Sequence[int] | int, nterms: int, seed:
     return SparsePoly(p, nvars, exps, coefs).sorted()
 
 
+@dataclass
+class QPoly:
+    """Polynomial with rational coefficients num[l]/den[l] (Python ints, den > 0,
+    gcd 1), exponents as in SparsePoly: the black box of a reconstruction over
+    several primes.  ``mod(p)`` is its image over F_p."""
+    nvars: int
+    exps: np.ndarray
+    num: List[int]
+    den: List[int]
+
+    @property
+    def nterms(self) -> int:
+        return int(self.exps.shape[0])
+
+    def mod(self, p: int) -> SparsePoly:
+        c = np.array([(a % p) * pow(b, -1, p) % p for a, b in zip(self.num, self.den)], dtype=np.uint64)
+        return SparsePoly(p, self.nvars, self.exps.copy(), c)
+
+
+def random_qpoly(nvars: int, deg: Sequence[int] | int, nterms: int, bits: int, seed: int) -> QPoly:
+    """Exponents as random_poly (distinct, uniform in prod [0, D_v]); numerators
+    uniform in (-2^bits, 2^bits) without 0, denominators uniform in [1, 2^bits),
+    each fraction reduced.  Draws: the exponent stream of seed, then per term a
+    numerator magnitude, its sign and a denominator from seed + 1, in 64-bit
+    words (low word first)."""
+    shape = random_poly(3, nvars, deg, nterms, seed)  # exponents only (F_3 coefficients unused)
+    g = SplitMix64(seed + 1)
+    words = (bits + 63) // 64
+
+    def draw(lo: int) -> int:
+        while True:
+            x = 0
+            for w in range(words):
+                x |= g.next() << (64 * w)
+            x &= (1 << bits) - 1
+            if x >= lo:
+                return x
+    num, den = [], []
+    for _ in range(nterms):
+        a = draw(1)
+        if g.next() & 1:
+            a = -a
+        b = draw(1)
+        d = math.gcd(a, b)
+        num.append(a // d)
+        den.append(b // d)
+    return QPoly(nvars, shape.exps, num, den)
+
+
+def prime_list(count: int, seed: int = PRIME_SEED) -> List[int]:
+    """count distinct primes in (2^62, 2^63): make_prime(seed), make_prime(seed + 1), ..."""
+    out: List[int] = []
+    j = 0
+    while len(out) < count:
+        q = make_prime(seed + j)
+        if q not in out:
+            out.append(q)
+        j += 1
+    return out
+
+
 def _simplex_row(g: SplitMix64, nvars: int, total: int) -> np.ndarray:
     """Uniform exponent vector with sum <= total (stars and bars: a uniform
     nvars-subset of {0..total+nvars-1} gives the bar positions)."""

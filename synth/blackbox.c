@@ -55,8 +55,10 @@ static void eval_poly(const zs_poly *P, uint32_t k, uint64_t i_first, uint64_t n
   /* per-term constants */
   uint64_t *Y = (uint64_t *)malloc(sizeof(uint64_t) * (T ? T : 1));
   uint64_t *W = (uint64_t *)malloc(sizeof(uint64_t) * (T ? T : 1) * (nj ? nj : 1));
+  /* k = nvars + 1: every variable at its Zippel power, no x_k (xk[0] unused) */
+  const int has_xk = k <= n;
   uint32_t maxd = 0;
-  for (uint32_t h = 0; h < T; ++h)
+  for (uint32_t h = 0; h < T && has_xk; ++h)
     if (P->exps[(size_t)h * n + (k - 1)] > maxd) maxd = P->exps[(size_t)h * n + (k - 1)];
   uint64_t *xpow = (uint64_t *)malloc(sizeof(uint64_t) * (maxd + 1) * (nj ? nj : 1));
   for (uint64_t jj = 0; jj < nj; ++jj) {
@@ -67,10 +69,11 @@ static void eval_poly(const zs_poly *P, uint32_t k, uint64_t i_first, uint64_t n
   for (uint32_t h = 0; h < T; ++h) {
     const uint16_t *e = P->exps + (size_t)h * n;
     uint64_t yh = 1 % p, ah = P->coefs[h] % p;
-    for (uint32_t v = 0; v + 1 < k; ++v) yh = mm(yh, pw(y[v], e[v], p), p);
+    for (uint32_t v = 0; v + 1 < k && v < n; ++v) yh = mm(yh, pw(y[v], e[v], p), p);
     for (uint32_t v = k; v < n; ++v) ah = mm(ah, pw(anchor[v], e[v], p), p);
     Y[h] = yh;
-    for (uint64_t jj = 0; jj < nj; ++jj) W[(size_t)h * nj + jj] = mm(ah, xpow[jj * (maxd + 1) + e[k - 1]], p);
+    const uint32_t ek = has_xk ? e[k - 1] : 0;
+    for (uint64_t jj = 0; jj < nj; ++jj) W[(size_t)h * nj + jj] = mm(ah, xpow[jj * (maxd + 1) + ek], p);
   }
   const uint64_t nblk = (ni + BLK - 1) / BLK;
 #pragma omp parallel num_threads(nthreads > 0 ? nthreads : omp_get_max_threads())
@@ -140,12 +143,14 @@ uint64_t zs_group_stage(const void *ctx, int den, uint32_t k, const uint64_t *y,
   uint64_t *start = (uint64_t *)malloc(sizeof(uint64_t) * (T + 1));
   for (uint32_t h = 0; h < T; ++h) {
     int same = h > 0;
-    for (uint32_t v = 0; same && v + 1 < k; ++v) same = P->exps[(size_t)h * n + v] == P->exps[(size_t)(h - 1) * n + v];
+    for (uint32_t v = 0; same && v + 1 < k && v < n; ++v) same = P->exps[(size_t)h * n + v] == P->exps[(size_t)(h - 1) * n + v];
     if (!same) start[ng++] = h;
   }
   start[ng] = T;
+  /* k = nvars + 1: every variable at its Zippel power, no x_k (xk[0] unused) */
+  const int has_xk = k <= n;
   uint32_t maxd = 0;
-  for (uint32_t h = 0; h < T; ++h)
+  for (uint32_t h = 0; h < T && has_xk; ++h)
     if (P->exps[(size_t)h * n + (k - 1)] > maxd) maxd = P->exps[(size_t)h * n + (k - 1)];
   uint64_t *xpow = (uint64_t *)malloc(sizeof(uint64_t) * (maxd + 1) * (nj ? nj : 1));
   for (uint64_t jj = 0; jj < nj; ++jj) {
@@ -156,15 +161,16 @@ uint64_t zs_group_stage(const void *ctx, int den, uint32_t k, const uint64_t *y,
   for (uint64_t g = 0; g < ng; ++g) {
     const uint16_t *e0 = P->exps + (size_t)start[g] * n;
     uint64_t yv = 1 % p;
-    for (uint32_t v = 0; v + 1 < k; ++v) yv = mm(yv, pw(y[v], e0[v], p), p);
+    for (uint32_t v = 0; v + 1 < k && v < n; ++v) yv = mm(yv, pw(y[v], e0[v], p), p);
     Y[g] = yv;
     for (uint64_t jj = 0; jj < nj; ++jj) W[g * nj + jj] = 0;
     for (uint64_t h = start[g]; h < start[g + 1]; ++h) {
       const uint16_t *e = P->exps + (size_t)h * n;
       uint64_t a = P->coefs[h] % p;
       for (uint32_t v = k; v < n; ++v) a = mm(a, pw(anchor[v], e[v], p), p);
+      const uint32_t ek = has_xk ? e[k - 1] : 0;
       for (uint64_t jj = 0; jj < nj; ++jj) {
-        uint64_t w = mm(a, xpow[jj * (maxd + 1) + e[k - 1]], p);
+        uint64_t w = mm(a, xpow[jj * (maxd + 1) + ek], p);
         uint64_t s = W[g * nj + jj] + w;
         W[g * nj + jj] = s >= p ? s - p : s;
       }
