@@ -72,7 +72,10 @@ void zr_poly_free(zr_poly* poly);
  *   x_v = anchor[v]             for v > k-1   (variables not yet reached)
  * and its value goes to d_vals[jj * ni + ii].  All three arrays are host memory.
  * A single explicit point x is expressed as k = nvars, ni = 1, i_first = 1,
- * y = x[0..n-2], xk = {x[n-1]}. */
+ * y = x[0..n-2], xk = {x[n-1]}.
+ * k = nvars + 1 (the further primes of zippel_reconstruct_rational): every
+ * variable at its Zippel power, x_v = y[v]^(i_first + ii) for all v, nj = 1,
+ * anchor and xk unused.  The values are always wanted modulo p below. */
 typedef struct {
   uint32_t nvars;
   uint32_t k;          /* stage, 1-based */
@@ -83,6 +86,9 @@ typedef struct {
   const uint64_t* anchor;
   const uint64_t* xk;
   uint64_t p;
+  uint32_t nexpr;      /* expressions wanted per point: value of expression e at
+                          point (ii, jj) goes to d_vals[(e * nj + jj) * ni + ii]
+                          (zippel_reconstruct_multi); 1 for every other call */
 } zr_points;
 
 /* Black box: fill d_vals[nj*ni] (device memory) with values in [0, p), ordered
@@ -121,6 +127,20 @@ typedef struct {
                                 coefficients < p); otherwise ignored.  Copied before the call returns. */
 } zr_params;
 
+/* Result with rational coefficients (zippel_reconstruct_rational).
+ * Library-owned host memory; release with zr_qpoly_free. */
+typedef struct {
+  uint32_t nvars;
+  uint64_t nterms;
+  uint32_t nwords;  /* 64-bit words per magnitude */
+  uint32_t nprimes; /* primes used, the confirming one included */
+  uint16_t* exps;   /* [nterms][nvars], lexicographically ascending */
+  uint64_t* num;    /* [nterms][nwords] |numerator|, least significant word first */
+  uint8_t* neg;     /* [nterms] 1 when the numerator is negative */
+  uint64_t* den;    /* [nterms][nwords] denominator > 0, coprime to the numerator */
+} zr_qpoly;
+void zr_qpoly_free(zr_qpoly* q);
+
 /* Number of nodes beyond the anchor that the balanced path needs for a variable
  * with numerator/denominator degree bounds (a, b): a continued fraction with
  * coefficients b_0..b_m has type (ceil(m/2), floor(m/2)), so m = max(2a-1, 2b),
@@ -147,6 +167,79 @@ zr_status zippel_reconstruct(const zr_params* params, zr_blackbox_fn bb, void* c
  * lowest terms with den(0,...,0) = 1 (ZR_ENORM if den has no constant term). */
 zr_status zippel_balanced_reconstruct(const zr_params* params, zr_blackbox_fn bb, void* ctx, hipStream_t stream,
                                       zr_poly* num, zr_poly* den);
+
+/* Polynomial Zippel without known degree bounds (Introduction: a result is
+ * accepted when further probes reproduce it).  Stage k samples x_k at its
+ * anchor and then at the schedule's nodes, eight at a time; after each node m
+ * it forms, for every term, the divided difference of order m of the term's
+ * values at x_0..x_m, and stops at the first m whose last `confirm` orders
+ * vanish for all terms.  The stage's degree is D = m - confirm; the terms are
+ * lifted over x_0..x_D as in zippel_reconstruct.
+ *   params     as for zippel_reconstruct, with deg[v] read as a cap: at most
+ *              deg[v] + confirm nodes of x_v are sampled, and an explicit
+ *              schedule must hold that many; last_stage 0 or nvars,
+ *              first_stage 0 or 1, deg[v] + confirm <= 127
+ *   confirm    1..8 vanishing orders that end a stage
+ *   deg_found  host [nvars] or NULL: the degree found for each variable
+ * Errors as zippel_reconstruct; ZR_EPROBE also when a stage reaches its cap
+ * without `confirm` vanishing orders. */
+zr_status zippel_reconstruct_adaptive(const zr_params* params, uint32_t confirm, zr_blackbox_fn bb, void* ctx,
+                                      hipStream_t stream, zr_poly* out, uint32_t* deg_found);
+
+/* Several polynomials reconstructed together (§2.2: one solve serves several
+ * expressions of various degrees).  The black box returns all nexpr values
+ * at each point (zr_points.nexpr = nexpr).  Stage k solves ONE transposed
+ * Vandermonde system on the union of the expressions' stage-(k-1) skeletons
+ * with sum_e deg[e][k-1] right-hand sides; each expression is lifted by its
+ * own Newton interpolation over the first deg[e][k-1] + 1 nodes of x_k.
+ *   params   prime, schedule, probes as for zippel_reconstruct; params->deg is
+ *            ignored (the schedule needs, per variable, the largest bound);
+ *            last_stage 0 or nvars, first_stage 0 or 1, deg_den NULL
+ *   nexpr    1..64 expressions
+ *   deg      host [nexpr][nvars] degree bounds of each expression
+ *   out      [nexpr] results (zr_poly_free each); probes compare every
+ *            expression with the black box
+ * Errors as zippel_reconstruct; on error every out[e] is left empty. */
+zr_status zippel_reconstruct_multi(const zr_params* params, uint32_t nexpr, const uint32_t* deg, zr_blackbox_fn bb,
+                                   void* ctx, hipStream_t stream, zr_poly* out);
+
+/* Polynomial with rational coefficients from its values modulo several
+ * primes: the modular reconstruction is finished by the recovery of rational
+ * numbers (§1; the multi-prime Zippel routine of §2.2).
+ *   params     the first prime and its reconstruction (params->p, schedule,
+ *              degree bounds, probes) exactly as for zippel_reconstruct, which
+ *              runs first and fixes the term set; last_stage must be 0 or
+ *              nvars and first_stage 0 or 1
+ *   primes     nprimes further primes, used in order (1 + nprimes <= 8); every
+ *              prime, the first included, lies in (2^62, 2^63) and all differ
+ *   bb, ctx    the black box; each call names its prime in zr_points.p.  For
+ *              further prime j (1-based) it is asked once for the t points
+ *              k = nvars + 1 (every x_v = y_v^i, i = 1..t, bases y drawn by
+ *              zr_schedule from seed params->seed + j)
+ * Each further prime gives every term's coefficient modulo it by one
+ * transposed Vandermonde system with a single right-hand side; after each,
+ * the fractions reconstructed from the primes so far (Chinese remainder
+ * theorem, then Wang's rational reconstruction with |num|, den < 2^e,
+ * e = floor((bits(P) - 2) / 2) for the product P of those primes) are tested
+ * against the next prime's residues, and the call returns when all agree.
+ * Errors: as zippel_reconstruct for the first prime; ZR_EPROBE when the
+ * primes run out before such a confirmation; ZR_ESINGULAR when two monomial
+ * values coincide modulo a further prime. */
+zr_status zippel_reconstruct_rational(const zr_params* params, const uint64_t* primes, uint32_t nprimes,
+                                      zr_blackbox_fn bb, void* ctx, hipStream_t stream, zr_qpoly* out);
+
+/* Coefficients of a known term set modulo p (the further-prime step of
+ * zippel_reconstruct_rational): solves sum_l a_l m_l^i = v_i, i = 1..t, with
+ * m_l = prod_v y[v]^e_{l,v} over all nvars variables, as W(m_l) / (m_l M'(m_l))
+ * with W's coefficients w_d = sum_r M_{r+d+1} v_{r+1} (M the master polynomial).
+ *   h_exps    host [t][nvars] exponents of distinct monomials
+ *   y         host [nvars] bases, each < p
+ *   d_vals    device [t]: v_i at [i-1]
+ *   d_out     device [t]: a_l at [l]
+ *   d_status  device int32: ZR_OK or ZR_ESINGULAR (two m_l equal, or one 0)
+ * Asynchronous on `stream` after the exponent upload; argument errors return at once. */
+zr_status zr_skeleton_solve(uint64_t p, uint32_t nvars, uint32_t t, const uint16_t* h_exps, const uint64_t* y,
+                            const uint64_t* d_vals, uint64_t* d_out, int32_t* d_status, hipStream_t stream);
 
 /* Per-slice Thiele reconstruction (eq. 2), the univariate step of balanced
  * Zippel (§2.2).  For each of T slices: the shortest continued fraction

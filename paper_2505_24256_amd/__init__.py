@@ -29,7 +29,8 @@ EXPORTS = [
     "zr_microbench", "zippel_reconstruct_batch", "zr_autotune", "zr_tuning_get", "zr_tuning_set",
     "zr_server_create", "zr_server_destroy", "zr_server_submit", "zr_server_step", "zr_server_poll",
     "zr_server_get_stats", "zr_batch_graphs", "zr_solve_variant", "zr_thiele_slices",
-    "zr_vandermonde_solve", "zr_vandermonde_solve_noalloc",
+    "zr_vandermonde_solve", "zr_vandermonde_solve_noalloc", "zippel_reconstruct_rational", "zr_qpoly_free",
+    "zr_skeleton_solve", "zippel_reconstruct_multi", "zippel_reconstruct_adaptive",
 ]
 MB_KINDS = {"mad_u64_u32": 0, "mul_lo_u32": 1, "mul_hi_u32": 2, "add_u32": 3, "mac192": 4, "shoup": 5, "copy": 6}
 
@@ -46,12 +47,19 @@ class ZrPoints(ctypes.Structure):
     _fields_ = [("nvars", ctypes.c_uint32), ("k", ctypes.c_uint32), ("i_first", ctypes.c_uint64),
                 ("ni", ctypes.c_uint64), ("nj", ctypes.c_uint64), ("y", ctypes.POINTER(ctypes.c_uint64)),
                 ("anchor", ctypes.POINTER(ctypes.c_uint64)), ("xk", ctypes.POINTER(ctypes.c_uint64)),
-                ("p", ctypes.c_uint64)]
+                ("p", ctypes.c_uint64), ("nexpr", ctypes.c_uint32)]
 
 
 class ZrPoly(ctypes.Structure):
     _fields_ = [("nvars", ctypes.c_uint32), ("nterms", ctypes.c_uint64), ("exps", ctypes.POINTER(ctypes.c_uint16)),
                 ("coeffs", ctypes.POINTER(ctypes.c_uint64))]
+
+
+class ZrQPoly(ctypes.Structure):
+    _fields_ = [("nvars", ctypes.c_uint32), ("nterms", ctypes.c_uint64), ("nwords", ctypes.c_uint32),
+                ("nprimes", ctypes.c_uint32), ("exps", ctypes.POINTER(ctypes.c_uint16)),
+                ("num", ctypes.POINTER(ctypes.c_uint64)), ("neg", ctypes.POINTER(ctypes.c_uint8)),
+                ("den", ctypes.POINTER(ctypes.c_uint64))]
 
 
 class ZrParams(ctypes.Structure):
@@ -112,6 +120,14 @@ def lib():
         L.zr_thiele_slices.argtypes = [u64, u32, u32, vp, vp, vp, vp, vp, vp, vp, vp]
         L.zr_vandermonde_solve.argtypes = [u64, u32, u32, vp, vp, vp, vp, vp]
         L.zr_vandermonde_solve_noalloc.argtypes = [u64, u32, u32, vp, vp, vp, vp, vp]
+        L.zippel_reconstruct_rational.argtypes = [ctypes.POINTER(ZrParams), vp, u32, vp, vp, vp,
+                                                  ctypes.POINTER(ZrQPoly)]
+        L.zr_qpoly_free.argtypes = [ctypes.POINTER(ZrQPoly)]
+        L.zr_qpoly_free.restype = None
+        L.zr_skeleton_solve.argtypes = [u64, u32, u32, vp, vp, vp, vp, vp, vp]
+        L.zippel_reconstruct_multi.argtypes = [ctypes.POINTER(ZrParams), u32, vp, vp, vp, vp, ctypes.POINTER(ZrPoly)]
+        L.zippel_reconstruct_adaptive.argtypes = [ctypes.POINTER(ZrParams), u32, vp, vp, vp, ctypes.POINTER(ZrPoly),
+                                                  vp]
         L.zippel_reconstruct_batch.argtypes = [u32, ctypes.POINTER(ZrParams), vp, vp, vp, ctypes.POINTER(ZrPoly),
                                                vp]
         L.zr_autotune.argtypes = [u64, vp, ctypes.POINTER(ZrBandChoice)]
@@ -201,9 +217,10 @@ class HostBlackBox:
     (e.g. ``synth.BlackBox.eval``) as a device black box: values are computed on
     the host and copied to the device buffer the library provides."""
 
-    def __init__(self, fn: Callable, nvars: int):
+    def __init__(self, fn: Callable, nvars: int, with_prime: bool = False):
         self.fn = fn
         self.nvars = nvars
+        self.with_prime = with_prime  # fn(p, k, ...) instead of fn(k, ...): boxes asked modulo several primes
         self.calls = 0
         self.error: Optional[BaseException] = None
         self._cb = BLACKBOX_FN(self._call)
@@ -215,8 +232,9 @@ class HostBlackBox:
             y = np.ctypeslib.as_array(pts.y, shape=(nv,)).copy() if nv else np.zeros(0, np.uint64)
             a = np.ctypeslib.as_array(pts.anchor, shape=(nv,)).copy()
             xk = np.ctypeslib.as_array(pts.xk, shape=(pts.nj,)).copy()
-            vals = _u64(self.fn(pts.k, pts.i_first, pts.ni, y, a, xk)).reshape(-1)
-            if vals.size != pts.ni * pts.nj:
+            args = (pts.k, pts.i_first, pts.ni, y, a, xk)
+            vals = _u64(self.fn(pts.p, *args) if self.with_prime else self.fn(*args)).reshape(-1)
+            if vals.size != pts.ni * pts.nj * max(pts.nexpr, 1):
                 return 11
             st = lib().zr_copy_h2d(d_vals, vals.ctypes.data, vals.nbytes, stream)
             self.calls += 1
@@ -353,6 +371,92 @@ def balanced_reconstruct(p: int, deg_num: Sequence[int], deg_den: Sequence[int],
     if st != ZR_OK:
         raise ZippelError(st, "zippel_balanced_reconstruct")
     return _take(on, len(deg_num)), _take(od, len(deg_num))
+
+
+def reconstruct_adaptive(p: int, caps: Sequence[int], box, sched=None, seed: int = 0, confirm: int = 1,
+                         nprobes: Optional[int] = None, stream=None):
+    """Polynomial Zippel without degree bounds (zippel_reconstruct_adaptive):
+    caps[v] limits the nodes of x_v to caps[v] + confirm.  Returns
+    (exps, coefs, degrees found per variable)."""
+    h = _ParamsHolder(p, caps, None, sched, seed, nprobes, 0)
+    out = ZrPoly()
+    found = np.zeros(len(caps), dtype=np.uint32)
+    fn, ctx = _box_args(box)
+    st = lib().zippel_reconstruct_adaptive(ctypes.byref(h.s), confirm, fn, ctx, _stream(stream), ctypes.byref(out),
+                                           found.ctypes.data)
+    if st != ZR_OK:
+        err = getattr(box, "error", None)
+        raise ZippelError(st, f"zippel_reconstruct_adaptive{' (' + repr(err) + ')' if err else ''}")
+    e, c = _take(out, len(caps))
+    return e, c, [int(d) for d in found]
+
+
+def reconstruct_multi(p: int, degs: Sequence[Sequence[int]], box, sched=None, seed: int = 0,
+                      nprobes: Optional[int] = None, stream=None):
+    """Several polynomials sampled together (zippel_reconstruct_multi):
+    degs[e] the degree bounds of expression e; the box returns all of them per
+    point.  Returns [(exps, coefs)] per expression."""
+    degs = np.ascontiguousarray(np.asarray(degs, dtype=np.uint32))
+    E, nv = degs.shape
+    h = _ParamsHolder(p, degs.max(axis=0), None, sched, seed, nprobes, 0)
+    outs = (ZrPoly * E)()
+    fn, ctx = _box_args(box)
+    st = lib().zippel_reconstruct_multi(ctypes.byref(h.s), E, degs.ctypes.data, fn, ctx, _stream(stream), outs)
+    if st != ZR_OK:
+        err = getattr(box, "error", None)
+        raise ZippelError(st, f"zippel_reconstruct_multi{' (' + repr(err) + ')' if err else ''}")
+    return [_take(outs[e], nv) for e in range(E)]
+
+
+def reconstruct_rational(p: int, deg: Sequence[int], box, primes: Sequence[int], sched=None, seed: int = 0,
+                         nprobes: Optional[int] = None, stream=None):
+    """Polynomial with rational coefficients (zippel_reconstruct_rational):
+    Zippel modulo p, then the further primes in order until one confirms.
+    Returns (exps [nterms][nvars] uint16, [(num, den)] as Python ints, primes used)."""
+    h = _ParamsHolder(p, deg, None, sched, seed, nprobes, 0)
+    pr = _u64(primes)
+    out = ZrQPoly()
+    fn, ctx = _box_args(box)
+    st = lib().zippel_reconstruct_rational(ctypes.byref(h.s), _ptr(pr) if len(pr) else None, len(pr), fn, ctx,
+                                           _stream(stream), ctypes.byref(out))
+    if st != ZR_OK:
+        err = getattr(box, "error", None)
+        raise ZippelError(st, f"zippel_reconstruct_rational{' (' + repr(err) + ')' if err else ''}")
+    n, nv, nw = out.nterms, len(deg), out.nwords
+    try:
+        if n:
+            e = np.ctypeslib.as_array(out.exps, shape=(n * nv,)).reshape(n, nv).copy()
+            num = np.ctypeslib.as_array(out.num, shape=(n * nw,)).reshape(n, nw)
+            den = np.ctypeslib.as_array(out.den, shape=(n * nw,)).reshape(n, nw)
+            neg = np.ctypeslib.as_array(out.neg, shape=(n,))
+
+            def big(row):
+                return sum(int(w) << (64 * i) for i, w in enumerate(row))
+            fr = [(-big(num[l]) if neg[l] else big(num[l]), big(den[l])) for l in range(n)]
+        else:
+            e, fr = np.zeros((0, nv), np.uint16), []
+        return e, fr, int(out.nprimes)
+    finally:
+        lib().zr_qpoly_free(ctypes.byref(out))
+
+
+def skeleton_solve(p: int, exps, y, vals, stream=None):
+    """Coefficients modulo p of the terms exps [t][nvars] from samples
+    vals[i-1] at x_v = y_v^i, i = 1..t (zr_skeleton_solve).  Returns (a [t], status)."""
+    import torch
+    exps = np.ascontiguousarray(np.asarray(exps, dtype=np.uint16))
+    t, nv = exps.shape
+    y = _u64(y)
+    dev = torch.device("cuda")
+    d_v = torch.from_numpy(np.concatenate([_u64(vals), np.zeros(1, np.uint64)]).view(np.int64)).to(dev)
+    d_o = torch.zeros_like(d_v)
+    d_s = torch.zeros(1, dtype=torch.int32, device=dev)
+    st = lib().zr_skeleton_solve(p, nv, t, exps.ctypes.data, _ptr(y), d_v.data_ptr(), d_o.data_ptr(),
+                                 d_s.data_ptr(), _stream(stream))
+    if st != ZR_OK:
+        raise ZippelError(st, "zr_skeleton_solve")
+    torch.cuda.synchronize()
+    return d_o.cpu().numpy().view(np.uint64)[:t].copy(), int(d_s.cpu().item())
 
 
 class _Dispatch:

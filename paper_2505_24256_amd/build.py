@@ -9,7 +9,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libzippel_hip.so")
-SOURCES = ["kernels.hip", "kernels_ilp.hip", "balanced.hip", "batch.hip", "microbench.hip", "zippel.cpp", "balanced.cpp", "batch.cpp", "serve.cpp", "noalloc.cpp"]
+SOURCES = ["kernels.hip", "kernels_ilp.hip", "balanced.hip", "batch.hip", "microbench.hip", "zippel.cpp", "balanced.cpp", "batch.cpp", "serve.cpp", "noalloc.cpp", "multiprime.hip", "multiprime.cpp", "multi.cpp", "adaptive.cpp"]
 ARCH = os.environ.get("ZR_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # keep hipcc from forming packed fp32 instructions

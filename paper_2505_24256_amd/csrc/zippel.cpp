@@ -400,6 +400,7 @@ void call_bb(zr_blackbox_fn bb, void* ctx, const Params& P, uint32_t k, uint64_t
   pts.anchor = P.anchor.data();
   pts.xk = xk;
   pts.p = P.p;
+  pts.nexpr = 1;
   if (ni == 0 || nj == 0) return;
   if (bb(ctx, &pts, d_vals, s) != 0) throw Error(ZR_EBLACKBOX);
 }
@@ -800,7 +801,7 @@ void zr_recorder_set_replay(zr_recorder* rec, int replay) {
 
 int zr_recorder_blackbox(void* ctx, const zr_points* pts, uint64_t* d_vals, hipStream_t stream) {
   zr_recorder* rec = (zr_recorder*)ctx;
-  const size_t n = (size_t)pts->ni * pts->nj;
+  const size_t n = (size_t)pts->ni * pts->nj * std::max<uint32_t>(pts->nexpr, 1);
   if (rec->replay) {
     if (rec->idx >= rec->recs.size()) return 2;
     const auto& r = rec->recs[rec->idx++];

@@ -648,7 +648,7 @@ class _ZrPoints(ctypes.Structure):
     _fields_ = [("nvars", ctypes.c_uint32), ("k", ctypes.c_uint32), ("i_first", ctypes.c_uint64),
                 ("ni", ctypes.c_uint64), ("nj", ctypes.c_uint64), ("y", ctypes.POINTER(ctypes.c_uint64)),
                 ("anchor", ctypes.POINTER(ctypes.c_uint64)), ("xk", ctypes.POINTER(ctypes.c_uint64)),
-                ("p", ctypes.c_uint64)]
+                ("p", ctypes.c_uint64), ("nexpr", ctypes.c_uint32)]
 
 
 _BB_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(_ZrPoints), ctypes.c_void_p,
