@@ -405,6 +405,163 @@ def config2_leg(zr, synth, args, stream):
             "mulmods_per_reconstruction": cnt["mulmods"], "steps": steps, "bit_exact": exact}
 
 
+def _replayed(zr, rec, run, steps):
+    """Median wall time of `steps` replays of a recorded call sequence."""
+    import torch
+    times = []
+    out = None
+    for _ in range(max(1, steps)):
+        zr.lib().zr_recorder_rewind(rec.handle)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        out = run()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
+    return statistics.median(times), out
+
+
+def multi_expression_leg(zr, synth, args, stream):
+    """Eight expressions sampled at the same points, each of few nodes per
+    variable: n = 6, about 10^4 terms each, each keeping a random 99% of a
+    common term set plus 0.5% terms of its own; degree bounds 8 in x_1..x_5
+    and 8, 8, 7, 7, 6, 6, 5, 5 in x_6 (terms beyond an expression's bound left
+    out).  One reconstruction of all eight over the union skeleton (one solve
+    per stage with about 64 right-hand sides) against eight separate
+    reconstructions (8 or fewer right-hand sides each), samples recorded once
+    and replayed."""
+    n, t = 6, args.multi_terms
+    last = [8, 8, 7, 7, 6, 6, 5, 5]
+    p = synth.make_prime()
+    base = synth.random_poly(p, n, 8, t, 4001)
+    g = synth.SplitMix64(4002)
+    polys = []
+    for e, d in enumerate(last):
+        bound = [8] * (n - 1) + [d]
+        ok = np.flatnonzero(base.exps[:, n - 1] <= d)
+        u = g.uniform_block(0, 1000, len(ok))
+        own = synth.random_poly(p, n, bound, max(1, t // 200), 4010 + e)
+        ex = np.concatenate([base.exps[ok[u < 990]], own.exps])
+        _, first = np.unique(ex, axis=0, return_index=True)
+        ex = ex[np.sort(first)]
+        polys.append(synth.SparsePoly(p, n, ex, g.uniform_block(1, p, len(ex))).sorted())
+    sched = synth.make_schedule(p, n, [8] * n, 4003, 2)
+    dg = [[8] * (n - 1) + [d] for d in last]
+    rec = zr.Recorder(synth.MultiDeviceBlackBox(polys, nthreads=args.cpu_threads))
+    res = zr.reconstruct_multi(p, dg, rec, sched=sched, stream=stream)
+    exact = all(np.array_equal(r[0], h.exps) and np.array_equal(r[1], h.coefs) for r, h in zip(res, polys))
+    rec.replay(True)
+    zr.timing(True, dots_only=True)
+    zr.timing_reset()
+    tm, res = _replayed(zr, rec, lambda: zr.reconstruct_multi(p, dg, rec, sched=sched, stream=stream),
+                        args.multi_steps)
+    zr.timing(False)
+    n_dots, ms_dots = zr.timing_get("vs_dots")
+    cm = zr.last_counters()
+    exact = exact and all(np.array_equal(r[0], h.exps) and np.array_equal(r[1], h.coefs) for r, h in zip(res, polys))
+    steps = max(1, args.multi_steps)
+    alu_m = cm["solve_mulmods"] * steps * MUL32_PER_MULMOD / (ms_dots / 1e3) / 1e12 if ms_dots else 0.0
+    # the same expressions one at a time
+    sep_s, sep_mul, sep_solve, sep_ms = 0.0, 0, 0, 0.0
+    for h, d in zip(polys, dg):
+        r1 = zr.Recorder(synth.DeviceBlackBox(h, nthreads=args.cpu_threads))
+        e1, c1 = zr.reconstruct(p, d, r1, sched=sched, stream=stream)
+        exact = exact and bool(np.array_equal(e1, h.exps) and np.array_equal(c1, h.coefs))
+        r1.replay(True)
+        zr.timing(True, dots_only=True)
+        zr.timing_reset()
+        t1, _ = _replayed(zr, r1, lambda: zr.reconstruct(p, d, r1, sched=sched, stream=stream), args.multi_steps)
+        zr.timing(False)
+        sep_ms += zr.timing_get("vs_dots")[1] / steps
+        c = zr.last_counters()
+        sep_s += t1
+        sep_mul += c["mulmods"]
+        sep_solve += c["solve_mulmods"]
+        r1.close()
+    alu_s = sep_solve * MUL32_PER_MULMOD / (sep_ms / 1e3) / 1e12 if sep_ms else 0.0
+    rec.close()
+    return {"workload": "8 expressions sampled together, n=6, degree bounds 8 in x_1..x_5 and 8/8/7/7/6/6/5/5 in x_6, "
+                        f"each 99% of a common {t}-term set within its bounds plus 0.5% own terms",
+            "terms": [int(h.nterms) for h in polys],
+            "together": {"seconds": round(tm, 4), "mulmods": cm["mulmods"], "max_system": cm["max_t"],
+                         "solve_kernel_TOPs": round(alu_m, 3), "frac_of_derived_peak": round(alu_m / MUL32_PEAK_TOPS, 4)},
+            "separately": {"seconds": round(sep_s, 4), "mulmods": sep_mul, "solve_kernel_TOPs": round(alu_s, 3),
+                           "frac_of_derived_peak": round(alu_s / MUL32_PEAK_TOPS, 4)},
+            "speedup": round(sep_s / tm, 3) if tm else None, "bit_exact": bool(exact)}
+
+
+def multiprime_leg(zr, synth, args, stream):
+    """Polynomial with rational coefficients (n = 6, per-variable degree 30,
+    10^4 terms, numerators and denominators of 100 bits): Zippel modulo the
+    first prime, then one single-right-hand-side solve per further prime until
+    a prime confirms the reconstructed fractions."""
+    n, D, t = 6, 30, args.multi_terms
+    q = synth.random_qpoly(n, D, t, 100, 4101)
+    primes = synth.prime_list(8, seed=4100)
+    sched = synth.make_schedule(primes[0], n, [D] * n, 4102, 2)
+    rec = zr.Recorder(synth.PrimeDeviceBlackBox(q, nthreads=args.cpu_threads))
+    e, fr, used = zr.reconstruct_rational(primes[0], [D] * n, rec, primes[1:], sched=sched, seed=4102,
+                                          stream=stream)
+    exact = bool(np.array_equal(e, q.exps) and fr == list(zip(q.num, q.den)))
+    rec.replay(True)
+
+    def run():
+        return zr.reconstruct_rational(primes[0], [D] * n, rec, primes[1:], sched=sched, seed=4102, stream=stream,
+                                       raw=True)
+    tm, out = _replayed(zr, rec, run, args.multi_steps)
+    e, fr, used = zr.rational_from_words(out)
+    # one more run with every named launch timed: where the time goes
+    zr.timing(True)
+    zr.timing_reset()
+    _replayed(zr, rec, run, 1)
+    zr.timing(False)
+    per = {k: round(zr.timing_get(k)[1], 3) for k in ("mp_corr", "mp_eval", "mp_crt_rr", "vs_dots", "master")}
+    exact = exact and bool(np.array_equal(e, q.exps) and fr == list(zip(q.num, q.den)))
+    # the first prime alone
+    r0 = zr.Recorder(synth.DeviceBlackBox(q.mod(primes[0]), nthreads=args.cpu_threads))
+    zr.reconstruct(primes[0], [D] * n, r0, sched=sched, stream=stream)
+    r0.replay(True)
+    t0, _ = _replayed(zr, r0, lambda: zr.reconstruct(primes[0], [D] * n, r0, sched=sched, stream=stream),
+                      args.multi_steps)
+    r0.close()
+    rec.close()
+    W1 = t * t + 2 * t * (t - 1) + t * (t - 1) // 2 + 4 * t  # one further prime's solve
+    further = used - 1
+    return {"workload": f"polynomial with rational coefficients, n={n}, per-variable degree<={D}, {t} terms, "
+                        "100-bit numerators and denominators",
+            "primes_used": used, "seconds": round(tm, 4), "first_prime_seconds": round(t0, 4),
+            "further_primes_seconds": round(tm - t0, 4),
+            "further_prime_solve_mulmod_per_s": round(further * W1 / max(tm - t0, 1e-9), 1),
+            "per_kernel_ms": per, "bit_exact": exact}
+
+
+def adaptive_leg(zr, synth, args, stream):
+    """The n = 6, t = 10^4 polynomial without its degree bounds: caps of 40
+    per variable (true bound 30), one confirming order, against the
+    fixed-bound reconstruction with the degrees found, same schedule."""
+    w = synth.config_workload(2)
+    caps = [40] * 6
+    sched = synth.make_schedule(w.p, 6, [41] * 6, 1002, 2)
+    rec = zr.Recorder(synth.DeviceBlackBox(w.hidden, nthreads=args.cpu_threads))
+    e, c, found = zr.reconstruct_adaptive(w.p, caps, rec, sched=sched, stream=stream)
+    exact = bool(np.array_equal(e, w.hidden.exps) and np.array_equal(c, w.hidden.coefs))
+    rec.replay(True)
+    ta, (e, c, found) = _replayed(zr, rec, lambda: zr.reconstruct_adaptive(w.p, caps, rec, sched=sched,
+                                                                             stream=stream), args.multi_steps)
+    ca = zr.last_counters()
+    exact = exact and bool(np.array_equal(e, w.hidden.exps) and np.array_equal(c, w.hidden.coefs))
+    rf = zr.Recorder(synth.DeviceBlackBox(w.hidden, nthreads=args.cpu_threads))
+    zr.reconstruct(w.p, found, rf, sched=sched, stream=stream)
+    rf.replay(True)
+    tf, _ = _replayed(zr, rf, lambda: zr.reconstruct(w.p, found, rf, sched=sched, stream=stream), args.multi_steps)
+    cf = zr.last_counters()
+    rec.close()
+    rf.close()
+    return {"workload": "n=6, t=10^4 polynomial (true per-variable degree 30) with caps of 40, one confirming order",
+            "degrees_found": found, "seconds": round(ta, 4), "fixed_bound_seconds": round(tf, 4),
+            "ratio": round(ta / tf, 3) if tf else None, "mulmods": ca["mulmods"], "fixed_bound_mulmods": cf["mulmods"],
+            "bit_exact": exact}
+
+
 def cpu_baseline(zr, synth, args, stream, W_step):
     """The oracle's transposed Vandermonde solve (master polynomial, synthetic
     division and dot products, inverse and scaling; unsigned __int128 products
@@ -449,6 +606,10 @@ def main():
     ap.add_argument("--batch-instances", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--no-serve", action="store_true", help="skip the served-form measurement")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the multi-expression, multi-prime and unknown-degree legs")
+    ap.add_argument("--multi-terms", type=int, default=10_000)
+    ap.add_argument("--multi-steps", type=int, default=2)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-slots", type=int, default=256)
     ap.add_argument("--serve-budget-gib", type=int, default=16)
@@ -489,7 +650,7 @@ def main():
                else None)
     # measured ceiling of the 32x32->64-bit multiply: the v_mad_u64_u32 probe
     # (independent streams at full occupancy), run here on the same GPU
-    mad_ms, mad_ops = zr.microbench("mad_u64_u32", blocks=2048, iters=4096)
+    mad_ms, mad_ops = zr.microbench("mad_u64_u32", blocks=2048, iters=131072)
     mad_peak = mad_ops / mad_ms / 1e9 if mad_ms > 0 else None
     roofline = {"bound": "alu", "achieved": round(alu, 3), "peak": round(MUL32_PEAK_TOPS, 3),
                 "unit": "TOP/s (32x32-bit multiplies; one 64x64-bit modular product or multiply-accumulate = 4)",
@@ -501,7 +662,8 @@ def main():
                 "work_per_launch": "4 (R t^2 + 2 t (t-1)) 32x32-bit multiplies, t = %d, R = %d" % (t_sys, R),
                 "measured_mul32_peak": {
                     "value": round(mad_peak, 3) if mad_peak else None, "unit": "TOP/s",
-                    "probe": "v_mad_u64_u32, 8 independent chains per lane, 2048 x 256 threads, this GPU, this run",
+                    "probe": "v_mad_u64_u32, 8 independent chains per lane, 2048 x 256 threads, 131072 iterations "
+                             "(about 17 ms, so that the clock settles as in the solve), this GPU, this run",
                     "frac": round(alu / mad_peak, 4) if mad_peak else None}}
     _progress("headline measured")
 
@@ -509,6 +671,14 @@ def main():
     _progress("cpu baseline done")
     c2 = None if args.no_config2 else config2_leg(zr, synth, args, stream)
     _progress("n=6 leg done")
+    multi = mprime = adapt = None
+    if not args.no_extras:
+        multi = multi_expression_leg(zr, synth, args, stream)
+        _progress("multi-expression leg done")
+        mprime = multiprime_leg(zr, synth, args, stream)
+        _progress("multi-prime leg done")
+        adapt = adaptive_leg(zr, synth, args, stream)
+        _progress("unknown-degree leg done")
     batch = None if args.no_batch else batched_vs_plain(zr, synth, args, stream)
     serve = None if args.no_serve else served(zr, synth, args, stream)
 
@@ -542,6 +712,9 @@ def main():
         "cpu_baseline": cpu,
         "kernels_warmup": {"steps": args.warmup, "per_kernel": H["kernels"]},
         "config2": c2,
+        "multi_expression": multi,
+        "multiprime": mprime,
+        "unknown_degrees": adapt,
         "batch": batch,
         "serve": serve,
     }

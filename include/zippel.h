@@ -170,11 +170,13 @@ zr_status zippel_balanced_reconstruct(const zr_params* params, zr_blackbox_fn bb
 
 /* Polynomial Zippel without known degree bounds (Introduction: a result is
  * accepted when further probes reproduce it).  Stage k samples x_k at its
- * anchor and then at the schedule's nodes, eight at a time; after each node m
- * it forms, for every term, the divided difference of order m of the term's
- * values at x_0..x_m, and stops at the first m whose last `confirm` orders
- * vanish for all terms.  The stage's degree is D = m - confirm; the terms are
- * lifted over x_0..x_D as in zippel_reconstruct.
+ * anchor and then at the schedule's nodes in batches of 16 (the batches
+ * change how many samples are drawn, not the result); after
+ * each node m it forms, for every term, the divided difference of order m of
+ * the term's values at x_0..x_m, and stops at the first m whose last
+ * `confirm` orders vanish for all terms.  The stage's degree is
+ * D = m - confirm; the terms are lifted over x_0..x_D as in
+ * zippel_reconstruct.
  *   params     as for zippel_reconstruct, with deg[v] read as a cap: at most
  *              deg[v] + confirm nodes of x_v are sampled, and an explicit
  *              schedule must hold that many; last_stage 0 or nvars,

@@ -408,11 +408,22 @@ def reconstruct_multi(p: int, degs: Sequence[Sequence[int]], box, sched=None, se
     return [_take(outs[e], nv) for e in range(E)]
 
 
+def rational_from_words(raw):
+    """(exps, num words [t][nw], den words [t][nw], neg [t], primes) -> (exps, [(num, den)], primes)."""
+    e, num, den, neg, used = raw
+
+    def big(row):
+        return sum(int(w) << (64 * i) for i, w in enumerate(row))
+    return e, [(-big(num[l]) if neg[l] else big(num[l]), big(den[l])) for l in range(len(neg))], used
+
+
 def reconstruct_rational(p: int, deg: Sequence[int], box, primes: Sequence[int], sched=None, seed: int = 0,
-                         nprobes: Optional[int] = None, stream=None):
+                         nprobes: Optional[int] = None, stream=None, raw: bool = False):
     """Polynomial with rational coefficients (zippel_reconstruct_rational):
     Zippel modulo p, then the further primes in order until one confirms.
-    Returns (exps [nterms][nvars] uint16, [(num, den)] as Python ints, primes used)."""
+    Returns (exps [nterms][nvars] uint16, [(num, den)] as Python ints, primes
+    used); with raw=True the magnitudes as uint64 word arrays [nterms][nwords]
+    and the signs instead (rational_from_words converts)."""
     h = _ParamsHolder(p, deg, None, sched, seed, nprobes, 0)
     pr = _u64(primes)
     out = ZrQPoly()
@@ -426,16 +437,15 @@ def reconstruct_rational(p: int, deg: Sequence[int], box, primes: Sequence[int],
     try:
         if n:
             e = np.ctypeslib.as_array(out.exps, shape=(n * nv,)).reshape(n, nv).copy()
-            num = np.ctypeslib.as_array(out.num, shape=(n * nw,)).reshape(n, nw)
-            den = np.ctypeslib.as_array(out.den, shape=(n * nw,)).reshape(n, nw)
-            neg = np.ctypeslib.as_array(out.neg, shape=(n,))
-
-            def big(row):
-                return sum(int(w) << (64 * i) for i, w in enumerate(row))
-            fr = [(-big(num[l]) if neg[l] else big(num[l]), big(den[l])) for l in range(n)]
+            num = np.ctypeslib.as_array(out.num, shape=(n * nw,)).reshape(n, nw).copy()
+            den = np.ctypeslib.as_array(out.den, shape=(n * nw,)).reshape(n, nw).copy()
+            neg = np.ctypeslib.as_array(out.neg, shape=(n,)).copy()
         else:
-            e, fr = np.zeros((0, nv), np.uint16), []
-        return e, fr, int(out.nprimes)
+            e = np.zeros((0, nv), np.uint16)
+            num = den = np.zeros((0, max(nw, 1)), np.uint64)
+            neg = np.zeros(0, np.uint8)
+        words = (e, num, den, neg, int(out.nprimes))
+        return words if raw else rational_from_words(words)
     finally:
         lib().zr_qpoly_free(ctypes.byref(out))
 

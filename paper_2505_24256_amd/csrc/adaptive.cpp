@@ -1,6 +1,7 @@
 // Zippel reconstruction without known degree bounds (Introduction: a result
 // is accepted when further probes reproduce it).  Each stage samples x_k at
-// its anchor and then at further nodes, a batch at a time; after each batch
+// its anchor and then at further nodes, a batch at a time (one master
+// polynomial per stage, one solve per batch); after each batch
 // every term's divided differences of the new orders,
 //   b_m = sum_{i<=m} f_i / prod_{j<=m, j!=i} (x_i - x_j),
 // are formed on the device and counted where nonzero.  The stage stops at the
@@ -48,7 +49,11 @@ __global__ void __launch_bounds__(256) k_ddiff_count(zr_mod M, uint32_t t, uint3
 
 namespace {
 
-constexpr uint32_t kBatch = 8;  // nodes sampled per black-box call and solve
+// Nodes per black-box call and solve: 16 at a time.  Each solve reruns the
+// synthetic-division chain (about eight right-hand sides' worth of work), so
+// fewer, wider solves cost less; batches of 16 keep the samples drawn beyond
+// a stage's stop below 16 and take the producer/consumer pass.
+constexpr uint32_t kBatchFirst = 16, kBatchMax = 16;
 
 // w[m][i] = 1 / prod_{j<=m, j!=i} (x_i - x_j) for m < X.size(), i <= m.
 std::vector<uint64_t> ddiff_weights(const zr_mod& M, const std::vector<uint64_t>& X) {
@@ -135,17 +140,34 @@ void reconstruct_adaptive(const zr_params* params, uint32_t confirm, zr_blackbox
       check(fill_i32((int32_t*)d_nz, 0, maxm + 1, s));
       if (k == 1) call_bb(bb, ctx, P, 1, 1, P.y.data(), X.data(), 1, vals, s);
       else check(copy_u64(vals, cur.coef, t, s));
-      uint32_t m = 0, run = 0, stop = 0;
+      // one master polynomial for all of the stage's solves
+      uint64_t* Mc = nullptr;
+      if (k >= 2 && t) {
+        Mc = A.alloc<uint64_t>(t);
+        uint64_t* tmp = A.alloc<uint64_t>(master_tmp_words(t));
+        check(master_poly(P.M, t, cur.mono, Mc, tmp, s));
+        C.mulmods += (uint64_t)t * (t - 1) / 2;
+      }
+      uint32_t m = 0, run = 0, stop = 0, batch = kBatchFirst;
       std::vector<uint32_t> nz(maxm + 1);
       while (!stop) {
         if (m == maxm) {
           note_error("stage %u: no %u vanishing orders within %u nodes", k, confirm, maxm);
           throw Error(ZR_EPROBE);
         }
-        const uint32_t B = std::min(kBatch, maxm - m);
+        const uint32_t B = std::min(batch, maxm - m);
+        batch = std::min(2 * batch, kBatchMax);
         uint64_t* rows = vals + (size_t)(m + 1) * t;
         call_bb(bb, ctx, P, k, k == 1 ? 1 : t, P.y.data(), X.data() + m + 1, B, rows, s);
-        if (k >= 2) solve_stage(P, cur, rows - t, B, s, d_status);  // rows m+1..m+B in place
+        if (k >= 2 && t) {
+          // rows m+1..m+B in place
+          DevArena W(s);
+          const VsolvePlan plan = vsolve_plan(t, B, device_cus());
+          uint64_t* work = W.alloc<uint64_t>(vsolve_workspace_words(plan));
+          check(vsolve(P.M, plan, cur.mono, Mc, rows, t, rows, t, work, d_status, s));
+          count_solve(t, B);
+          C.mulmods -= (uint64_t)t * (t - 1) / 2;  // the master polynomial is counted once per stage
+        }
         if (t)
           hipLaunchKernelGGL(k_ddiff_count, dim3(cdiv(t, 256)), dim3(256), 0, s, P.M, t, m + 1, m + 1 + B,
                              (uint32_t)X.size(), d_w, vals, d_nz);

@@ -68,14 +68,24 @@ VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
     const uint32_t slots = std::max<uint32_t>(1, num_cus) * dots_pc_blocks_per_cu(P.RT, P.ntile);
     const uint32_t S0 = std::max<uint32_t>(1, cdiv(4ull * slots, (uint64_t)row_blocks));
     // equal chunks make equal workgroups, which run in rounds of `slots`:
-    // among the chunk counts around S0 take the one whose last round is fullest
-    S = S0;
-    double best = 2.0;
-    for (uint32_t s = std::max<uint32_t>(1, S0 - S0 / 4); s <= S0 + S0 / 4; ++s) {
+    // among the chunk counts around S0 (up to at least 32) take the one whose
+    // rounds waste the least, counting that every chunk but the last also
+    // costs a chain pass of about 1/64 of its dot-product pass.  Chunks of at
+    // most 4096 steps also measured faster by themselves (R = 40: at
+    // t = 10^5, 101 ms per launch from 32 chunks on against 107-119 ms with
+    // 24 to 2; at t = 5*10^5 flat from 24 chunks on, 4% below 16 and 8%
+    // below 3).  The partial sums of all chunks, 8 S R t bytes, stay below
+    // 4 GiB.
+    const uint64_t cap = std::max<uint64_t>(1, ((uint64_t)4 << 30) / (8ull * std::max<uint32_t>(R, 1) * t));
+    const uint32_t s_lo = (uint32_t)std::min<uint64_t>(cap, std::max<uint32_t>(S0 - S0 / 4, cdiv(t, 4096)));
+    S = std::max<uint32_t>(1, s_lo);
+    double best = 1e30;
+    for (uint32_t s = std::max<uint32_t>(1, s_lo); s <= std::max<uint32_t>(32, S0 + S0 / 4); ++s) {
+      if (s > cap && s > 1) break;
       const uint64_t w = (uint64_t)row_blocks * s, rounds = (w + slots - 1) / slots;
-      const double idle = (double)(rounds * slots - w) / (double)w;
-      if (idle < best) {
-        best = idle;
+      const double cost = (double)(rounds * slots) / (double)w * (1.0 + (s - 1.0) / s / 64.0);
+      if (cost < best) {
+        best = cost;
         S = s;
       }
     }

@@ -777,3 +777,72 @@ class DeviceBlackBox:
         return ctypes.cast(self._cb, ctypes.c_void_p)
 
     ctx = None
+
+
+class MultiDeviceBlackBox:
+    """Several hidden polynomials sampled at the same points (zr_points.nexpr
+    of them): expression e's values go to d_vals[e * nj * ni ...]."""
+
+    def __init__(self, polys: Sequence[SparsePoly], nthreads: int = 0):
+        self.boxes = [DeviceBlackBox(h, nthreads=nthreads) for h in polys]
+        self.calls = 0
+        self.error = None
+        self._cb = _BB_FN(self._call)
+
+    def _call(self, ctx, pts_ptr, d_vals, stream):
+        try:
+            pts = pts_ptr.contents
+            if pts.nexpr != len(self.boxes):
+                return 31
+            n = pts.ni * pts.nj
+            for e, b in enumerate(self.boxes):
+                st = b._call(ctx, pts_ptr, (d_vals or 0) + 8 * n * e, stream)
+                if st:
+                    self.error = b.error
+                    return st
+            self.calls += 1
+            return 0
+        except BaseException as e:  # noqa: BLE001 - reported through the status code
+            self.error = e
+            return 32
+
+    @property
+    def fn_ptr(self):
+        return ctypes.cast(self._cb, ctypes.c_void_p)
+
+    ctx = None
+
+
+class PrimeDeviceBlackBox:
+    """A polynomial with rational coefficients, evaluated modulo whichever
+    prime a call names (zr_points.p): one DeviceBlackBox per prime."""
+
+    def __init__(self, q: QPoly, nthreads: int = 0):
+        self.q = q
+        self.nthreads = nthreads
+        self.boxes = {}
+        self.calls = 0
+        self.error = None
+        self._cb = _BB_FN(self._call)
+
+    def _call(self, ctx, pts_ptr, d_vals, stream):
+        try:
+            p = int(pts_ptr.contents.p)
+            b = self.boxes.get(p)
+            if b is None:
+                b = self.boxes[p] = DeviceBlackBox(self.q.mod(p), nthreads=self.nthreads)
+            st = b._call(ctx, pts_ptr, d_vals, stream)
+            if st:
+                self.error = b.error
+                return st
+            self.calls += 1
+            return 0
+        except BaseException as e:  # noqa: BLE001 - reported through the status code
+            self.error = e
+            return 33
+
+    @property
+    def fn_ptr(self):
+        return ctypes.cast(self._cb, ctypes.c_void_p)
+
+    ctx = None
