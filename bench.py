@@ -659,7 +659,8 @@ def main():
                 "kernel": "k_vs_dots_pc" if args.solve_variant == "producer_consumer" else "k_vs_dots",
                 "launches_per_step": n_dots // steps if steps else 0,
                 "avg_launch_ms": round(ms_dots / n_dots, 3) if n_dots else None,
-                "work_per_launch": "4 (R t^2 + 2 t (t-1)) 32x32-bit multiplies, t = %d, R = %d" % (t_sys, R),
+                "work_per_step": "4 (R t^2 + 2 t (t-1)) 32x32-bit multiplies, t = %d, R = %d, over the step's "
+                                 "launches (chunk groups of equal size)" % (t_sys, R),
                 "measured_mul32_peak": {
                     "value": round(mad_peak, 3) if mad_peak else None, "unit": "TOP/s",
                     "probe": "v_mad_u64_u32, 8 independent chains per lane, 2048 x 256 threads, 131072 iterations "

@@ -704,7 +704,7 @@ static BPlan bplan(uint32_t t, uint32_t R, double cap, const Tuning& T) {
   P.pc = !P.packed && R > kPcMinR && pc_tiles_for(R) && vsolve_uses_pc() ? 1 : 0;
   P.ntile = P.pc ? pc_tiles_for(R) : cdiv(R, kMaxRT);
   P.RT = cdiv(R, P.ntile);
-  P.ldv = (3 * P.RT + 2 + 15) & ~15u;
+  P.ldv = P.pc ? pc_ldv(P.RT) : (3 * P.RT + 2 + 15) & ~15u;  // as in the one-system solve
   uint32_t S = 1;
   if (!P.packed) {
     const double item = 64.0 * t * P.RT;  // one wave's work for an unsplit row block

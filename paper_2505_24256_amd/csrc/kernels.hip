@@ -45,6 +45,17 @@ bool vsolve_uses_pc() { return dots_pc_enabled(); }
 // waves per SIMD (20 would drop to one).
 constexpr uint32_t kPlanRT = 16;
 
+// Packed rows of one chunk of the producer/consumer pass, at most (bytes):
+// under half of an XCD's 4 MiB L2.
+constexpr uint64_t kChunkRowBytes = 7ull << 18;
+// Partial dot-product sums of one solve (Sd R t words), at most (bytes): more
+// chunks than fit take the slots in turn over several launches.
+constexpr uint64_t kSpartBytes = 4ull << 30;
+// Per-chunk state of one solve (chain values, start values and Horner
+// partials, 3 S t words), at most (bytes); beyond it chunks grow longer, which
+// changes only the speed.
+constexpr uint64_t kChunkStateBytes = 4ull << 30;
+
 VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
   VsolvePlan P;
   P.t = t;
@@ -62,28 +73,42 @@ VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
     P.ntile = R == 0 ? 1 : cdiv(R, kPlanRT);
     P.RT = R == 0 ? 1 : cdiv(R, P.ntile);
   }
-  P.ldv = (3 * P.RT + 2 + 15) & ~15u;  // 32-bit words per packed row: 3 limbs per value + M_r, 64-byte groups
+  // 32-bit words per packed row: the producer/consumer pass reads only the
+  // limbs (pc_ldv); the one-wave-per-tile pass also reads M_r, in 64-byte groups
+  P.ldv = P.pc ? pc_ldv(P.RT) : (3 * P.RT + 2 + 15) & ~15u;
   uint32_t S;
   if (P.pc) {
     const uint32_t slots = std::max<uint32_t>(1, num_cus) * dots_pc_blocks_per_cu(P.RT, P.ntile);
     const uint32_t S0 = std::max<uint32_t>(1, cdiv(4ull * slots, (uint64_t)row_blocks));
-    // equal chunks make equal workgroups, which run in rounds of `slots`:
-    // among the chunk counts around S0 (up to at least 32) take the one whose
-    // rounds waste the least, counting that every chunk but the last also
-    // costs a chain pass of about 1/64 of its dot-product pass.  Chunks of at
-    // most 4096 steps also measured faster by themselves (R = 40: at
-    // t = 10^5, 101 ms per launch from 32 chunks on against 107-119 ms with
-    // 24 to 2; at t = 5*10^5 flat from 24 chunks on, 4% below 16 and 8%
-    // below 3).  The partial sums of all chunks, 8 S R t bytes, stay below
-    // 4 GiB.
-    const uint64_t cap = std::max<uint64_t>(1, ((uint64_t)4 << 30) / (8ull * std::max<uint32_t>(R, 1) * t));
-    const uint32_t s_lo = (uint32_t)std::min<uint64_t>(cap, std::max<uint32_t>(S0 - S0 / 4, cdiv(t, 4096)));
+    // chunk state (chain values, start values, Horner partials: 3 S t words)
+    // within kChunkStateBytes; partial sums (Sd R t words) within kSpartBytes,
+    // the chunks taking Sd slots in turn, one launch per Sd chunks
+    const uint32_t s_cap = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(4096, kChunkStateBytes / (24ull * t)));
+    const uint32_t sd_max = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(4096, kSpartBytes / (8ull * std::max<uint32_t>(R, 1) * t)));
+    auto slots_for = [&](uint32_t s) { return cdiv(s, cdiv(s, sd_max)); };
+    // The workgroups resident on one XCD work through the same chunk and share
+    // its packed rows in that XCD's L2 while the chunk's rows fit in it with
+    // room to spare, so chunks hold at most kChunkRowBytes of rows.  At R = 40,
+    // t = 5*10^5 the pass took 2.70 s with 26 chunks (19 231 steps, 9.7 MB of
+    // rows), 2.58 s with 64, and 2.43 s from 128 chunks (3 906 steps, 2.0 MB)
+    // up; 32-word rows (3.5 MB a chunk at 128 chunks) took 2.51 s.  From
+    // there, among chunk counts up to a quarter more (at least 32), take the
+    // one whose launches waste the least in their last round of `slots` equal
+    // workgroups, counting that every chunk but the last also costs a chain
+    // pass of about 1/64 of its dot-product pass.
+    const uint64_t row_bytes = 4ull * P.ntile * P.ldv;
+    const uint32_t l2_steps = (uint32_t)std::max<uint64_t>(64, kChunkRowBytes / row_bytes);
+    const uint32_t s_lo = std::min(s_cap, std::max<uint32_t>(S0 - S0 / 4, cdiv(t, l2_steps)));
+    const uint32_t s_hi = std::max<uint32_t>({32u, S0 + S0 / 4, s_lo + s_lo / 4});
     S = std::max<uint32_t>(1, s_lo);
     double best = 1e30;
-    for (uint32_t s = std::max<uint32_t>(1, s_lo); s <= std::max<uint32_t>(32, S0 + S0 / 4); ++s) {
-      if (s > cap && s > 1) break;
-      const uint64_t w = (uint64_t)row_blocks * s, rounds = (w + slots - 1) / slots;
-      const double cost = (double)(rounds * slots) / (double)w * (1.0 + (s - 1.0) / s / 64.0);
+    for (uint32_t s = std::max<uint32_t>(1, s_lo); s <= s_hi && s <= s_cap; ++s) {
+      const uint32_t sd = slots_for(s);
+      uint64_t rounds = 0;
+      for (uint32_t c0 = 0; c0 < s; c0 += sd)
+        rounds += ((uint64_t)row_blocks * std::min(sd, s - c0) + slots - 1) / slots;
+      const double cost =
+          (double)(rounds * slots) / ((double)row_blocks * s) * (1.0 + (s - 1.0) / s / 64.0);
       if (cost < best) {
         best = cost;
         S = s;
@@ -94,10 +119,15 @@ VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
     S = std::max<uint32_t>(1, cdiv(4ull * slots, (uint64_t)row_blocks * P.ntile));
   }
   S = std::min<uint32_t>(S, std::max<uint32_t>(1, t / 128));
-  S = std::min<uint32_t>(S, 256);
+  if (!P.pc) S = std::min<uint32_t>(S, 256);
   P.L = std::max<uint32_t>(1, cdiv(t, S));
   P.S = std::max<uint32_t>(1, cdiv(t, P.L));
   P.Sd = P.S;
+  if (P.pc) {
+    const uint32_t sd_max =
+        (uint32_t)std::max<uint64_t>(1, kSpartBytes / (8ull * std::max<uint32_t>(R, 1) * std::max<uint32_t>(t, 1)));
+    P.Sd = cdiv(P.S, cdiv(P.S, sd_max));
+  }
   return P;
 }
 
@@ -139,9 +169,9 @@ __global__ void __launch_bounds__(64) k_vs_dots(VsArgs a) {
 
 // producer + one consumer wave per tile (64 * (1 + ntile) threads)
 template <int RT>
-__global__ void __launch_bounds__(64 * (1 + kPcMaxTiles)) k_vs_dots_pc(VsArgs a, uint32_t ntile) {
+__global__ void __launch_bounds__(64 * (1 + kPcMaxTiles)) k_vs_dots_pc(VsArgs a, uint32_t ntile, uint32_t c0) {
   __shared__ uint64_t qbuf[2][kQB][64];
-  vs_dots_pc_body<RT>(a, blockIdx.x, blockIdx.y, ntile, qbuf);
+  vs_dots_pc_body<RT>(a, blockIdx.x, c0 + blockIdx.y, ntile, qbuf);
 }
 
 __global__ void __launch_bounds__(kDeltaBlock) k_vs_delta(VsArgs a, const uint64_t* __restrict__ mLv,
@@ -169,7 +199,7 @@ static DotsKernel dots_kernel(uint32_t RT) {
   return RT >= 1 && RT <= kMaxRT ? table[RT] : nullptr;
 }
 
-typedef void (*DotsPcKernel)(VsArgs, uint32_t);
+typedef void (*DotsPcKernel)(VsArgs, uint32_t, uint32_t);
 template <int RT>
 static DotsPcKernel dots_pc_ptr() {
   return k_vs_dots_pc<RT>;
@@ -252,8 +282,12 @@ hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, co
   if (P.pc) {
     DotsPcKernel kp = dots_pc_kernel(P.RT);
     if (!kp) return hipErrorInvalidValue;
-    TimedLaunch tl("vs_dots", s);
-    hipLaunchKernelGGL(kp, dim3(cdiv(t, 64), P.S), dim3(64 * (1 + P.ntile)), 0, s, a, P.ntile);
+    // chunks in launches of Sd (one partial-sum slot each), in order
+    for (uint32_t c0 = 0; c0 < P.S; c0 += P.Sd) {
+      TimedLaunch tl("vs_dots", s);
+      hipLaunchKernelGGL(kp, dim3(cdiv(t, 64), std::min<uint32_t>(P.Sd, P.S - c0)), dim3(64 * (1 + P.ntile)), 0, s,
+                         a, P.ntile, c0);
+    }
   } else {
     DotsKernel kd = dots_kernel(P.RT);
     if (!kd) return hipErrorInvalidValue;

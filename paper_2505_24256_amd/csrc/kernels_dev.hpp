@@ -24,7 +24,7 @@ constexpr uint32_t kMaxRT = 20;
 struct VsArgs {
   zr_mod M;
   uint32_t t, L, S, R, ldv;
-  uint32_t Sd;  // partial dot-product sums per row and right-hand side in spart
+  uint32_t Sd;  // partial-sum slots per row and right-hand side in spart (chunk c adds into c mod Sd)
   const uint64_t* mono;
   const uint64_t* mono_p;
   const uint64_t* Mc;
@@ -321,8 +321,53 @@ __device__ __forceinline__ void vs_chain_body(const VsArgs& a, uint32_t l, uint3
   a.Bc[(size_t)c * a.t + l] = y;
 }
 
-// 64-byte group of a packed row as one vector (one scalar load)
-typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
+// Packed row of the producer/consumer pass: the 3 RT limbs of the tile's
+// values at one step, without M_r (the producer reads M_r itself).  It is
+// loaded through the scalar cache as one 16-word group and a tail of K words,
+// K a power of two up to 16 (none for RT <= 5), so a row of six values is 18
+// words (72 bytes) rather than two 64-byte groups: a chunk's rows take less
+// of the L2 that the workgroups on one XCD share.  Rows start at any 4-byte
+// boundary, which scalar loads accept.
+__host__ __device__ constexpr uint32_t pc_tail(uint32_t RT) {
+  return 3 * RT <= 16 ? 0 : 3 * RT - 16 <= 2 ? 2 : 3 * RT - 16 <= 4 ? 4 : 3 * RT - 16 <= 8 ? 8 : 16;
+}
+__host__ __device__ constexpr uint32_t pc_ldv(uint32_t RT) { return 16 + pc_tail(RT); }
+
+typedef uint32_t u32x16a4 __attribute__((ext_vector_type(16))) __attribute__((aligned(4)));
+template <int K>
+struct PcTail {
+  typedef uint32_t type __attribute__((ext_vector_type(K))) __attribute__((aligned(4)));
+};
+template <int K>
+struct PcRow {
+  u32x16a4 a;
+  typename PcTail<K>::type b;
+};
+template <>
+struct PcRow<0> {
+  u32x16a4 a;
+};
+template <int K>
+__device__ __forceinline__ uint32_t pc_word(const PcRow<K>& row, int w) {
+  if constexpr (K == 0)
+    return row.a[w];
+  else
+    return w < 16 ? row.a[w] : row.b[w - 16];
+}
+template <int K>
+__device__ __forceinline__ void pc_load(PcRow<K>& row, const_as<uint32_t> base) {
+  row.a = *(const_as<u32x16a4>)base;
+  if constexpr (K != 0) row.b = *(const_as<typename PcTail<K>::type>)(base + 16);
+}
+// Every word of the row stays live up to the end of its step, unused words
+// included: a value of the step (such as the dead carry-out of a multiply) is
+// then never given a register that a still pending row load writes, which
+// would force a wait for that load.
+template <int K>
+__device__ __forceinline__ void pc_keep(const PcRow<K>& row) {
+  asm volatile("" ::"s"(row.a));
+  if constexpr (K != 0) asm volatile("" ::"s"(row.b));
+}
 
 // One consumer step: q (already in registers) times row r held in cur.  Row
 // rn and the next step's q are requested into nxt and qn right after the
@@ -330,28 +375,21 @@ typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
 // first use of cur and q then covers only requests a whole step old, and the
 // sched barriers keep the scheduler from moving the requests down to their
 // own uses.
-template <int RT, int G>
-__device__ __forceinline__ void vs_pc_step(const zr_mod& M, Acc6 (&acc)[RT], const u32x16 (&cur)[G],
-                                           u32x16 (&nxt)[G], uint64_t& q, const uint64_t* qnext,
-                                           const_as<u32x16> rows, uint32_t rn, uint32_t& since) {
+template <int RT, int K>
+__device__ __forceinline__ void vs_pc_step(const zr_mod& M, Acc6 (&acc)[RT], const PcRow<K>& cur,
+                                           PcRow<K>& nxt, uint64_t& q, const uint64_t* qnext,
+                                           const_as<uint32_t> rows, uint32_t rn, uint32_t& since) {
+  constexpr uint32_t LDV = pc_ldv(RT);
   const uint32_t q0 = (uint32_t)q, q1 = (uint32_t)(q >> 32);
-  acc6_mac(acc[0], q0, q1, cur[0][0], cur[0][1], cur[0][2]);
+  acc6_mac(acc[0], q0, q1, pc_word(cur, 0), pc_word(cur, 1), pc_word(cur, 2));
   __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-  for (int g = 0; g < G; ++g) nxt[g] = rows[(size_t)rn * G + g];
+  pc_load(nxt, rows + (size_t)rn * LDV);
   const uint64_t qn = *qnext;
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int jj = 1; jj < RT; ++jj) {
-    const int w0 = 3 * jj, w1 = 3 * jj + 1, w2 = 3 * jj + 2;
-    acc6_mac(acc[jj], q0, q1, cur[w0 / 16][w0 % 16], cur[w1 / 16][w1 % 16], cur[w2 / 16][w2 % 16]);
-  }
-  // Every word of the row stays live up to here, unused words included: a
-  // value of this step (such as the dead carry-out of a multiply) is then never
-  // given a register that a still pending row load writes, which would force
-  // a wait for that load.
-#pragma unroll
-  for (int g = 0; g < G; ++g) asm volatile("" ::"s"(cur[g]));
+  for (int jj = 1; jj < RT; ++jj)
+    acc6_mac(acc[jj], q0, q1, pc_word(cur, 3 * jj), pc_word(cur, 3 * jj + 1), pc_word(cur, 3 * jj + 2));
+  pc_keep(cur);
   if (++since == kFold) {
 #pragma unroll
     for (int j = 0; j < RT; ++j) acc6_fold(acc[j], M);
@@ -363,8 +401,8 @@ __device__ __forceinline__ void vs_pc_step(const zr_mod& M, Acc6 (&acc)[RT], con
 template <int RT>
 __device__ __forceinline__ void vs_dots_pc_body(const VsArgs& a, uint32_t rb, uint32_t c, uint32_t ntile,
                                                 uint64_t (*qbuf)[kQB][64]) {
-  constexpr int LDV = (3 * RT + 2 + 15) & ~15;
-  constexpr int G = LDV / 16;
+  constexpr uint32_t LDV = pc_ldv(RT);
+  constexpr int K = (int)pc_tail(RT);
   // the wave index is uniform within a wave: say so, so that each role's code
   // is compiled as uniform control flow (scalar loads, scalar loop counters)
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -422,7 +460,7 @@ __device__ __forceinline__ void vs_dots_pc_body(const VsArgs& a, uint32_t rb, ui
   Acc6 acc[RT];
 #pragma unroll
   for (int j = 0; j < RT; ++j) acc6_zero(acc[j]);
-  const_as<u32x16> rows = (const_as<u32x16>)((const uint32_t*)a.VT + (size_t)tile * a.t * LDV);
+  const_as<uint32_t> rows = (const_as<uint32_t>)((const uint32_t*)a.VT + (size_t)tile * a.t * LDV);
   // two row buffers: while one feeds the products of step r the other receives
   // row r-1, so each row's scalar loads have a whole step to arrive.  Blocks
   // hold an even number of steps except the last, so steps go in pairs (no
@@ -430,9 +468,8 @@ __device__ __forceinline__ void vs_dots_pc_body(const VsArgs& a, uint32_t rb, ui
   // alone.
   uint32_t r = hi - 1;
   uint32_t since = 0;
-  u32x16 b0[G], b1[G];
-#pragma unroll
-  for (int g = 0; g < G; ++g) b0[g] = rows[(size_t)r * G + g];
+  PcRow<K> b0, b1;
+  pc_load(b0, rows + (size_t)r * LDV);
   for (uint32_t it = 0; it <= nb; ++it) {
     if (it >= 1) {
       const uint32_t b = it - 1;
@@ -442,25 +479,31 @@ __device__ __forceinline__ void vs_dots_pc_body(const VsArgs& a, uint32_t rb, ui
       uint32_t s = 0;
       for (; s + 2 <= s_end; s += 2) {
         // the q of step s_end (past the block) is read from the last slot and not used
-        vs_pc_step<RT, G>(M, acc, b0, b1, q, qb + 64 * (s + 1), rows, r > lo ? r - 1 : r, since);
+        vs_pc_step<RT, K>(M, acc, b0, b1, q, qb + 64 * (s + 1), rows, r > lo ? r - 1 : r, since);
         r = r > lo ? r - 1 : r;
-        vs_pc_step<RT, G>(M, acc, b1, b0, q, qb + 64 * min(s + 2, kQB - 1), rows, r > lo ? r - 1 : r, since);
+        vs_pc_step<RT, K>(M, acc, b1, b0, q, qb + 64 * min(s + 2, kQB - 1), rows, r > lo ? r - 1 : r, since);
         r = r > lo ? r - 1 : r;
       }
       if (s < s_end) {
-        vs_pc_step<RT, G>(M, acc, b0, b1, q, qb, rows, r > lo ? r - 1 : r, since);
+        vs_pc_step<RT, K>(M, acc, b0, b1, q, qb, rows, r > lo ? r - 1 : r, since);
         r = r > lo ? r - 1 : r;
-#pragma unroll
-        for (int g = 0; g < G; ++g) b0[g] = b1[g];
+        b0 = b1;
       }
     }
     __syncthreads();
   }
   if (live) {
-    const uint32_t j0 = tile * RT;
+    // chunk c adds into partial-sum slot c mod Sd: the chunks of one launch
+    // take distinct slots, and chunks c >= Sd (later launches) add to what
+    // the earlier chunk of their slot left there
+    const uint32_t j0 = tile * RT, slot = c % a.Sd;
 #pragma unroll
     for (int j = 0; j < RT; ++j)
-      if (j0 + j < a.R) a.spart[((size_t)c * a.R + j0 + j) * a.t + l] = acc6_reduce(M, acc[j]);
+      if (j0 + j < a.R) {
+        uint64_t* dst = a.spart + ((size_t)slot * a.R + j0 + j) * a.t + l;
+        const uint64_t v = acc6_reduce(M, acc[j]);
+        *dst = c >= a.Sd ? zr_add(M, v, *dst) : v;
+      }
   }
 }
 

@@ -53,24 +53,42 @@ uint64_t* scratch_on_current_device() {
 
 size_t round_words(size_t w) { return (w + 31) & ~(size_t)31; }  // 256-byte boundaries
 
-// The plan of vsolve_plan with fewer chunks if its workspace would exceed
-// max_words; false when even one chunk does not fit.
+// The plan of vsolve_plan, cut down until its workspace fits max_words: for
+// the producer/consumer pass first fewer partial-sum slots (the same chunks in
+// more launches), then fewer chunks; false when even one chunk does not fit.
+// Every cut changes only the speed.
 bool vsolve_plan_within(uint32_t t, uint32_t R, uint32_t num_cus, size_t max_words, VsolvePlan* out) {
-  VsolvePlan P = vsolve_plan(t, R, num_cus);
-  // every chunk adds S t (R + 3) words (chain values, start values, Horner
-  // partials and the R dot-product partials); fewer chunks change only the speed
+  const VsolvePlan Q = vsolve_plan(t, R, num_cus);
+  if (vsolve_workspace_words(Q) <= max_words) {
+    *out = Q;
+    return true;
+  }
+  const size_t per_slot = std::max<size_t>((size_t)R * t, 1);
+  if (Q.pc) {
+    VsolvePlan P = Q;
+    P.Sd = 1;
+    const size_t w1 = vsolve_workspace_words(P);
+    if (w1 <= max_words) {
+      const uint32_t sd = (uint32_t)std::min<size_t>(Q.S, 1 + (max_words - w1) / per_slot);
+      P.Sd = cdiv(P.S, cdiv(P.S, sd));
+      *out = P;
+      return true;
+    }
+  }
+  // one chunk, then as many as fit: each adds 3 t words of chunk state, and
+  // R t of partial sums unless the slots are shared (producer/consumer pass)
+  VsolvePlan P = Q;
   P.S = P.Sd = 1;
   P.L = std::max<uint32_t>(1, t);
-  const size_t base = vsolve_workspace_words(P), per_chunk = (size_t)t * (R + 3);
+  const size_t base = vsolve_workspace_words(P);
   if (base > max_words) return false;
-  VsolvePlan Q = vsolve_plan(t, R, num_cus);
-  if (vsolve_workspace_words(Q) > max_words) {
-    const uint32_t smax = (uint32_t)std::min<size_t>(Q.S, 1 + (max_words - base) / std::max<size_t>(per_chunk, 1));
-    Q.L = std::max<uint32_t>(1, cdiv(t, smax));
-    Q.S = Q.Sd = std::max<uint32_t>(1, cdiv(t, Q.L));
-  }
-  if (vsolve_workspace_words(Q) > max_words) return false;
-  *out = Q;
+  const size_t per_chunk = 3 * (size_t)t + (Q.pc ? 0 : per_slot);
+  const uint32_t smax = (uint32_t)std::min<size_t>(Q.S, 1 + (max_words - base) / std::max<size_t>(per_chunk, 1));
+  P.L = std::max<uint32_t>(1, cdiv(t, smax));
+  P.S = std::max<uint32_t>(1, cdiv(t, P.L));
+  P.Sd = Q.pc ? 1 : P.S;
+  if (vsolve_workspace_words(P) > max_words) return false;
+  *out = P;
   return true;
 }
 

@@ -81,3 +81,31 @@ def test_config3_full(zr, cfg3):
     _note(f"config3 full: {len(c)} terms, max system {cnt['max_t']}, {time.perf_counter() - t0:.1f} s")
     assert cnt["max_t"] > 490_000
     assert np.array_equal(e, w.hidden.exps) and np.array_equal(c, w.hidden.coefs)
+
+
+def test_headline_solve_size_multiply_back(zr):
+    """One system at the size and launch configuration the benchmark times
+    (t = 5*10^5 unknowns, 40 right-hand sides: seven consumer tiles of six,
+    chunks of at most 4096 steps within the partial-sum budget).  The oracle
+    cannot build the master polynomial at this size in test time, so the
+    check is the defining property at sampled equations: every right-hand
+    side j satisfies sum_l a_l m_l^i = v_i at three values of i (the oracle's
+    multiply-back, O(t log i) each); a wrong coefficient passes one such
+    equation with probability 1/p.  A coefficient changed on the host copy is
+    caught, so the check has the power it claims."""
+    p = synth.make_prime()
+    t, R = 500_000, 40
+    g = synth.SplitMix64(321)
+    m = g.uniform_block(1, p, t)
+    assert len(np.unique(m)) == t
+    rhs = g.uniform_block(0, p, t * R).reshape(R, t)
+    _note(f"headline-size solve t={t} R={R}")
+    a, st = zr.vandermonde_solve(p, m, rhs)
+    assert st == 0
+    _note("multiply-back at sampled equations")
+    for j in range(R):
+        for i in (1, 1 + (j * 12347 + 5) % t, t):
+            assert int(oracle.vandermonde_apply(p, m, a[j], i, 1)[0]) == int(rhs[j, i - 1]), (j, i)
+    bad = a[7].copy()
+    bad[123_456] = (int(bad[123_456]) + 1) % p
+    assert int(oracle.vandermonde_apply(p, m, bad, 77, 1)[0]) != int(rhs[7, 76])
