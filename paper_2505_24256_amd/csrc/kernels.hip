@@ -65,11 +65,22 @@ VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
   // producer wave (k_vs_dots_pc) and consumer waves take tiles of at most
   // kPcRT; the unit of the launch is then a workgroup of 1 + ntile waves, a
   // multiple of four (pc_tiles_for).
-  P.pc = (R > kPcMinR && pc_tiles_for(R) && dots_pc_enabled()) ? 1 : 0;
+  // More than kPcMaxR right-hand sides go through the pass in ng groups of
+  // nearly equal size, which share the chain values, start values and
+  // inverses of the solve.
+  P.ng = 1;
+  P.Rg = R;
+  if (R > kPcMaxR && dots_pc_enabled()) {
+    P.ng = cdiv(R, kPcMaxR);
+    P.Rg = cdiv(R, P.ng);
+  }
+  P.pc = (P.Rg > kPcMinR && pc_tiles_for(P.Rg) && dots_pc_enabled()) ? 1 : 0;
   if (P.pc) {
-    P.ntile = pc_tiles_for(R);
-    P.RT = cdiv(R, P.ntile);
+    P.ntile = pc_tiles_for(P.Rg);
+    P.RT = cdiv(P.Rg, P.ntile);
   } else {
+    P.ng = 1;
+    P.Rg = R;
     P.ntile = R == 0 ? 1 : cdiv(R, kPlanRT);
     P.RT = R == 0 ? 1 : cdiv(R, P.ntile);
   }
@@ -84,7 +95,7 @@ VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
     // within kChunkStateBytes; partial sums (Sd R t words) within kSpartBytes,
     // the chunks taking Sd slots in turn, one launch per Sd chunks
     const uint32_t s_cap = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(4096, kChunkStateBytes / (24ull * t)));
-    const uint32_t sd_max = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(4096, kSpartBytes / (8ull * std::max<uint32_t>(R, 1) * t)));
+    const uint32_t sd_max = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(4096, kSpartBytes / (8ull * std::max<uint32_t>(P.Rg, 1) * t)));
     auto slots_for = [&](uint32_t s) { return cdiv(s, cdiv(s, sd_max)); };
     // The workgroups resident on one XCD work through the same chunk and share
     // its packed rows in that XCD's L2 while the chunk's rows fit in it with
@@ -125,7 +136,7 @@ VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
   P.Sd = P.S;
   if (P.pc) {
     const uint32_t sd_max =
-        (uint32_t)std::max<uint64_t>(1, kSpartBytes / (8ull * std::max<uint32_t>(R, 1) * std::max<uint32_t>(t, 1)));
+        (uint32_t)std::max<uint64_t>(1, kSpartBytes / (8ull * std::max<uint32_t>(P.Rg, 1) * std::max<uint32_t>(t, 1)));
     P.Sd = cdiv(P.S, cdiv(P.S, sd_max));
   }
   return P;
@@ -138,7 +149,7 @@ static size_t vsolve_rhs_words(const VsolvePlan& P) { return (size_t)P.ntile * P
 
 size_t vsolve_workspace_words(const VsolvePlan& P) {
   const size_t t = P.t, S = P.S;
-  return vsolve_rhs_words(P) + t + 2 * S * t + t + P.Sd * (size_t)P.R * t + S * t + 2 * t + 64;
+  return vsolve_rhs_words(P) + t + 2 * S * t + t + P.Sd * (size_t)P.Rg * t + S * t + 2 * t + 64;
 }
 
 // Packed right-hand sides [ntile][t][ldv] and Shoup constants of the monomials.
@@ -246,7 +257,7 @@ hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, co
   uint64_t* qstart = Bc + S * t;
   uint64_t* mL = qstart + S * t;
   uint64_t* spart = mL + t;
-  uint64_t* hpart = spart + P.Sd * (size_t)P.R * t;
+  uint64_t* hpart = spart + P.Sd * (size_t)P.Rg * t;
   VsArgs a;
   a.M = M;
   a.t = P.t;
@@ -263,42 +274,52 @@ hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, co
   a.Bc = Bc;
   a.spart = spart;
   a.hpart = hpart;
-  {
-    const size_t total = std::max<size_t>(P.ntile * t * P.ldv, t);  // 32-bit words
-    TimedLaunch tl("vs_pack", s);
-    hipLaunchKernelGGL(k_pack, dim3(cdiv(total, 256)), dim3(256), 0, s, P.t, P.R, P.RT, P.ntile, P.ldv, rhs, ld_rhs,
-                       Mc, (uint32_t*)VT, mono, mono_p, M);
-  }
-  if (S > 1) {
+  uint64_t* winv = hpart + S * t;
+  // right-hand-side groups in turn; the chain values and start values (before
+  // the first group's dot products) and the inverses (after them, from the
+  // Horner partials) are the same for all and made once
+  for (uint32_t g = 0, r0 = 0; g < P.ng; ++g) {
+    const uint32_t Rg = P.R / P.ng + (g < P.R % P.ng ? 1 : 0);
+    a.R = Rg;
     {
-      TimedLaunch tl("vs_chain", s);
-      hipLaunchKernelGGL(k_vs_chain, dim3(cdiv(t, 256), P.S - 1), dim3(256), 0, s, a);
+      const size_t total = std::max<size_t>(P.ntile * t * P.ldv, t);  // 32-bit words
+      TimedLaunch tl("vs_pack", s);
+      hipLaunchKernelGGL(k_pack, dim3(cdiv(total, 256)), dim3(256), 0, s, P.t, Rg, P.RT, P.ntile, P.ldv,
+                         rhs + (size_t)r0 * ld_rhs, ld_rhs, Mc, (uint32_t*)VT, mono, mono_p, M);
     }
-    {
-      TimedLaunch tl("vs_scan", s);
-      hipLaunchKernelGGL(k_vs_scan, dim3(cdiv(t, 256)), dim3(256), 0, s, a, qstart, mL);
+    if (g == 0 && S > 1) {
+      {
+        TimedLaunch tl("vs_chain", s);
+        hipLaunchKernelGGL(k_vs_chain, dim3(cdiv(t, 256), P.S - 1), dim3(256), 0, s, a);
+      }
+      {
+        TimedLaunch tl("vs_scan", s);
+        hipLaunchKernelGGL(k_vs_scan, dim3(cdiv(t, 256)), dim3(256), 0, s, a, qstart, mL);
+      }
     }
-  }
-  if (P.pc) {
-    DotsPcKernel kp = dots_pc_kernel(P.RT);
-    if (!kp) return hipErrorInvalidValue;
-    // chunks in launches of Sd (one partial-sum slot each), in order
-    for (uint32_t c0 = 0; c0 < P.S; c0 += P.Sd) {
+    if (P.pc) {
+      DotsPcKernel kp = dots_pc_kernel(P.RT);
+      if (!kp) return hipErrorInvalidValue;
+      // chunks in launches of Sd (one partial-sum slot each), in order
+      for (uint32_t c0 = 0; c0 < P.S; c0 += P.Sd) {
+        TimedLaunch tl("vs_dots", s);
+        hipLaunchKernelGGL(kp, dim3(cdiv(t, 64), std::min<uint32_t>(P.Sd, P.S - c0)), dim3(64 * (1 + P.ntile)), 0,
+                           s, a, P.ntile, c0);
+      }
+    } else {
+      DotsKernel kd = dots_kernel(P.RT);
+      if (!kd) return hipErrorInvalidValue;
       TimedLaunch tl("vs_dots", s);
-      hipLaunchKernelGGL(kp, dim3(cdiv(t, 64), std::min<uint32_t>(P.Sd, P.S - c0)), dim3(64 * (1 + P.ntile)), 0, s,
-                         a, P.ntile, c0);
+      hipLaunchKernelGGL(kd, dim3(cdiv(t, 64), P.S, P.ntile), dim3(64), 0, s, a);
     }
-  } else {
-    DotsKernel kd = dots_kernel(P.RT);
-    if (!kd) return hipErrorInvalidValue;
-    TimedLaunch tl("vs_dots", s);
-    hipLaunchKernelGGL(kd, dim3(cdiv(t, 64), P.S, P.ntile), dim3(64), 0, s, a);
-  }
-  {
-    TimedLaunch tl("vs_finish", s);
-    uint64_t* winv = hpart + S * t;
-    hipLaunchKernelGGL(k_vs_delta, dim3(cdiv(t, kDeltaBlock)), dim3(kDeltaBlock), 0, s, a, mL, winv, status);
-    hipLaunchKernelGGL(k_vs_scale, dim3(cdiv(t, 256), P.R), dim3(256), 0, s, a, winv, out, ld_out);
+    {
+      TimedLaunch tl("vs_finish", s);
+      if (g == 0)
+        hipLaunchKernelGGL(k_vs_delta, dim3(cdiv(t, kDeltaBlock)), dim3(kDeltaBlock), 0, s, a, mL, winv, status);
+      hipLaunchKernelGGL(k_vs_scale, dim3(cdiv(t, 256), Rg), dim3(256), 0, s, a, winv, out + (size_t)r0 * ld_out,
+                         ld_out);
+    }
+    r0 += Rg;
   }
   return hipGetLastError();
 }

@@ -20,7 +20,8 @@ struct VsolvePlan {
   uint32_t RT, ntile;  // right-hand sides per tile (even), number of tiles
   uint32_t ldv;        // row stride (32-bit words) of one packed row of a tile
   uint32_t pc;         // 1: producer/consumer pass (chain once per row block, one wave per tile)
-  uint32_t Sd;         // partial dot-product sums per row and right-hand side (= S)
+  uint32_t Sd;         // partial-sum slots per row and right-hand side (the chunks take them in turn)
+  uint32_t ng, Rg;     // right-hand-side groups (one dot-product pass each) and the largest group's size
 };
 VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus);
 // true when the producer/consumer pass is selected (solve variant 1, the default)

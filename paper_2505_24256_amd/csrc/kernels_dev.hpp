@@ -255,19 +255,25 @@ __device__ __forceinline__ void vs_dots_body(const VsArgs& a, uint32_t rb, uint3
 // q_{l,r} through LDS in blocks of kQB steps (double buffered); wave 1 + tile
 // accumulates that tile's RT dot products.  Compared with one wave per tile,
 // the chain is computed once instead of ntile times and the consumer waves
-// hold no chain state, which leaves room for RT = 20 at two waves per SIMD.
+// hold no chain state.
 constexpr uint32_t kQB = 16;
 constexpr uint32_t kPcMinR = 10;     // more right-hand sides than this: producer/consumer pass
 constexpr uint32_t kPcRT = 10;       // right-hand sides per consumer wave (at most)
 constexpr uint32_t kPcMaxTiles = 7;  // consumer waves per workgroup (at most)
+// Right-hand sides of one producer/consumer pass, at most: seven consumer waves
+// of ten values take 140 VGPRs, which leaves one 8-wave workgroup per CU; of
+// nine (128 VGPRs) two fit (t = 10^5: 64 values ran at 14.5 TOP/s, 60 at 19.3).
+// More right-hand sides are solved in groups (vsolve).
+constexpr uint32_t kPcMaxR = 63;
 
 // Consumer waves per workgroup for R right-hand sides: at least
 // cdiv(R, kPcRT), rounded up so that the workgroup's 1 + ntile waves are a
 // multiple of the CU's four SIMDs.  Every SIMD then carries the same share of
 // the workgroup, and the barriers that pace producer and consumers do not wait
 // on one overloaded SIMD (at R = 40, workgroups of 5 and 6 waves measured 1.7x
-// and 1.2x slower than 8).  0 when R needs more than kPcMaxTiles waves.
+// and 1.2x slower than 8).  0 when R is above kPcMaxR.
 __host__ __device__ inline uint32_t pc_tiles_for(uint32_t R) {
+  if (R > kPcMaxR) return 0;
   uint32_t n = cdiv(R, kPcRT);
   while ((1 + n) % 4) ++n;
   return n <= kPcMaxTiles ? n : 0;

@@ -83,8 +83,9 @@ struct Union {
   uint64_t* coef = nullptr;  // [E][t]
 };
 
-// Right-hand sides in groups of at most 70 (the producer/consumer pass's
-// widest workgroup: seven consumer waves of ten), one master polynomial.
+// All expressions' right-hand sides in one solve over the union skeleton: one
+// master polynomial, and one chain pass and inversion for all (vsolve takes
+// more than kPcMaxR right-hand sides in groups).
 void solve_groups(const Params& P, const Union& U, uint64_t* rhs, uint32_t R, hipStream_t s, int32_t* d_status) {
   const uint32_t t = U.t;
   if (t == 0 || R == 0) return;
@@ -92,20 +93,9 @@ void solve_groups(const Params& P, const Union& U, uint64_t* rhs, uint32_t R, hi
   uint64_t* Mc = A.alloc<uint64_t>(t);
   uint64_t* tmp = A.alloc<uint64_t>(master_tmp_words(t));
   check(master_poly(P.M, t, U.mono, Mc, tmp, s));
-  const uint32_t per = kPcMaxTiles * kPcRT, ng = cdiv(R, per), base = R / ng, extra = R % ng;
-  size_t words = 0;
-  std::vector<VsolvePlan> plans(ng);
-  for (uint32_t g = 0; g < ng; ++g) {
-    plans[g] = vsolve_plan(t, base + (g < extra ? 1 : 0), device_cus());
-    words = std::max(words, vsolve_workspace_words(plans[g]));
-  }
-  uint64_t* work = A.alloc<uint64_t>(words);
-  uint32_t r0 = 0;
-  for (uint32_t g = 0; g < ng; ++g) {
-    uint64_t* rows = rhs + (size_t)r0 * t;
-    check(vsolve(P.M, plans[g], U.mono, Mc, rows, t, rows, t, work, d_status, s));
-    r0 += plans[g].R;
-  }
+  const VsolvePlan plan = vsolve_plan(t, R, device_cus());
+  uint64_t* work = A.alloc<uint64_t>(vsolve_workspace_words(plan));
+  check(vsolve(P.M, plan, U.mono, Mc, rhs, t, rhs, t, work, d_status, s));
   count_solve(t, R);
 }
 

@@ -63,7 +63,7 @@ bool vsolve_plan_within(uint32_t t, uint32_t R, uint32_t num_cus, size_t max_wor
     *out = Q;
     return true;
   }
-  const size_t per_slot = std::max<size_t>((size_t)R * t, 1);
+  const size_t per_slot = std::max<size_t>((size_t)Q.Rg * t, 1);
   if (Q.pc) {
     VsolvePlan P = Q;
     P.Sd = 1;

@@ -47,9 +47,11 @@ def _both(zr, p, m, rhs):
 def test_noalloc_equals_allocating_solve_twice():
     import paper_2505_24256_amd as zr
     p = synth.make_prime()
-    # first: 40 right-hand sides (producer/consumer pass, several chunks);
-    # second: smaller and with fewer right-hand sides (one wave per tile)
-    for t, R, seed in ((6000, 40, 71), (700, 7, 72)):
+    # first: 40 right-hand sides, more chunks than the fixed workspace holds
+    # partial-sum slots for (the chunks take the slots in turn over several
+    # launches); second: fewer chunks, all with a slot of their own; third:
+    # smaller and with fewer right-hand sides (one wave per tile)
+    for t, R, seed in ((20000, 40, 70), (6000, 40, 71), (700, 7, 72)):
         m, rhs = _system(p, t, R, seed)
         print(f"[no-alloc] t={t} R={R} seed={seed}", flush=True)
         ref, got, st_ref, st_got = _both(zr, p, m, rhs)
