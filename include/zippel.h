@@ -447,6 +447,7 @@ typedef struct {
   uint32_t stages;
   uint64_t max_t;
   uint64_t dot_products;  /* of which the dot products of the solves: R t^2 per system */
+  uint64_t chain_steps;   /* steps of the synthetic-division chains q_{l,r}: t(t-1) per system */
 } zr_counters;
 void zr_last_counters(zr_counters* out);
 

@@ -84,7 +84,8 @@ class ZrServerStats(ctypes.Structure):
 
 class ZrCounters(ctypes.Structure):
     _fields_ = [("mulmods", ctypes.c_uint64), ("solve_mulmods", ctypes.c_uint64), ("vsolve_terms", ctypes.c_uint64),
-                ("stages", ctypes.c_uint32), ("max_t", ctypes.c_uint64), ("dot_products", ctypes.c_uint64)]
+                ("stages", ctypes.c_uint32), ("max_t", ctypes.c_uint64), ("dot_products", ctypes.c_uint64),
+                ("chain_steps", ctypes.c_uint64)]
 
 
 BLACKBOX_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ZrPoints), ctypes.c_void_p,

@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(64 * (1 + kPcMaxTiles))
     a.VT = vt_base + b.vt_off;
     a.spart = part_base + b.sp_off;
     a.hpart = part_base + b.hp_off;
-    vs_dots_pc_body<RT>(a, w.y, w.z, b.ntile, qbuf);
+    vs_dots_pc_body<RT, true>(a, w.y, w.z, b.ntile, qbuf);
   }
 }
 

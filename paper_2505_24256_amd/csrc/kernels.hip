@@ -134,6 +134,13 @@ VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
   P.L = std::max<uint32_t>(1, cdiv(t, S));
   P.S = std::max<uint32_t>(1, cdiv(t, P.L));
   P.Sd = P.S;
+  // delta from the chain pass instead of a Horner sum in the producer where the
+  // producer's SIMD sets the pace: seven consumers of at most seven values.
+  // At R = 40 (seven of six) the pass ran 12% faster without the producer's
+  // Horner (t = 5*10^5: 2.46 -> 2.15 s, for 0.26 s more chain pass); at R = 30
+  // (three of ten) and R = 56 (seven of eight) 1-2%, less than the chain pass
+  // adds.
+  P.dchain = P.pc && P.ntile == kPcMaxTiles && P.RT <= 7 ? 1 : 0;
   if (P.pc) {
     const uint32_t sd_max =
         (uint32_t)std::max<uint64_t>(1, kSpartBytes / (8ull * std::max<uint32_t>(P.Rg, 1) * std::max<uint32_t>(t, 1)));
@@ -144,28 +151,44 @@ VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
 
 // workspace layout (64-bit words): right-hand sides VT [ntile][t][ldv/2] |
 //                   mono_p [t] | Bc [S][t] | qstart [S][t] | mL [t] |
-//                   spart [Sd][R][t] | hpart [S][t] | winv [2t]
+//                   spart [Sd][Rg][t] | dpart [S][t] | winv [2t] | CL [t][6] (32-bit)
 static size_t vsolve_rhs_words(const VsolvePlan& P) { return (size_t)P.ntile * P.t * (P.ldv / 2); }
 
 size_t vsolve_workspace_words(const VsolvePlan& P) {
   const size_t t = P.t, S = P.S;
-  return vsolve_rhs_words(P) + t + 2 * S * t + t + P.Sd * (size_t)P.Rg * t + S * t + 2 * t + 64;
+  return vsolve_rhs_words(P) + t + 2 * S * t + t + P.Sd * (size_t)P.Rg * t + S * t + 2 * t + 3 * t + 64;
 }
 
-// Packed right-hand sides [ntile][t][ldv] and Shoup constants of the monomials.
+// Packed right-hand sides [ntile][t][ldv], Shoup constants of the monomials
+// and the coefficients r M_r of m M'(m).
 __global__ void k_pack(uint32_t t, uint32_t R, uint32_t RT, uint32_t ntile, uint32_t ldv,
                        const uint64_t* __restrict__ rhs, size_t ld_rhs, const uint64_t* __restrict__ Mc,
                        uint32_t* __restrict__ VT, const uint64_t* __restrict__ mono, uint64_t* __restrict__ mono_p,
-                       zr_mod M) {
+                       uint32_t* __restrict__ CL, zr_mod M) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t total = (size_t)ntile * t * ldv;
   if (idx < total) VT[idx] = pack_word(idx, t, R, RT, ldv, rhs, ld_rhs, Mc);
-  if (idx < t) mono_p[idx] = zr_shoup_pre(M, mono[idx]);
+  if (idx < t) {
+    mono_p[idx] = zr_shoup_pre(M, mono[idx]);
+    const uint64_t v = Mc[idx], d = zr_mul(M, idx % M.p, v);
+    uint32_t* w = CL + idx * kChainW;
+    w[0] = (uint32_t)(v & 0x3FFFFF);
+    w[1] = (uint32_t)((v >> 22) & 0x3FFFFF);
+    w[2] = (uint32_t)(v >> 44);
+    w[3] = (uint32_t)(d & 0x3FFFFF);
+    w[4] = (uint32_t)((d >> 22) & 0x3FFFFF);
+    w[5] = (uint32_t)(d >> 44);
+  }
 }
 
+// Chain values B_c (WB, the chunks c < S-1) and partials D_c of m M'(m) (WD):
+// B and D for the chunks c < S-1 and D alone for the last one when delta
+// comes from this pass, else B alone.  One kernel per stream set, so that each
+// is compiled for its own registers.
+template <bool WB, bool WD>
 __global__ void __launch_bounds__(256) k_vs_chain(VsArgs a) {
   const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l < a.t) vs_chain_body(a, l, blockIdx.y);
+  if (l < a.t) vs_chain_cl<WB, WD>(a, l, WB ? blockIdx.y : a.S - 1);
 }
 
 __global__ void k_vs_scan(VsArgs a, uint64_t* __restrict__ qstart, uint64_t* __restrict__ mL_out) {
@@ -179,10 +202,10 @@ __global__ void __launch_bounds__(64) k_vs_dots(VsArgs a) {
 }
 
 // producer + one consumer wave per tile (64 * (1 + ntile) threads)
-template <int RT>
+template <int RT, bool HORNER>
 __global__ void __launch_bounds__(64 * (1 + kPcMaxTiles)) k_vs_dots_pc(VsArgs a, uint32_t ntile, uint32_t c0) {
   __shared__ uint64_t qbuf[2][kQB][64];
-  vs_dots_pc_body<RT>(a, blockIdx.x, c0 + blockIdx.y, ntile, qbuf);
+  vs_dots_pc_body<RT, HORNER>(a, blockIdx.x, c0 + blockIdx.y, ntile, qbuf);
 }
 
 __global__ void __launch_bounds__(kDeltaBlock) k_vs_delta(VsArgs a, const uint64_t* __restrict__ mLv,
@@ -211,15 +234,21 @@ static DotsKernel dots_kernel(uint32_t RT) {
 }
 
 typedef void (*DotsPcKernel)(VsArgs, uint32_t, uint32_t);
-template <int RT>
+template <int RT, bool H>
 static DotsPcKernel dots_pc_ptr() {
-  return k_vs_dots_pc<RT>;
+  return k_vs_dots_pc<RT, H>;
 }
-static DotsPcKernel dots_pc_kernel(uint32_t RT) {
-  static const DotsPcKernel table[kPcRT + 1] = {
-      nullptr,          dots_pc_ptr<1>(), dots_pc_ptr<2>(), dots_pc_ptr<3>(), dots_pc_ptr<4>(), dots_pc_ptr<5>(),
-      dots_pc_ptr<6>(), dots_pc_ptr<7>(), dots_pc_ptr<8>(), dots_pc_ptr<9>(), dots_pc_ptr<10>()};
-  return RT >= 1 && RT <= kPcRT ? table[RT] : nullptr;
+// the producer/consumer pass for RT values per consumer, with the producer's
+// Horner sum (horner) or without it (delta from the chain pass)
+static DotsPcKernel dots_pc_kernel(uint32_t RT, bool horner = true) {
+  static const DotsPcKernel table[2][kPcRT + 1] = {
+      {nullptr, dots_pc_ptr<1, false>(), dots_pc_ptr<2, false>(), dots_pc_ptr<3, false>(), dots_pc_ptr<4, false>(),
+       dots_pc_ptr<5, false>(), dots_pc_ptr<6, false>(), dots_pc_ptr<7, false>(), dots_pc_ptr<8, false>(),
+       dots_pc_ptr<9, false>(), dots_pc_ptr<10, false>()},
+      {nullptr, dots_pc_ptr<1, true>(), dots_pc_ptr<2, true>(), dots_pc_ptr<3, true>(), dots_pc_ptr<4, true>(),
+       dots_pc_ptr<5, true>(), dots_pc_ptr<6, true>(), dots_pc_ptr<7, true>(), dots_pc_ptr<8, true>(),
+       dots_pc_ptr<9, true>(), dots_pc_ptr<10, true>()}};
+  return RT >= 1 && RT <= kPcRT ? table[horner ? 1 : 0][RT] : nullptr;
 }
 
 // Workgroups of the producer/consumer pass resident per CU for ntile tiles.
@@ -257,7 +286,9 @@ hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, co
   uint64_t* qstart = Bc + S * t;
   uint64_t* mL = qstart + S * t;
   uint64_t* spart = mL + t;
-  uint64_t* hpart = spart + P.Sd * (size_t)P.Rg * t;
+  uint64_t* dpart = spart + P.Sd * (size_t)P.Rg * t;
+  uint64_t* winv = dpart + S * t;
+  uint32_t* CL = (uint32_t*)(winv + 2 * t);
   VsArgs a;
   a.M = M;
   a.t = P.t;
@@ -273,8 +304,11 @@ hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, co
   a.qstart = S > 1 ? qstart : nullptr;
   a.Bc = Bc;
   a.spart = spart;
-  a.hpart = hpart;
-  uint64_t* winv = hpart + S * t;
+  a.CL = CL;
+  // per-chunk partials of delta: D_c from the chain pass, or the Horner sums
+  // of the dot-product pass
+  a.hpart = P.dchain ? nullptr : dpart;
+  a.dpart = P.dchain ? dpart : nullptr;
   // right-hand-side groups in turn; the chain values and start values (before
   // the first group's dot products) and the inverses (after them, from the
   // Horner partials) are the same for all and made once
@@ -285,20 +319,25 @@ hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, co
       const size_t total = std::max<size_t>(P.ntile * t * P.ldv, t);  // 32-bit words
       TimedLaunch tl("vs_pack", s);
       hipLaunchKernelGGL(k_pack, dim3(cdiv(total, 256)), dim3(256), 0, s, P.t, Rg, P.RT, P.ntile, P.ldv,
-                         rhs + (size_t)r0 * ld_rhs, ld_rhs, Mc, (uint32_t*)VT, mono, mono_p, M);
+                         rhs + (size_t)r0 * ld_rhs, ld_rhs, Mc, (uint32_t*)VT, mono, mono_p, CL, M);
     }
-    if (g == 0 && S > 1) {
+    if (g == 0) {
       {
         TimedLaunch tl("vs_chain", s);
-        hipLaunchKernelGGL(k_vs_chain, dim3(cdiv(t, 256), P.S - 1), dim3(256), 0, s, a);
+        if (P.dchain) {
+          if (S > 1) hipLaunchKernelGGL((k_vs_chain<true, true>), dim3(cdiv(t, 256), P.S - 1), dim3(256), 0, s, a);
+          hipLaunchKernelGGL((k_vs_chain<false, true>), dim3(cdiv(t, 256)), dim3(256), 0, s, a);
+        } else if (S > 1) {
+          hipLaunchKernelGGL((k_vs_chain<true, false>), dim3(cdiv(t, 256), P.S - 1), dim3(256), 0, s, a);
+        }
       }
-      {
+      if (S > 1) {
         TimedLaunch tl("vs_scan", s);
         hipLaunchKernelGGL(k_vs_scan, dim3(cdiv(t, 256)), dim3(256), 0, s, a, qstart, mL);
       }
     }
     if (P.pc) {
-      DotsPcKernel kp = dots_pc_kernel(P.RT);
+      DotsPcKernel kp = dots_pc_kernel(P.RT, !P.dchain);
       if (!kp) return hipErrorInvalidValue;
       // chunks in launches of Sd (one partial-sum slot each), in order
       for (uint32_t c0 = 0; c0 < P.S; c0 += P.Sd) {

@@ -32,7 +32,9 @@ struct VsArgs {
   const uint64_t* qstart;
   uint64_t* Bc;
   uint64_t* spart;
-  uint64_t* hpart;
+  uint64_t* hpart;              // Horner partials per chunk (null: the dot-product pass runs no Horner)
+  const uint32_t* CL = nullptr;  // limbs of M_r and r M_r for the chain pass (kChainW words per r)
+  uint64_t* dpart = nullptr;      // D_c = sum over chunk c of r M_r m^(r - lo_c), per chunk and row
 };
 
 __device__ __forceinline__ void chunk_range(uint32_t t, uint32_t L, uint32_t c, uint32_t& lo, uint32_t& hi) {
@@ -200,7 +202,7 @@ __device__ __forceinline__ void vs_dots_body(const VsArgs& a, uint32_t rb, uint3
 #pragma unroll
   for (int j = 0; j < RT; ++j) acc6_zero(acc[j]);
   const VGroup* __restrict__ rows = (const VGroup*)((const uint32_t*)a.VT + (size_t)tile * a.t * LDV);
-  const bool horner = tile == 0;
+  const bool horner = tile == 0 && a.hpart != nullptr;
   uint32_t r = hi - 1;
   uint32_t since = 0;
   VGroup buf[G];
@@ -285,6 +287,9 @@ __host__ __device__ inline uint32_t pc_tiles_for(uint32_t R) {
 template <class T>
 using const_as = const __attribute__((address_space(4))) T*;
 
+// 16 words of a uniform array at any 4-byte boundary (one scalar load)
+typedef uint32_t u32x16a4 __attribute__((ext_vector_type(16))) __attribute__((aligned(4)));
+
 // Pass 1 for row l, chunk c < S-1: B_c = sum_{lo <= r < hi} M_r m^(r-lo), the
 // chain over the chunk started from 0, evaluated by baby steps and giant
 // steps.  With r - lo = K j + i (0 <= i < K),
@@ -292,8 +297,8 @@ using const_as = const __attribute__((address_space(4))) T*;
 // the K powers m^i are made once per row and chunk (K Shoup products); each
 // s_j is an exact six-column sum of K products of the uniform M_r (22-bit
 // limbs, scalar) with the lane's powers, reduced once; the outer sum is Horner
-// in m^K.  About ten vector instructions per step instead of a Shoup product
-// and a reduction per step.
+// in m^K.  (The batched solve and the multi-prime evaluation; the one-system
+// solve uses vs_chain_cl below.)
 constexpr int kChainK = 32;  // K: below kFold, so a block's columns never fold
 
 __device__ __forceinline__ void vs_chain_body(const VsArgs& a, uint32_t l, uint32_t c) {
@@ -327,6 +332,98 @@ __device__ __forceinline__ void vs_chain_body(const VsArgs& a, uint32_t l, uint3
   a.Bc[(size_t)c * a.t + l] = y;
 }
 
+// Coefficients of the one-system chain pass, split once into 22-bit limbs:
+// per r < t the limbs of M_r and of r M_r (six 32-bit words).
+constexpr uint32_t kChainW = 6;
+
+// Sum of a block's six columns mod p when every column is below 2^60 (at most
+// 64 products since the last fold): the value is below 2^137, three words
+// with the top one below 2^9.  No branch, so the products of a block and its
+// reduction stay in one basic block.
+__device__ __forceinline__ uint64_t acc6_reduce_block(const zr_mod& M, const Acc6& a) {
+  const zr_u128 low = (zr_u128)a.w0 + ((zr_u128)a.w22 << 22) + ((zr_u128)a.w32 << 32) + ((zr_u128)a.w44 << 44) +
+                      ((zr_u128)a.w54 << 54);  // below 2^115
+  const zr_u128 mid = (low >> 64) + ((zr_u128)a.w76 << 12);  // bits 64.. of the value, below 2^73
+  const uint64_t w0 = (uint64_t)low, w1 = (uint64_t)mid, w2 = (uint64_t)(mid >> 64);
+  uint64_t r = zr_mod128(M, 0, w2);
+  r = zr_mod128(M, r, w1);
+  return zr_mod128(M, r, w0);
+}
+
+// Pass 1 of the one-system solve for row l and chunk c: B_c as above (WB,
+// chunks c < S-1) and, when delta comes from this pass (WD), also
+// D_c = sum_{lo <= r < hi} r M_r m^(r-lo), the chunk's share of
+// m M'(m) = sum_r r M_r m^r, from the same powers of m.  The coefficients come
+// from the limb array CL: eight steps of both streams (48 words) arrive by
+// three 16-word scalar loads at a time.
+template <bool WB, bool WD>
+__device__ __forceinline__ void vs_chain_cl(const VsArgs& a, uint32_t l, uint32_t c) {
+  uint32_t lo, hi;
+  chunk_range(a.t, a.L, c, lo, hi);
+  const zr_mod M = a.M;
+  const uint64_t m = a.mono[l], mp = a.mono_p[l];
+  const_as<uint32_t> CL = (const_as<uint32_t>)a.CL;  // uniform: the chunk is the block's
+  uint64_t pw[kChainK];
+  pw[0] = 1 % M.p;
+#pragma unroll
+  for (int i = 1; i < kChainK; ++i) pw[i] = zr_shoup(M, pw[i - 1], m, mp);
+  const uint64_t mK = zr_shoup(M, pw[kChainK - 1], m, mp), mKp = zr_shoup_pre(M, mK);
+  uint64_t y = 0, z = 0;
+  Acc6 ab, ad;
+  auto fold_in = [&]() {
+    if (WB) y = zr_add(M, zr_shoup(M, y, mK, mKp), acc6_reduce_block(M, ab));
+    if (WD) z = zr_add(M, zr_shoup(M, z, mK, mKp), acc6_reduce_block(M, ad));
+  };
+  auto step = [&](int i, uint32_t b0, uint32_t b1, uint32_t b2, uint32_t d0, uint32_t d1, uint32_t d2) {
+    const uint32_t p0 = (uint32_t)pw[i], p1 = (uint32_t)(pw[i] >> 32);
+    if (WB) acc6_mac(ab, p0, p1, b0, b1, b2);
+    if (WD) acc6_mac(ad, p0, p1, d0, d1, d2);
+  };
+  // the top block, r in [base, hi), may be partial
+  const uint32_t nfull = (hi - lo) / kChainK;
+  const uint32_t base_top = lo + nfull * kChainK;
+  if (base_top < hi) {
+    acc6_zero(ab);
+    acc6_zero(ad);
+    const uint32_t n = hi - base_top;
+#pragma unroll
+    for (int i = 0; i < kChainK; ++i)
+      if ((uint32_t)i < n) {
+        const_as<uint32_t> w = CL + (size_t)(base_top + i) * kChainW;
+        step(i, w[0], w[1], w[2], w[3], w[4], w[5]);
+      }
+    fold_in();
+  }
+  for (uint32_t j = nfull; j-- > 0;) {
+    acc6_zero(ab);
+    acc6_zero(ad);
+#pragma unroll
+    for (int g = 0; g < kChainK / 8; ++g) {
+      // the group's address passes through an empty asm so that its loads
+      // cannot be hoisted above the previous group's products
+      const_as<u32x16a4> src = (const_as<u32x16a4>)(CL + (size_t)(lo + j * kChainK + 8 * g) * kChainW);
+      asm volatile("" : "+s"(src));
+      const u32x16a4 c0 = src[0], c1 = src[1], c2 = src[2];
+      uint32_t w[48];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        w[k] = c0[k];
+        w[16 + k] = c1[k];
+        w[32 + k] = c2[k];
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        step(8 * g + i, w[6 * i], w[6 * i + 1], w[6 * i + 2], w[6 * i + 3], w[6 * i + 4], w[6 * i + 5]);
+      // one group's 48 words live at a time: the next group's loads are not
+      // hoisted above this group's products
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    fold_in();
+  }
+  if (WB) a.Bc[(size_t)c * a.t + l] = y;
+  if (WD) a.dpart[(size_t)c * a.t + l] = z;
+}
+
 // Packed row of the producer/consumer pass: the 3 RT limbs of the tile's
 // values at one step, without M_r (the producer reads M_r itself).  It is
 // loaded through the scalar cache as one 16-word group and a tail of K words,
@@ -339,7 +436,6 @@ __host__ __device__ constexpr uint32_t pc_tail(uint32_t RT) {
 }
 __host__ __device__ constexpr uint32_t pc_ldv(uint32_t RT) { return 16 + pc_tail(RT); }
 
-typedef uint32_t u32x16a4 __attribute__((ext_vector_type(16))) __attribute__((aligned(4)));
 template <int K>
 struct PcTail {
   typedef uint32_t type __attribute__((ext_vector_type(K))) __attribute__((aligned(4)));
@@ -404,7 +500,9 @@ __device__ __forceinline__ void vs_pc_step(const zr_mod& M, Acc6 (&acc)[RT], con
   q = qn;
 }
 
-template <int RT>
+// HORNER: the producer also sums h = q(m) over the chunk into hpart (the
+// batched solve); without it delta comes from the chain pass's D_c.
+template <int RT, bool HORNER>
 __device__ __forceinline__ void vs_dots_pc_body(const VsArgs& a, uint32_t rb, uint32_t c, uint32_t ntile,
                                                 uint64_t (*qbuf)[kQB][64]) {
   constexpr uint32_t LDV = pc_ldv(RT);
@@ -443,7 +541,7 @@ __device__ __forceinline__ void vs_dots_pc_body(const VsArgs& a, uint32_t rb, ui
               // q and h kept in [0, 2p); the consumers' column sums take any
               // q below 2^64.  cur[u] - 2p is uniform (scalar unit).
               qbuf[it & 1][g8 * 8 + u][lane] = q;
-              h = add_lazy2p(shoup_lazy_v(h, m, mp, M.p), q - p2, p2);
+              if (HORNER) h = add_lazy2p(shoup_lazy_v(h, m, mp, M.p), q - p2, p2);
               q = add_lazy2p(shoup_lazy_v(q, m, mp, M.p), cur[u] - p2, p2);
             }
           }
@@ -454,7 +552,7 @@ __device__ __forceinline__ void vs_dots_pc_body(const VsArgs& a, uint32_t rb, ui
       }
       __syncthreads();
     }
-    if (live) a.hpart[(size_t)c * a.t + l] = h >= M.p ? h - M.p : h;
+    if (HORNER && live) a.hpart[(size_t)c * a.t + l] = h >= M.p ? h - M.p : h;
     return;
   }
   // consumer of tile wave - 1
@@ -552,10 +650,13 @@ __device__ __forceinline__ uint64_t block_inverse(const zr_mod& M, uint64_t w, b
 }
 
 // Combine chunks, part 1 for the rows of one block (l = row of this thread,
-// live when l < t): delta = sum_c m^{lo_c} H_c by Horner over the chunk
-// partials, w = m delta, and the inverses of the block's w (one inversion per
-// block) with their Shoup constants into winv[2t]; a zero w marks the system
-// singular.  Every thread of the block must call it (it holds barriers).
+// live when l < t): w = m_l delta_l = m_l M'(m_l), either as
+// t m^t + sum_c m^{lo_c} D_c from the chain pass's D_c, or as m times
+// sum_c m^{lo_c} H_c from the Horner partials H_c of the dot-product pass,
+// both by Horner over the chunks; then the inverses of the block's w (one
+// inversion per block) with their Shoup constants into winv[2t].  A zero w
+// marks the system singular.  Every thread of the block must call it (it
+// holds barriers).
 __device__ __forceinline__ void vs_delta_block(const VsArgs& a, uint32_t l, const uint64_t* __restrict__ mLv,
                                                uint64_t* __restrict__ winv, int32_t* __restrict__ status,
                                                uint64_t* sh) {
@@ -564,17 +665,27 @@ __device__ __forceinline__ void vs_delta_block(const VsArgs& a, uint32_t l, cons
   uint64_t w = 0;
   if (live) {
     const uint64_t m = a.mono[l];
-    uint64_t delta = a.hpart[l];
+    // chunk partials from the top chunk (c = 0) down, Horner in m^L (m^len
+    // for the last, shorter chunk)
+    const uint64_t* part = a.dpart ? a.dpart : a.hpart;
+    uint64_t acc = part[l];
+    uint64_t mL = 0, mLp = 0;
     if (a.S > 1) {
-      const uint64_t mL = mLv[l], mLp = zr_shoup_pre(M, mL);
+      mL = mLv[l];
+      mLp = zr_shoup_pre(M, mL);
       const uint32_t len_last = a.t - (a.S - 1) * a.L;
       const uint64_t mlast = zr_pow(M, m, len_last);
+      // with D_c, the leading term t m^t = m^(lo_0) t m^L enters first
+      if (a.dpart) acc = zr_add(M, zr_mul(M, a.t % M.p, mL), acc);
       for (uint32_t c = 1; c < a.S; ++c) {
-        const uint64_t hc = a.hpart[(size_t)c * a.t + l];
-        delta = (c + 1 < a.S) ? zr_add(M, zr_shoup(M, delta, mL, mLp), hc) : zr_add(M, zr_mul(M, delta, mlast), hc);
+        const uint64_t pc = part[(size_t)c * a.t + l];
+        acc = (c + 1 < a.S) ? zr_add(M, zr_shoup(M, acc, mL, mLp), pc) : zr_add(M, zr_mul(M, acc, mlast), pc);
       }
+    } else if (a.dpart) {
+      acc = zr_add(M, zr_mul(M, a.t % M.p, zr_pow(M, m, a.t)), acc);
     }
-    w = zr_mul(M, m, delta);
+    // with D_c the sum is m M'(m) itself; the Horner partials give M'(m)
+    w = a.dpart ? acc : zr_mul(M, m, acc);
     if (w == 0) atomicCAS(status, 0, -3);  // ZR_ESINGULAR, unless an earlier step already failed
   }
   const uint64_t wi = block_inverse(M, w, live, sh);

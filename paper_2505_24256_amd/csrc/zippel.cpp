@@ -380,6 +380,7 @@ void count_solve(uint64_t t, uint64_t R) {
   g_counters.solve_mulmods += R * t * t + 2 * t * (t ? t - 1 : 0);
   g_counters.vsolve_terms += t * R;
   g_counters.dot_products += R * t * t;
+  g_counters.chain_steps += t * (t ? t - 1 : 0);
   g_counters.max_t = std::max<uint64_t>(g_counters.max_t, t);
 }
 

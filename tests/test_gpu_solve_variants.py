@@ -48,7 +48,7 @@ def _system(p, t, R, seed):
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("t,R", [(1, 1), (2, 3), (15, 1), (16, 2), (17, 5), (63, 10), (64, 16), (65, 17),
                                  (200, 30), (1000, 33), (777, 40), (1100, 15), (2500, 30), (300, 64),
-                                 (640, 70), (1000, 100), (129, 127)])
+                                 (640, 70), (1000, 100), (129, 127), (100, 33), (250, 40)])
 def test_solve_matches_oracle(zr, variant, t, R):
     p = synth.make_prime()
     m, rhs = _system(p, t, R, 1)
