@@ -408,8 +408,7 @@ hipError_t master_poly(const zr_mod& M, uint32_t t, const uint64_t* mono, uint64
     w ^= 1;
     const uint32_t IC = conv_ic(half, cdiv(t, 64));
     const uint32_t nic = cdiv(half, IC);
-    launch_master_conv(dim3(cdiv(t, 64), nic), (64 + IC + 8) * 8, s, M, t, half, IC, nic, bufs[r], limbs[r], part,
-                       bufs[w], limbs[w]);
+    launch_master_conv(s, M, t, half, IC, nic, bufs[r], limbs[r], part, bufs[w], limbs[w]);
     if (nic > 1)
       hipLaunchKernelGGL(k_master_sum, dim3(cdiv(t, 256)), dim3(256), 0, s, M, t, half, nic, bufs[r], part, bufs[w],
                          limbs[w]);

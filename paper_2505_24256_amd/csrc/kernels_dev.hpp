@@ -358,16 +358,21 @@ __device__ __forceinline__ uint64_t acc6_reduce_block(const zr_mod& M, const Acc
 // three 16-word scalar loads at a time.
 template <bool WB, bool WD>
 __device__ __forceinline__ void vs_chain_cl(const VsArgs& a, uint32_t l, uint32_t c) {
+  // baby steps per block: with both streams 48 (against 32) cuts the
+  // reductions per step and still leaves two waves per SIMD; one stream keeps
+  // 32 and three waves.  A block's columns stay below 2^60, as
+  // acc6_reduce_block needs.
+  constexpr int KC = WB && WD ? 48 : kChainK;
   uint32_t lo, hi;
   chunk_range(a.t, a.L, c, lo, hi);
   const zr_mod M = a.M;
   const uint64_t m = a.mono[l], mp = a.mono_p[l];
   const_as<uint32_t> CL = (const_as<uint32_t>)a.CL;  // uniform: the chunk is the block's
-  uint64_t pw[kChainK];
+  uint64_t pw[KC];
   pw[0] = 1 % M.p;
 #pragma unroll
-  for (int i = 1; i < kChainK; ++i) pw[i] = zr_shoup(M, pw[i - 1], m, mp);
-  const uint64_t mK = zr_shoup(M, pw[kChainK - 1], m, mp), mKp = zr_shoup_pre(M, mK);
+  for (int i = 1; i < KC; ++i) pw[i] = zr_shoup(M, pw[i - 1], m, mp);
+  const uint64_t mK = zr_shoup(M, pw[KC - 1], m, mp), mKp = zr_shoup_pre(M, mK);
   uint64_t y = 0, z = 0;
   Acc6 ab, ad;
   auto fold_in = [&]() {
@@ -380,14 +385,14 @@ __device__ __forceinline__ void vs_chain_cl(const VsArgs& a, uint32_t l, uint32_
     if (WD) acc6_mac(ad, p0, p1, d0, d1, d2);
   };
   // the top block, r in [base, hi), may be partial
-  const uint32_t nfull = (hi - lo) / kChainK;
-  const uint32_t base_top = lo + nfull * kChainK;
+  const uint32_t nfull = (hi - lo) / KC;
+  const uint32_t base_top = lo + nfull * KC;
   if (base_top < hi) {
     acc6_zero(ab);
     acc6_zero(ad);
     const uint32_t n = hi - base_top;
 #pragma unroll
-    for (int i = 0; i < kChainK; ++i)
+    for (int i = 0; i < KC; ++i)
       if ((uint32_t)i < n) {
         const_as<uint32_t> w = CL + (size_t)(base_top + i) * kChainW;
         step(i, w[0], w[1], w[2], w[3], w[4], w[5]);
@@ -398,10 +403,10 @@ __device__ __forceinline__ void vs_chain_cl(const VsArgs& a, uint32_t l, uint32_
     acc6_zero(ab);
     acc6_zero(ad);
 #pragma unroll
-    for (int g = 0; g < kChainK / 8; ++g) {
+    for (int g = 0; g < KC / 8; ++g) {
       // the group's address passes through an empty asm so that its loads
       // cannot be hoisted above the previous group's products
-      const_as<u32x16a4> src = (const_as<u32x16a4>)(CL + (size_t)(lo + j * kChainK + 8 * g) * kChainW);
+      const_as<u32x16a4> src = (const_as<u32x16a4>)(CL + (size_t)(lo + j * KC + 8 * g) * kChainW);
       asm volatile("" : "+s"(src));
       const u32x16a4 c0 = src[0], c1 = src[1], c2 = src[2];
       uint32_t w[48];
@@ -787,13 +792,18 @@ __device__ __forceinline__ uint64_t master_linear_terms(const zr_mod& M, uint64_
   return s;
 }
 
+// NW waves of one workgroup take 64 NW consecutive coefficients of one
+// product (64 NW <= 2 half) and share one LDS window, so a window of
+// 64 NW + IC words serves NW waves.
+template <int NW = 1>
 __device__ __forceinline__ void master_conv_body(const zr_mod& M, uint32_t t, uint32_t half, uint32_t IC, uint32_t nic,
                                                  uint32_t g0, uint32_t ic, const uint64_t* __restrict__ cur,
                                                  const uint4* __restrict__ limbs, uint64_t* __restrict__ part,
                                                  size_t ld_part, uint64_t* __restrict__ nxt,
                                                  uint4* __restrict__ limbs_nxt, uint64_t* win) {
-  const uint32_t g = g0 + (threadIdx.x & 63);
-  const uint32_t a = (g0 / (2 * half)) * (2 * half);  // one product per wave since 2*half >= 64
+  constexpr uint32_t W = 64 * NW;  // coefficients of the workgroup, from g0
+  const uint32_t g = g0 + (threadIdx.x & (W - 1));
+  const uint32_t a = (g0 / (2 * half)) * (2 * half);  // one product per workgroup since 2*half >= W
   const uint32_t n1 = std::min(half, t - a);
   const uint32_t n2 = std::min(half, t - a - n1);
   const uint32_t k0 = g0 - a;
@@ -804,7 +814,7 @@ __device__ __forceinline__ void master_conv_body(const zr_mod& M, uint32_t t, ui
   uint32_t ilo = ic * IC, ihi = std::min(ilo + IC, n1);
   if (n2 > 0) {
     const uint32_t wlo = k0 + 1 > n2 ? k0 + 1 - n2 : 0;
-    const uint32_t whi = std::min(k0 + 64, n1);
+    const uint32_t whi = std::min(k0 + W, n1);
     ilo = std::max(ilo, wlo);
     ihi = std::min(ihi, whi);
   } else {
@@ -813,10 +823,12 @@ __device__ __forceinline__ void master_conv_body(const zr_mod& M, uint32_t t, ui
   if (ilo < ihi) {
     // round the i range up to whole groups of 8; the extra i are masked
     const uint32_t ihi8 = ilo + ((ihi - ilo + 7) & ~7u);
-    // window: R index j = k - i for k in [k0, k0+63], i in [ilo, ihi8): j in [k0 - ihi8 + 1, k0 + 63 - ilo]
+    // window: R index j = k - i for k in [k0, k0+W-1], i in [ilo, ihi8):
+    // j in [k0 - ihi8 + 1, k0 + W - 1 - ilo]; terms with j outside [0, n2)
+    // read zeros
     const int64_t jbase = (int64_t)k0 - (int64_t)ihi8 + 1;
-    const uint32_t wlen = 63 + (ihi8 - ilo);
-    for (uint32_t x = threadIdx.x & 63; x < wlen; x += 64) {
+    const uint32_t wlen = W - 1 + (ihi8 - ilo);
+    for (uint32_t x = threadIdx.x & (W - 1); x < wlen; x += W) {
       const int64_t j = jbase + x;
       win[x] = (j >= 0 && j < (int64_t)n2) ? Rc[j] : 0;
     }
@@ -943,8 +955,7 @@ namespace zr {
 
 // Host launcher of the product-tree convolution, compiled with the
 // latency-aware scheduler (kernels_ilp.hip).
-void launch_master_conv(dim3 grid, size_t shmem, hipStream_t s, const zr_mod& M, uint32_t t, uint32_t half,
-                        uint32_t IC, uint32_t nic, const uint64_t* cur, const uint4* limbs, uint64_t* part,
-                        uint64_t* nxt, uint4* limbs_nxt);
+void launch_master_conv(hipStream_t s, const zr_mod& M, uint32_t t, uint32_t half, uint32_t IC, uint32_t nic,
+                        const uint64_t* cur, const uint4* limbs, uint64_t* part, uint64_t* nxt, uint4* limbs_nxt);
 
 }  // namespace zr
