@@ -795,6 +795,7 @@ void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs_in, hipStr
     b.a.Sd = P.S;
     b.a.R = P.R;
     b.a.ldv = P.ldv;
+    for (uint32_t k = 0; k < 8; ++k) b.a.tw[k] = (uint8_t)(k < P.ntile ? P.RT : 0);  // uniform tiles
     b.a.mono = jobs[i].mono;
     b.a.VT = vt_base + b.vt_off;
     b.a.mono_p = A.alloc<uint64_t>(t);

@@ -31,7 +31,7 @@ namespace zr {
 // ============================================================================
 
 static uint32_t dots_waves_per_cu(uint32_t RT);
-static uint32_t dots_pc_blocks_per_cu(uint32_t RT, uint32_t ntile);
+static uint32_t dots_pc_blocks_per_cu(uint32_t RT, uint32_t ntile, bool uneven);
 
 // Variant of the dot-product pass: one wave per tile (0) or the
 // producer/consumer form (1, the default; systems of at most kPcMinR
@@ -55,6 +55,42 @@ constexpr uint64_t kSpartBytes = 4ull << 30;
 // partials, 3 S t words), at most (bytes); beyond it chunks grow longer, which
 // changes only the speed.
 constexpr uint64_t kChunkStateBytes = 4ull << 30;
+
+// Tile widths of the producer/consumer pass.  Waves 1..7 of a workgroup take
+// tiles 0..6 and sit on SIMD (1 + k) mod 4, and the CU's two workgroups are
+// placed alike: tile 3 shares SIMD 0 with the producer, tiles (0, 4), (1, 5)
+// and (2, 6) share SIMDs 1, 2 and 3, and the busiest SIMD paces the barriers.
+// With seven consumers the widths may differ from RT by one (at most
+// kPcUnevenMax) so that the loads, counted in consumer values per step (the
+// producer's step is about 4.4 values, 8.7 with its Horner sum), are as even
+// as the sum allows; R = 40: 7 for tile 3 and 6 + 5 on each other SIMD
+// against 6 everywhere (t = 10^5: 90.0 -> 87.9 ms, 5*10^5: 4% faster).
+static void pc_widths(uint32_t R, uint32_t ntile, uint32_t RT, bool dchain, uint32_t tw[8]) {
+  for (uint32_t k = 0; k < 8; ++k) tw[k] = k < ntile ? RT : 0;
+  if (ntile != kPcMaxTiles || RT < 2 || RT + 1 > kPcUnevenMax) return;
+  const double prod = dchain ? 4.4 : 8.7;
+  auto cost = [&](const uint32_t* w) {
+    double c = prod + w[3];
+    for (uint32_t k = 0; k < 3; ++k) c = std::max(c, (double)(w[k] + w[k + 4]));
+    return c;
+  };
+  uint32_t best[7], w[7];
+  for (uint32_t k = 0; k < 7; ++k) best[k] = tw[k];
+  double bc = cost(best);
+  uint32_t bsum = 7 * RT;
+  for (uint32_t code = 0; code < 2187; ++code) {  // 3^7 choices of RT - 1, RT, RT + 1
+    uint32_t x = code, sum = 0;
+    for (uint32_t k = 0; k < 7; ++k, x /= 3) sum += (w[k] = RT - 1 + x % 3);
+    if (sum < R) continue;
+    const double c = cost(w);
+    if (c < bc - 1e-9 || (c < bc + 1e-9 && sum < bsum)) {
+      bc = c;
+      bsum = sum;
+      for (uint32_t k = 0; k < 7; ++k) best[k] = w[k];
+    }
+  }
+  for (uint32_t k = 0; k < 7; ++k) tw[k] = best[k];
+}
 
 VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
   VsolvePlan P;
@@ -87,9 +123,35 @@ VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
   // 32-bit words per packed row: the producer/consumer pass reads only the
   // limbs (pc_ldv); the one-wave-per-tile pass also reads M_r, in 64-byte groups
   P.ldv = P.pc ? pc_ldv(P.RT) : (3 * P.RT + 2 + 15) & ~15u;
+  // delta from the chain pass instead of a Horner sum in the producer where the
+  // producer's SIMD sets the pace: seven consumers of at most seven values.
+  // At R = 40 (seven of six) the pass ran 12% faster without the producer's
+  // Horner (t = 5*10^5: 2.46 -> 2.15 s, for 0.26 s more chain pass); at R = 30
+  // (three of ten) and R = 56 (seven of eight) 1-2%, less than the chain pass
+  // adds.
+  P.dchain = P.pc && P.ntile == kPcMaxTiles && P.RT <= 7 ? 1 : 0;
+  pc_widths(P.Rg, P.ntile, P.RT, P.dchain, P.tw);
+  if (P.pc) {
+    // the uneven kernel carries the bodies of the neighbouring widths; where
+    // their registers cost a resident workgroup per CU, keep even tiles
+    // (R = 31 and 33, RT = 5: three workgroups per CU against two, and the
+    // uneven split ran 8-13% slower)
+    bool uneven = false;
+    for (uint32_t k = 0; k < P.ntile; ++k) uneven |= P.tw[k] != P.RT;
+    if (uneven && dots_pc_blocks_per_cu(P.RT, P.ntile, true) < dots_pc_blocks_per_cu(P.RT, P.ntile, false))
+      for (uint32_t k = 0; k < P.ntile; ++k) P.tw[k] = P.RT;
+  }
+  uint32_t row_words = 0;  // one step's packed rows over all tiles
+  if (P.pc)
+    for (uint32_t k = 0; k < P.ntile; ++k) row_words += pc_ldv(P.tw[k]);
+  else
+    row_words = P.ntile * P.ldv;
+  P.vt32 = (size_t)row_words * t;
   uint32_t S;
   if (P.pc) {
-    const uint32_t slots = std::max<uint32_t>(1, num_cus) * dots_pc_blocks_per_cu(P.RT, P.ntile);
+    bool uneven = false;
+    for (uint32_t k = 0; k < P.ntile; ++k) uneven |= P.tw[k] != P.RT;
+    const uint32_t slots = std::max<uint32_t>(1, num_cus) * dots_pc_blocks_per_cu(P.RT, P.ntile, uneven);
     const uint32_t S0 = std::max<uint32_t>(1, cdiv(4ull * slots, (uint64_t)row_blocks));
     // chunk state (chain values, start values, Horner partials: 3 S t words)
     // within kChunkStateBytes; partial sums (Sd R t words) within kSpartBytes,
@@ -107,7 +169,7 @@ VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
     // one whose launches waste the least in their last round of `slots` equal
     // workgroups, counting that every chunk but the last also costs a chain
     // pass of about 1/64 of its dot-product pass.
-    const uint64_t row_bytes = 4ull * P.ntile * P.ldv;
+    const uint64_t row_bytes = 4ull * row_words;
     const uint32_t l2_steps = (uint32_t)std::max<uint64_t>(64, kChunkRowBytes / row_bytes);
     const uint32_t s_lo = std::min(s_cap, std::max<uint32_t>(S0 - S0 / 4, cdiv(t, l2_steps)));
     const uint32_t s_hi = std::max<uint32_t>({32u, S0 + S0 / 4, s_lo + s_lo / 4});
@@ -134,13 +196,6 @@ VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
   P.L = std::max<uint32_t>(1, cdiv(t, S));
   P.S = std::max<uint32_t>(1, cdiv(t, P.L));
   P.Sd = P.S;
-  // delta from the chain pass instead of a Horner sum in the producer where the
-  // producer's SIMD sets the pace: seven consumers of at most seven values.
-  // At R = 40 (seven of six) the pass ran 12% faster without the producer's
-  // Horner (t = 5*10^5: 2.46 -> 2.15 s, for 0.26 s more chain pass); at R = 30
-  // (three of ten) and R = 56 (seven of eight) 1-2%, less than the chain pass
-  // adds.
-  P.dchain = P.pc && P.ntile == kPcMaxTiles && P.RT <= 7 ? 1 : 0;
   if (P.pc) {
     const uint32_t sd_max =
         (uint32_t)std::max<uint64_t>(1, kSpartBytes / (8ull * std::max<uint32_t>(P.Rg, 1) * std::max<uint32_t>(t, 1)));
@@ -149,10 +204,10 @@ VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
   return P;
 }
 
-// workspace layout (64-bit words): right-hand sides VT [ntile][t][ldv/2] |
+// workspace layout (64-bit words): right-hand sides VT (vt32 32-bit words: per tile [t][row]) |
 //                   mono_p [t] | Bc [S][t] | qstart [S][t] | mL [t] |
 //                   spart [Sd][Rg][t] | dpart [S][t] | winv [2t] | CL [t][6] (32-bit)
-static size_t vsolve_rhs_words(const VsolvePlan& P) { return (size_t)P.ntile * P.t * (P.ldv / 2); }
+static size_t vsolve_rhs_words(const VsolvePlan& P) { return (P.vt32 + 1) / 2; }
 
 size_t vsolve_workspace_words(const VsolvePlan& P) {
   const size_t t = P.t, S = P.S;
@@ -181,6 +236,21 @@ __global__ void k_pack(uint32_t t, uint32_t R, uint32_t RT, uint32_t ntile, uint
   }
 }
 
+// Packed rows of the producer/consumer tiles (blockIdx.y = tile), widths tw.
+__global__ void k_pack_pc(VsArgs a, const uint64_t* __restrict__ rhs, size_t ld_rhs, uint32_t* __restrict__ VT) {
+  const uint32_t tile = blockIdx.y;
+  uint32_t j0 = 0, off = 0;
+  for (uint32_t k = 0; k < tile; ++k) {
+    j0 += a.tw[k];
+    off += pc_ldv(a.tw[k]);
+  }
+  const uint32_t ldv = pc_ldv(a.tw[tile]);
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < (size_t)a.t * ldv)
+    VT[(size_t)off * a.t + idx] =
+        pack_word_pc((uint32_t)(idx / ldv), (uint32_t)(idx % ldv), a.R, a.tw[tile], j0, rhs, ld_rhs);
+}
+
 // Chain values B_c (WB, the chunks c < S-1) and partials D_c of m M'(m) (WD):
 // B and D for the chunks c < S-1 and D alone for the last one when delta
 // comes from this pass, else B alone.  One kernel per stream set, so that each
@@ -202,10 +272,10 @@ __global__ void __launch_bounds__(64) k_vs_dots(VsArgs a) {
 }
 
 // producer + one consumer wave per tile (64 * (1 + ntile) threads)
-template <int RT, bool HORNER>
+template <int RT, bool HORNER, bool UNEVEN>
 __global__ void __launch_bounds__(64 * (1 + kPcMaxTiles)) k_vs_dots_pc(VsArgs a, uint32_t ntile, uint32_t c0) {
   __shared__ uint64_t qbuf[2][kQB][64];
-  vs_dots_pc_body<RT, HORNER>(a, blockIdx.x, c0 + blockIdx.y, ntile, qbuf);
+  vs_dots_pc_body<RT, HORNER, UNEVEN>(a, blockIdx.x, c0 + blockIdx.y, ntile, qbuf);
 }
 
 __global__ void __launch_bounds__(kDeltaBlock) k_vs_delta(VsArgs a, const uint64_t* __restrict__ mLv,
@@ -234,35 +304,41 @@ static DotsKernel dots_kernel(uint32_t RT) {
 }
 
 typedef void (*DotsPcKernel)(VsArgs, uint32_t, uint32_t);
-template <int RT, bool H>
+template <int RT, bool H, bool U>
 static DotsPcKernel dots_pc_ptr() {
-  return k_vs_dots_pc<RT, H>;
+  return k_vs_dots_pc<RT, H, U>;
+}
+template <bool H, bool U>
+static DotsPcKernel dots_pc_pick(uint32_t RT) {
+  static const DotsPcKernel table[kPcRT + 1] = {
+      nullptr,                  dots_pc_ptr<1, H, U>(), dots_pc_ptr<2, H, U>(), dots_pc_ptr<3, H, U>(),
+      dots_pc_ptr<4, H, U>(),   dots_pc_ptr<5, H, U>(), dots_pc_ptr<6, H, U>(), dots_pc_ptr<7, H, U>(),
+      dots_pc_ptr<8, H, U>(),   dots_pc_ptr<9, H, U>(), dots_pc_ptr<10, H, U>()};
+  return RT >= 1 && RT <= kPcRT ? table[RT] : nullptr;
 }
 // the producer/consumer pass for RT values per consumer, with the producer's
-// Horner sum (horner) or without it (delta from the chain pass)
-static DotsPcKernel dots_pc_kernel(uint32_t RT, bool horner = true) {
-  static const DotsPcKernel table[2][kPcRT + 1] = {
-      {nullptr, dots_pc_ptr<1, false>(), dots_pc_ptr<2, false>(), dots_pc_ptr<3, false>(), dots_pc_ptr<4, false>(),
-       dots_pc_ptr<5, false>(), dots_pc_ptr<6, false>(), dots_pc_ptr<7, false>(), dots_pc_ptr<8, false>(),
-       dots_pc_ptr<9, false>(), dots_pc_ptr<10, false>()},
-      {nullptr, dots_pc_ptr<1, true>(), dots_pc_ptr<2, true>(), dots_pc_ptr<3, true>(), dots_pc_ptr<4, true>(),
-       dots_pc_ptr<5, true>(), dots_pc_ptr<6, true>(), dots_pc_ptr<7, true>(), dots_pc_ptr<8, true>(),
-       dots_pc_ptr<9, true>(), dots_pc_ptr<10, true>()}};
-  return RT >= 1 && RT <= kPcRT ? table[horner ? 1 : 0][RT] : nullptr;
+// Horner sum (horner) or without it (delta from the chain pass), with tiles of
+// RT - 1 to RT + 1 values (uneven) or all of RT
+static DotsPcKernel dots_pc_kernel(uint32_t RT, bool horner = true, bool uneven = false) {
+  return horner ? (uneven ? dots_pc_pick<true, true>(RT) : dots_pc_pick<true, false>(RT))
+                : (uneven ? dots_pc_pick<false, true>(RT) : dots_pc_pick<false, false>(RT));
 }
 
-// Workgroups of the producer/consumer pass resident per CU for ntile tiles.
-static uint32_t dots_pc_blocks_per_cu(uint32_t RT, uint32_t ntile) {
-  static int cache[kPcRT + 1][kPcMaxTiles + 1] = {{0}};
+// Workgroups of the producer/consumer pass resident per CU for ntile tiles
+// (uneven: the kernel with the bodies of the neighbouring widths).
+static uint32_t dots_pc_blocks_per_cu(uint32_t RT, uint32_t ntile, bool uneven) {
+  static int cache[2][kPcRT + 1][kPcMaxTiles + 1] = {{{0}}};
   if (RT < 1 || RT > kPcRT || ntile < 1 || ntile > kPcMaxTiles) return 2;
-  if (!cache[RT][ntile]) {
+  int& c = cache[uneven ? 1 : 0][RT][ntile];
+  if (!c) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, dots_pc_kernel(RT), 64 * (1 + ntile), 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, dots_pc_kernel(RT, true, uneven), 64 * (1 + ntile), 0) !=
+            hipSuccess ||
         nb <= 0)
       nb = 2;
-    cache[RT][ntile] = nb;
+    c = nb;
   }
-  return (uint32_t)cache[RT][ntile];
+  return (uint32_t)c;
 }
 
 static uint32_t dots_waves_per_cu(uint32_t RT) {
@@ -297,6 +373,7 @@ hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, co
   a.Sd = P.Sd;
   a.R = P.R;
   a.ldv = P.ldv;
+  for (uint32_t k = 0; k < 8; ++k) a.tw[k] = (uint8_t)P.tw[k];
   a.mono = mono;
   a.mono_p = mono_p;
   a.Mc = Mc;
@@ -316,9 +393,16 @@ hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, co
     const uint32_t Rg = P.R / P.ng + (g < P.R % P.ng ? 1 : 0);
     a.R = Rg;
     {
-      const size_t total = std::max<size_t>(P.ntile * t * P.ldv, t);  // 32-bit words
       TimedLaunch tl("vs_pack", s);
-      hipLaunchKernelGGL(k_pack, dim3(cdiv(total, 256)), dim3(256), 0, s, P.t, Rg, P.RT, P.ntile, P.ldv,
+      if (P.pc) {
+        uint32_t wmax = 0;
+        for (uint32_t k = 0; k < P.ntile; ++k) wmax = std::max(wmax, P.tw[k]);
+        hipLaunchKernelGGL(k_pack_pc, dim3(cdiv((size_t)t * pc_ldv(wmax), 256), P.ntile), dim3(256), 0, s, a,
+                           rhs + (size_t)r0 * ld_rhs, ld_rhs, (uint32_t*)VT);
+      }
+      // the one-wave-per-tile rows (ldv words with M_r), Shoup constants and chain limbs
+      const size_t total = std::max<size_t>(P.pc ? 0 : P.ntile * t * P.ldv, t);  // 32-bit words
+      hipLaunchKernelGGL(k_pack, dim3(cdiv(total, 256)), dim3(256), 0, s, P.t, Rg, P.RT, P.pc ? 0 : P.ntile, P.ldv,
                          rhs + (size_t)r0 * ld_rhs, ld_rhs, Mc, (uint32_t*)VT, mono, mono_p, CL, M);
     }
     if (g == 0) {
@@ -337,7 +421,9 @@ hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, co
       }
     }
     if (P.pc) {
-      DotsPcKernel kp = dots_pc_kernel(P.RT, !P.dchain);
+      bool uneven = false;
+      for (uint32_t k = 0; k < P.ntile; ++k) uneven |= P.tw[k] != P.RT;
+      DotsPcKernel kp = dots_pc_kernel(P.RT, !P.dchain, uneven);
       if (!kp) return hipErrorInvalidValue;
       // chunks in launches of Sd (one partial-sum slot each), in order
       for (uint32_t c0 = 0; c0 < P.S; c0 += P.Sd) {

@@ -23,6 +23,8 @@ struct VsolvePlan {
   uint32_t Sd;         // partial-sum slots per row and right-hand side (the chunks take them in turn)
   uint32_t ng, Rg;     // right-hand-side groups (one dot-product pass each) and the largest group's size
   uint32_t dchain;     // 1: delta_l from the chain pass (sum r M_r m^r), no Horner sum in the producer
+  uint32_t tw[8];      // producer/consumer pass: right-hand sides of each consumer's tile
+  size_t vt32;         // 32-bit words of the packed right-hand sides
 };
 VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus);
 // true when the producer/consumer pass is selected (solve variant 1, the default)

@@ -35,6 +35,9 @@ struct VsArgs {
   uint64_t* hpart;              // Horner partials per chunk (null: the dot-product pass runs no Horner)
   const uint32_t* CL = nullptr;  // limbs of M_r and r M_r for the chain pass (kChainW words per r)
   uint64_t* dpart = nullptr;      // D_c = sum over chunk c of r M_r m^(r - lo_c), per chunk and row
+  // producer/consumer pass: right-hand sides of consumer k's tile; tile k's
+  // rows (pc_ldv(tw[k]) words each) follow those of the tiles before it
+  uint8_t tw[8] = {};
 };
 
 __device__ __forceinline__ void chunk_range(uint32_t t, uint32_t L, uint32_t c, uint32_t& lo, uint32_t& hi) {
@@ -64,6 +67,17 @@ __device__ __forceinline__ uint32_t pack_word(size_t idx, uint32_t t, uint32_t R
     out = (uint32_t)(Mc[r] >> 32);
   }
   return out;
+}
+
+// Word w of packed row r of a producer/consumer tile of width tw whose first
+// right-hand side is j0: the three 22-bit limbs of v^(j0+jj)_{r+1} at words
+// 3jj..3jj+2, zero beyond (and for right-hand sides past R).
+__device__ __forceinline__ uint32_t pack_word_pc(uint32_t r, uint32_t w, uint32_t R, uint32_t tw, uint32_t j0,
+                                                 const uint64_t* __restrict__ rhs, size_t ld_rhs) {
+  if (w >= 3 * tw) return 0;
+  const uint32_t j = j0 + w / 3, limb = w % 3;
+  const uint64_t v = j < R ? rhs[(size_t)j * ld_rhs + r] : 0;
+  return (uint32_t)((v >> (22 * limb)) & (limb < 2 ? 0x3FFFFFu : 0xFFFFFFFFu));
 }
 
 // Shoup product x*w mod p in [0, 2p) for any 64-bit x (w < p, wp its Shoup
@@ -267,6 +281,9 @@ constexpr uint32_t kPcMaxTiles = 7;  // consumer waves per workgroup (at most)
 // nine (128 VGPRs) two fit (t = 10^5: 64 values ran at 14.5 TOP/s, 60 at 19.3).
 // More right-hand sides are solved in groups (vsolve).
 constexpr uint32_t kPcMaxR = 63;
+// Widest tile of an uneven split (pc_widths): nine values keep 128 VGPRs and
+// two 8-wave workgroups per CU.
+constexpr uint32_t kPcUnevenMax = 9;
 
 // Consumer waves per workgroup for R right-hand sides: at least
 // cdiv(R, kPcRT), rounded up so that the workgroup's 1 + ntile waves are a
@@ -505,13 +522,71 @@ __device__ __forceinline__ void vs_pc_step(const zr_mod& M, Acc6 (&acc)[RT], con
   q = qn;
 }
 
-// HORNER: the producer also sums h = q(m) over the chunk into hpart (the
-// batched solve); without it delta comes from the chain pass's D_c.
-template <int RT, bool HORNER>
-__device__ __forceinline__ void vs_dots_pc_body(const VsArgs& a, uint32_t rb, uint32_t c, uint32_t ntile,
-                                                uint64_t (*qbuf)[kQB][64]) {
+// Consumer of a tile of RT right-hand sides, j0 the first of them, whose
+// packed rows (pc_ldv(RT) words each) start at rows.
+template <int RT>
+__device__ __forceinline__ void vs_pc_consume(const VsArgs& a, uint32_t c, uint32_t lo, uint32_t hi, uint32_t nb,
+                                              bool live, uint32_t l, uint32_t lane, uint32_t j0,
+                                              const_as<uint32_t> rows, uint64_t (*qbuf)[kQB][64], const zr_mod& M) {
   constexpr uint32_t LDV = pc_ldv(RT);
   constexpr int K = (int)pc_tail(RT);
+  Acc6 acc[RT];
+#pragma unroll
+  for (int j = 0; j < RT; ++j) acc6_zero(acc[j]);
+  // two row buffers: while one feeds the products of step r the other receives
+  // row r-1, so each row's scalar loads have a whole step to arrive.  Blocks
+  // hold an even number of steps except the last, so steps go in pairs (no
+  // branch between a request and its use) and a last odd step, if any, runs
+  // alone.
+  uint32_t r = hi - 1;
+  uint32_t since = 0;
+  PcRow<K> b0, b1;
+  pc_load(b0, rows + (size_t)r * LDV);
+  for (uint32_t it = 0; it <= nb; ++it) {
+    if (it >= 1) {
+      const uint32_t b = it - 1;
+      const uint32_t s_end = min(kQB, hi - lo - b * kQB);
+      const uint64_t* qb = &qbuf[b & 1][0][lane];
+      uint64_t q = qb[0];
+      uint32_t s = 0;
+      for (; s + 2 <= s_end; s += 2) {
+        // the q of step s_end (past the block) is read from the last slot and not used
+        vs_pc_step<RT, K>(M, acc, b0, b1, q, qb + 64 * (s + 1), rows, r > lo ? r - 1 : r, since);
+        r = r > lo ? r - 1 : r;
+        vs_pc_step<RT, K>(M, acc, b1, b0, q, qb + 64 * min(s + 2, kQB - 1), rows, r > lo ? r - 1 : r, since);
+        r = r > lo ? r - 1 : r;
+      }
+      if (s < s_end) {
+        vs_pc_step<RT, K>(M, acc, b0, b1, q, qb, rows, r > lo ? r - 1 : r, since);
+        r = r > lo ? r - 1 : r;
+        b0 = b1;
+      }
+    }
+    __syncthreads();
+  }
+  if (live) {
+    // chunk c adds into partial-sum slot c mod Sd: the chunks of one launch
+    // take distinct slots, and chunks c >= Sd (later launches) add to what
+    // the earlier chunk of their slot left there
+    const uint32_t slot = c % a.Sd;
+#pragma unroll
+    for (int j = 0; j < RT; ++j)
+      if (j0 + j < a.R) {
+        uint64_t* dst = a.spart + ((size_t)slot * a.R + j0 + j) * a.t + l;
+        const uint64_t v = acc6_reduce(M, acc[j]);
+        *dst = c >= a.Sd ? zr_add(M, v, *dst) : v;
+      }
+  }
+}
+
+
+// HORNER: the producer also sums h = q(m) over the chunk into hpart (the
+// batched solve); without it delta comes from the chain pass's D_c.  UNEVEN:
+// tiles may be one value narrower or wider than RT (the bodies for those
+// widths are compiled in, which costs registers; off, every tile is RT wide).
+template <int RT, bool HORNER, bool UNEVEN = false>
+__device__ __forceinline__ void vs_dots_pc_body(const VsArgs& a, uint32_t rb, uint32_t c, uint32_t ntile,
+                                                uint64_t (*qbuf)[kQB][64]) {
   // the wave index is uniform within a wave: say so, so that each role's code
   // is compiled as uniform control flow (scalar loads, scalar loop counters)
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -560,60 +635,33 @@ __device__ __forceinline__ void vs_dots_pc_body(const VsArgs& a, uint32_t rb, ui
     if (HORNER && live) a.hpart[(size_t)c * a.t + l] = h >= M.p ? h - M.p : h;
     return;
   }
-  // consumer of tile wave - 1
+  // consumer of tile wave - 1, of width a.tw[tile]: RT, or (uneven tiles,
+  // pc_widths) one less or one more
   const uint32_t tile = wave - 1;
   if (tile >= ntile) {
     for (uint32_t it = 0; it <= nb; ++it) __syncthreads();
     return;
   }
-  Acc6 acc[RT];
-#pragma unroll
-  for (int j = 0; j < RT; ++j) acc6_zero(acc[j]);
-  const_as<uint32_t> rows = (const_as<uint32_t>)((const uint32_t*)a.VT + (size_t)tile * a.t * LDV);
-  // two row buffers: while one feeds the products of step r the other receives
-  // row r-1, so each row's scalar loads have a whole step to arrive.  Blocks
-  // hold an even number of steps except the last, so steps go in pairs (no
-  // branch between a request and its use) and a last odd step, if any, runs
-  // alone.
-  uint32_t r = hi - 1;
-  uint32_t since = 0;
-  PcRow<K> b0, b1;
-  pc_load(b0, rows + (size_t)r * LDV);
-  for (uint32_t it = 0; it <= nb; ++it) {
-    if (it >= 1) {
-      const uint32_t b = it - 1;
-      const uint32_t s_end = min(kQB, hi - lo - b * kQB);
-      const uint64_t* qb = &qbuf[b & 1][0][lane];
-      uint64_t q = qb[0];
-      uint32_t s = 0;
-      for (; s + 2 <= s_end; s += 2) {
-        // the q of step s_end (past the block) is read from the last slot and not used
-        vs_pc_step<RT, K>(M, acc, b0, b1, q, qb + 64 * (s + 1), rows, r > lo ? r - 1 : r, since);
-        r = r > lo ? r - 1 : r;
-        vs_pc_step<RT, K>(M, acc, b1, b0, q, qb + 64 * min(s + 2, kQB - 1), rows, r > lo ? r - 1 : r, since);
-        r = r > lo ? r - 1 : r;
-      }
-      if (s < s_end) {
-        vs_pc_step<RT, K>(M, acc, b0, b1, q, qb, rows, r > lo ? r - 1 : r, since);
-        r = r > lo ? r - 1 : r;
-        b0 = b1;
-      }
+  uint32_t j0 = 0, off = 0;
+  for (uint32_t k = 0; k < tile; ++k) {
+    j0 += a.tw[k];
+    off += pc_ldv(a.tw[k]);
+  }
+  [[maybe_unused]] const uint32_t w = a.tw[tile];
+  const_as<uint32_t> rows = (const_as<uint32_t>)((const uint32_t*)a.VT + (size_t)off * a.t);
+  if constexpr (UNEVEN && RT > 1) {
+    if (w == RT - 1) {
+      vs_pc_consume<RT - 1>(a, c, lo, hi, nb, live, l, lane, j0, rows, qbuf, M);
+      return;
     }
-    __syncthreads();
   }
-  if (live) {
-    // chunk c adds into partial-sum slot c mod Sd: the chunks of one launch
-    // take distinct slots, and chunks c >= Sd (later launches) add to what
-    // the earlier chunk of their slot left there
-    const uint32_t j0 = tile * RT, slot = c % a.Sd;
-#pragma unroll
-    for (int j = 0; j < RT; ++j)
-      if (j0 + j < a.R) {
-        uint64_t* dst = a.spart + ((size_t)slot * a.R + j0 + j) * a.t + l;
-        const uint64_t v = acc6_reduce(M, acc[j]);
-        *dst = c >= a.Sd ? zr_add(M, v, *dst) : v;
-      }
+  if constexpr (UNEVEN && RT + 1 <= kPcUnevenMax) {
+    if (w == RT + 1) {
+      vs_pc_consume<RT + 1>(a, c, lo, hi, nb, live, l, lane, j0, rows, qbuf, M);
+      return;
+    }
   }
+  vs_pc_consume<RT>(a, c, lo, hi, nb, live, l, lane, j0, rows, qbuf, M);
 }
 
 // Inverses of the values w of a block's kDeltaBlock threads by Montgomery's

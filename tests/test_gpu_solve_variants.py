@@ -3,8 +3,9 @@ both forms of its dot-product pass on the integer vector ALU: one wave per
 right-hand-side tile, and the producer/consumer form.  Each solve goes
 through zr_vandermonde_solve and is compared with the oracle's solve bit for
 bit; sizes straddle the row blocks (64), the chunks and the right-hand-side
-tiles (1, 2, 15, 16, 17, 30, 33, 40) and the right-hand-side groups (64, 70,
-100, 127), and the values include the edges of the field and small primes."""
+tiles (1, 2, 15, 16, 17, 30, 33, 40), the uneven tile splits (31 to 50) and the
+right-hand-side groups (64, 70, 100, 127), and the values include the edges of
+the field and small primes."""
 import random
 import sys
 
@@ -48,7 +49,8 @@ def _system(p, t, R, seed):
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("t,R", [(1, 1), (2, 3), (15, 1), (16, 2), (17, 5), (63, 10), (64, 16), (65, 17),
                                  (200, 30), (1000, 33), (777, 40), (1100, 15), (2500, 30), (300, 64),
-                                 (640, 70), (1000, 100), (129, 127), (100, 33), (250, 40)])
+                                 (640, 70), (1000, 100), (129, 127), (100, 33), (250, 40), (900, 36),
+                                 (700, 41), (600, 45), (500, 50)])
 def test_solve_matches_oracle(zr, variant, t, R):
     p = synth.make_prime()
     m, rhs = _system(p, t, R, 1)
