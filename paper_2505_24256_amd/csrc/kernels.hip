@@ -239,16 +239,20 @@ __global__ void k_pack(uint32_t t, uint32_t R, uint32_t RT, uint32_t ntile, uint
 // Packed rows of the producer/consumer tiles (blockIdx.y = tile), widths tw.
 __global__ void k_pack_pc(VsArgs a, const uint64_t* __restrict__ rhs, size_t ld_rhs, uint32_t* __restrict__ VT) {
   const uint32_t tile = blockIdx.y;
-  uint32_t j0 = 0, off = 0;
-  for (uint32_t k = 0; k < tile; ++k) {
-    j0 += a.tw[k];
-    off += pc_ldv(a.tw[k]);
+  uint32_t j0 = 0, off = 0, w = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kPcMaxTiles; ++k) {
+    if (k < tile) {
+      j0 += a.tw[k];
+      off += pc_ldv(a.tw[k]);
+    }
+    if (k == tile) w = a.tw[k];
   }
-  const uint32_t ldv = pc_ldv(a.tw[tile]);
+  const uint32_t ldv = pc_ldv(w);
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < (size_t)a.t * ldv)
     VT[(size_t)off * a.t + idx] =
-        pack_word_pc((uint32_t)(idx / ldv), (uint32_t)(idx % ldv), a.R, a.tw[tile], j0, rhs, ld_rhs);
+        pack_word_pc((uint32_t)(idx / ldv), (uint32_t)(idx % ldv), a.R, w, j0, rhs, ld_rhs);
 }
 
 // Chain values B_c (WB, the chunks c < S-1) and partials D_c of m M'(m) (WD):

@@ -642,12 +642,18 @@ __device__ __forceinline__ void vs_dots_pc_body(const VsArgs& a, uint32_t rb, ui
     for (uint32_t it = 0; it <= nb; ++it) __syncthreads();
     return;
   }
-  uint32_t j0 = 0, off = 0;
-  for (uint32_t k = 0; k < tile; ++k) {
-    j0 += a.tw[k];
-    off += pc_ldv(a.tw[k]);
+  // the tile's first right-hand side, row offset and width (unrolled, so that
+  // tw is only read at fixed indices: a copy of the arguments indexed at run
+  // time would go to scratch memory)
+  uint32_t j0 = 0, off = 0, w = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kPcMaxTiles; ++k) {
+    if (k < tile) {
+      j0 += a.tw[k];
+      off += pc_ldv(a.tw[k]);
+    }
+    if (k == tile) w = a.tw[k];
   }
-  [[maybe_unused]] const uint32_t w = a.tw[tile];
   const_as<uint32_t> rows = (const_as<uint32_t>)((const uint32_t*)a.VT + (size_t)off * a.t);
   if constexpr (UNEVEN && RT > 1) {
     if (w == RT - 1) {
