@@ -286,9 +286,9 @@ zr_status zr_vandermonde_solve(uint64_t p, uint32_t t, uint32_t R, const uint64_
  * a kernel, and every workspace word is written before it is read, so nothing
  * left by an earlier call is used.
  *   Size limit: a system whose workspace does not fit the array (at R = 40,
- *   t above about 60 000; the dot-product pass runs in fewer chunks before
- *   that) returns ZR_EINVAL before any device work, with the reason in
- *   zr_last_error().
+ *   t above about 45 000; before that the chunks share fewer partial-sum
+ *   slots, then the dot-product pass runs in fewer chunks) returns ZR_EINVAL
+ *   before any device work, with the reason in zr_last_error().
  *   Every call on one GPU uses that GPU's one array: calls that overlap on the
  *   same GPU (other streams, other threads) race and must be serialised by the
  *   caller.  The first call on a device looks the array's address up once. */

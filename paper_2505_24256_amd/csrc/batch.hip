@@ -226,6 +226,20 @@ __global__ void __launch_bounds__(64) k_b_master_conv(zr_mod M, uint32_t half, u
                    b.limbs[r ^ 1], win);
 }
 
+// the same for factors of degree half >= 128 with four waves (256
+// coefficients) sharing each window
+__global__ void __launch_bounds__(256) k_b_master_conv4(zr_mod M, uint32_t half, uint32_t IC, uint32_t r, uint32_t n,
+                                                        const uint32_t* __restrict__ prefix,
+                                                        const BMaster* __restrict__ sys) {
+  extern __shared__ uint64_t win[];  // 256 + IC + 8 words
+  const uint32_t s = seg_find(prefix, n, blockIdx.x);
+  const BMaster& b = sys[s];
+  const uint32_t nic = cdiv(half, IC);
+  const uint32_t lb = blockIdx.x - prefix[s], nrb = cdiv(b.t, 256);
+  master_conv_body<4>(M, b.t, half, IC, nic, (lb % nrb) * 256, lb / nrb, b.buf[r], b.limbs[r], b.part, b.t,
+                      b.buf[r ^ 1], b.limbs[r ^ 1], win);
+}
+
 __global__ void k_b_master_sum(zr_mod M, uint32_t half, uint32_t nic, uint32_t r, uint32_t n,
                                const uint32_t* __restrict__ prefix, const BMaster* __restrict__ sys) {
   const uint32_t s = seg_find(prefix, n, blockIdx.x);
@@ -825,7 +839,7 @@ void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs_in, hipStr
     const uint32_t nic = cdiv(h, level_ic[lv]);
     for (uint32_t i = 0; i < n; ++i) {
       const uint32_t t = jobs[i].t;
-      c.add(t > h ? (size_t)cdiv(t, 64) * nic : 0);
+      c.add(t > h ? (size_t)cdiv(t, h >= 128 ? 256 : 64) * nic : 0);  // workgroups of 4 or 1 waves
       su.add(t > h && nic > 1 ? cdiv(t, 256) : 0);
     }
     conv.push_back(c);
@@ -924,7 +938,10 @@ void batched_solve(const zr_mod& M, const std::vector<SolveJob>& jobs_in, hipStr
     uint32_t r = 0;
     for (size_t lv = 0; lv < conv.size(); ++lv, r ^= 1) {
       const uint32_t h = 64u << lv, IC = level_ic[lv];
-      if (conv[lv].total())
+      if (conv[lv].total() && h >= 128)
+        hipLaunchKernelGGL(k_b_master_conv4, dim3(conv[lv].total()), dim3(256), (256 + IC + 8) * 8, ls, M, h, IC, r,
+                           n, P32(o_conv[lv]), d_bm);
+      else if (conv[lv].total())
         hipLaunchKernelGGL(k_b_master_conv, dim3(conv[lv].total()), dim3(64), (64 + IC + 8) * 8, ls, M, h, IC, r, n,
                            P32(o_conv[lv]), d_bm);
       if (csum[lv].total())
