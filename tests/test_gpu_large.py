@@ -85,8 +85,9 @@ def test_config3_full(zr, cfg3):
 
 def test_headline_solve_size_multiply_back(zr):
     """One system at the size and launch configuration the benchmark times
-    (t = 5*10^5 unknowns, 40 right-hand sides: seven consumer tiles of six,
-    chunks of at most 4096 steps within the partial-sum budget).  The oracle
+    (t = 5*10^5 unknowns, 40 right-hand sides: seven consumer tiles of 5, 5,
+    5, 7, 6, 6 and 6 values, 138 chunks in six launches that share 23
+    partial-sum slots, denominators from the chain pass).  The oracle
     cannot build the master polynomial at this size in test time, so the
     check is the defining property at sampled equations: every right-hand
     side j satisfies sum_l a_l m_l^i = v_i at three values of i (the oracle's
