@@ -104,6 +104,9 @@ def microbench(zr):
         out[kind] = {"ms": round(ms, 4), "Gops_per_s": round(ops / ms / 1e6, 1)}
     ms, nbytes = zr.microbench("copy", blocks=8192, nbytes=2 << 30)
     out["copy"] = {"ms": round(ms, 4), "GB_per_s": round(nbytes / ms / 1e6, 1), "bytes": nbytes}
+    for kind in ("lds_read", "lds_bcast"):  # bytes delivered to lanes
+        ms, nbytes = zr.microbench(kind, blocks=2048, iters=4096)
+        out[kind] = {"ms": round(ms, 4), "GB_per_s": round(nbytes / ms / 1e6, 1)}
     return out
 
 

@@ -8,7 +8,8 @@
  *   below).  The first launch warms up; the second is timed with HIP events
  *   on `stream`.  *ms = duration of the timed launch, *ops = number of probed
  *   operations it executed (lanes x iters x 8), or bytes moved for COPY
- *   (reads + writes of a `bytes`-long buffer, 16-byte vector accesses).
+ *   (reads + writes of a `bytes`-long buffer, 16-byte vector accesses), or
+ *   bytes delivered to lanes for the LDS kinds (lanes x iters x 8 x 8).
  *   Returns 0, -1 for an unknown kind, -7 if allocation fails, -8 on a HIP error.
  *   Allocates and frees its own device memory.
  */
@@ -27,7 +28,9 @@ enum {
   ZR_MB_ADD_U32 = 3,     /* v_add_u32 (full-rate reference) */
   ZR_MB_MAC192 = 4,      /* the library's 64x64 -> 192-bit multiply-accumulate */
   ZR_MB_SHOUP = 5,       /* the library's Shoup product by a fixed multiplier */
-  ZR_MB_COPY = 6         /* streaming device-to-device copy */
+  ZR_MB_COPY = 6,        /* streaming device-to-device copy */
+  ZR_MB_LDS_READ = 7,    /* 8-byte LDS reads at lane-consecutive addresses */
+  ZR_MB_LDS_BCAST = 8    /* 8-byte LDS reads, one address per wave (broadcast) */
 };
 
 int zr_microbench(int kind, uint32_t blocks, uint32_t iters, uint64_t bytes, hipStream_t stream, double* ms,

@@ -32,7 +32,8 @@ EXPORTS = [
     "zr_vandermonde_solve", "zr_vandermonde_solve_noalloc", "zippel_reconstruct_rational", "zr_qpoly_free",
     "zr_skeleton_solve", "zippel_reconstruct_multi", "zippel_reconstruct_adaptive",
 ]
-MB_KINDS = {"mad_u64_u32": 0, "mul_lo_u32": 1, "mul_hi_u32": 2, "add_u32": 3, "mac192": 4, "shoup": 5, "copy": 6}
+MB_KINDS = {"mad_u64_u32": 0, "mul_lo_u32": 1, "mul_hi_u32": 2, "add_u32": 3, "mac192": 4, "shoup": 5, "copy": 6,
+            "lds_read": 7, "lds_bcast": 8}
 
 
 class ZippelError(RuntimeError):

@@ -92,6 +92,13 @@ static void pc_widths(uint32_t R, uint32_t ntile, uint32_t RT, bool dchain, uint
   for (uint32_t k = 0; k < 7; ++k) tw[k] = best[k];
 }
 
+// true when the plan's producer/consumer tiles are not all RT wide
+static bool plan_uneven(const VsolvePlan& P) {
+  bool u = false;
+  for (uint32_t k = 0; k < P.ntile && k < 8; ++k) u |= P.tw[k] != P.RT;
+  return u;
+}
+
 VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
   VsolvePlan P;
   P.t = t;
@@ -136,9 +143,7 @@ VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
     // their registers cost a resident workgroup per CU, keep even tiles
     // (R = 31 and 33, RT = 5: three workgroups per CU against two, and the
     // uneven split ran 8-13% slower)
-    bool uneven = false;
-    for (uint32_t k = 0; k < P.ntile; ++k) uneven |= P.tw[k] != P.RT;
-    if (uneven && dots_pc_blocks_per_cu(P.RT, P.ntile, true) < dots_pc_blocks_per_cu(P.RT, P.ntile, false))
+    if (plan_uneven(P) && dots_pc_blocks_per_cu(P.RT, P.ntile, true) < dots_pc_blocks_per_cu(P.RT, P.ntile, false))
       for (uint32_t k = 0; k < P.ntile; ++k) P.tw[k] = P.RT;
   }
   uint32_t row_words = 0;  // one step's packed rows over all tiles
@@ -149,11 +154,9 @@ VsolvePlan vsolve_plan(uint32_t t, uint32_t R, uint32_t num_cus) {
   P.vt32 = (size_t)row_words * t;
   uint32_t S;
   if (P.pc) {
-    bool uneven = false;
-    for (uint32_t k = 0; k < P.ntile; ++k) uneven |= P.tw[k] != P.RT;
-    const uint32_t slots = std::max<uint32_t>(1, num_cus) * dots_pc_blocks_per_cu(P.RT, P.ntile, uneven);
+    const uint32_t slots = std::max<uint32_t>(1, num_cus) * dots_pc_blocks_per_cu(P.RT, P.ntile, plan_uneven(P));
     const uint32_t S0 = std::max<uint32_t>(1, cdiv(4ull * slots, (uint64_t)row_blocks));
-    // chunk state (chain values, start values, Horner partials: 3 S t words)
+    // chunk state (chain values, start values, partials of delta: 3 S t words)
     // within kChunkStateBytes; partial sums (Sd R t words) within kSpartBytes,
     // the chunks taking Sd slots in turn, one launch per Sd chunks
     const uint32_t s_cap = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(4096, kChunkStateBytes / (24ull * t)));
@@ -425,9 +428,7 @@ hipError_t vsolve(const zr_mod& M, const VsolvePlan& P, const uint64_t* mono, co
       }
     }
     if (P.pc) {
-      bool uneven = false;
-      for (uint32_t k = 0; k < P.ntile; ++k) uneven |= P.tw[k] != P.RT;
-      DotsPcKernel kp = dots_pc_kernel(P.RT, !P.dchain, uneven);
+      DotsPcKernel kp = dots_pc_kernel(P.RT, !P.dchain, plan_uneven(P));
       if (!kp) return hipErrorInvalidValue;
       // chunks in launches of Sd (one partial-sum slot each), in order
       for (uint32_t c0 = 0; c0 < P.S; c0 += P.Sd) {

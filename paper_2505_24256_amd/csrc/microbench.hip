@@ -1,7 +1,7 @@
 // Throughput microbenchmarks for the roofline of the integer path on gfx950:
 // independent streams of one VALU instruction per lane, at full occupancy, plus
-// the library's 64x64 multiply-accumulate and Shoup product, and a streaming
-// copy for the HBM bandwidth and the traffic-counter calibration.
+// the library's 64x64 multiply-accumulate and Shoup product, LDS reads, and a
+// streaming copy for the HBM bandwidth and the traffic-counter calibration.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -119,6 +119,31 @@ __global__ void __launch_bounds__(256) k_shoup(zr_mod M, uint32_t iters, uint32_
   if (r == 0x123456789ull) sink[0] = r;
 }
 
+// LDS reads of 8 bytes per lane: at lane-consecutive addresses (the
+// consumers' read of q) or, with BCAST, at one address per wave (a broadcast).
+// The reads are volatile so that every one is issued; the addresses move with
+// the iteration and stay inside the 16 KB array.
+template <bool BCAST>
+__global__ void __launch_bounds__(256) k_lds_read(uint32_t iters, uint32_t seed, uint64_t* sink) {
+  __shared__ uint64_t buf[2048];
+  for (uint32_t i = threadIdx.x; i < 2048; i += blockDim.x) buf[i] = (uint64_t)seed * (i + 1);
+  __syncthreads();
+  typedef const volatile __attribute__((address_space(3))) uint64_t lds_u64;
+  lds_u64* lds = (lds_u64*)buf;  // LDS reads proper, not flat ones
+  const uint32_t lane = BCAST ? 0 : (threadIdx.x & 63), wave = threadIdx.x >> 6;
+  uint64_t x[kChains];
+#pragma unroll
+  for (int i = 0; i < kChains; ++i) x[i] = 0;
+  for (uint32_t it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < kChains; ++i) x[i] += lds[(lane + 64 * ((wave + i + it) & 31)) & 2047];
+  }
+  uint64_t r = 0;
+#pragma unroll
+  for (int i = 0; i < kChains; ++i) r ^= x[i];
+  if (r == 0x123456789ull) sink[0] = r;
+}
+
 __global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
@@ -172,6 +197,12 @@ extern "C" int zr_microbench(int kind, uint32_t blocks, uint32_t iters, uint64_t
         case ZR_MB_COPY:
           hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(threads), 0, s, (const uint4*)a, (uint4*)b, bytes / 16);
           break;
+        case ZR_MB_LDS_READ:
+          hipLaunchKernelGGL(k_lds_read<false>, dim3(blocks), dim3(threads), 0, s, iters, 7u, sink);
+          break;
+        case ZR_MB_LDS_BCAST:
+          hipLaunchKernelGGL(k_lds_read<true>, dim3(blocks), dim3(threads), 0, s, iters, 7u, sink);
+          break;
         default:
           rc = -1;
       }
@@ -183,6 +214,8 @@ extern "C" int zr_microbench(int kind, uint32_t blocks, uint32_t iters, uint64_t
   float ms = 0;
   if (!rc) (void)hipEventElapsedTime(&ms, e0, e1);
   if (kind == ZR_MB_COPY) ops = 2.0 * (double)(bytes / 16) * 16;
+  else if (kind == ZR_MB_LDS_READ || kind == ZR_MB_LDS_BCAST)
+    ops = (double)blocks * threads * (double)iters * kChains * 8;  // bytes delivered to lanes
   else ops = (double)blocks * threads * (double)iters * kChains;
   if (ms_out) *ms_out = ms;
   if (ops_out) *ops_out = ops;
