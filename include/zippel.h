@@ -170,8 +170,9 @@ zr_status zippel_balanced_reconstruct(const zr_params* params, zr_blackbox_fn bb
 
 /* Polynomial Zippel without known degree bounds (Introduction: a result is
  * accepted when further probes reproduce it).  Stage k samples x_k at its
- * anchor and then at the schedule's nodes in batches of 16 (the batches
- * change how many samples are drawn, not the result); after
+ * anchor and then at the schedule's nodes in batches (the first as wide as
+ * the previous stage's degree plus `confirm`, at most 63, then 16 at a time;
+ * the batches change how many samples are drawn, not the result); after
  * each node m it forms, for every term, the divided difference of order m of
  * the term's values at x_0..x_m, and stops at the first m whose last
  * `confirm` orders vanish for all terms.  The stage's degree is

@@ -52,8 +52,11 @@ namespace {
 // Nodes per black-box call and solve: 16 at a time.  Each solve reruns the
 // synthetic-division chain (about eight right-hand sides' worth of work), so
 // fewer, wider solves cost less; batches of 16 keep the samples drawn beyond
-// a stage's stop below 16 and take the producer/consumer pass.
-constexpr uint32_t kBatchFirst = 16, kBatchMax = 16;
+// a stage's stop below 16 and take the producer/consumer pass.  A stage's
+// first batch is as wide as the previous stage's degree plus the confirming
+// orders (at most kBatchGuess, one producer/consumer pass), so that a
+// polynomial of even degrees needs one solve per stage.
+constexpr uint32_t kBatchFirst = 16, kBatchMax = 16, kBatchGuess = 63;
 
 // w[m][i] = 1 / prod_{j<=m, j!=i} (x_i - x_j) for m < X.size(), i <= m.
 std::vector<uint64_t> ddiff_weights(const zr_mod& M, const std::vector<uint64_t>& X) {
@@ -123,6 +126,7 @@ void reconstruct_adaptive(const zr_params* params, uint32_t confirm, zr_blackbox
   check(fill_u64(cur.coef, 1 % P.p, 1, s));
   check(fill_u64((uint64_t*)cur.exps, 0, (n * 2 + 7) / 8, s));
   int32_t* h = host_scratch();
+  uint32_t prevD = 0;  // degree found in the previous stage
   for (uint32_t k = 1; k <= n; ++k) {
     const uint32_t kv = k - 1, t = cur.t, maxm = need[kv];  // orders 1..maxm
     const std::vector<uint64_t> X = P.node_list(kv, maxm + 1);
@@ -148,7 +152,8 @@ void reconstruct_adaptive(const zr_params* params, uint32_t confirm, zr_blackbox
         check(master_poly(P.M, t, cur.mono, Mc, tmp, s));
         C.mulmods += (uint64_t)t * (t - 1) / 2;
       }
-      uint32_t m = 0, run = 0, stop = 0, batch = kBatchFirst;
+      uint32_t m = 0, run = 0, stop = 0;
+      uint32_t batch = k >= 2 ? std::min(std::max(kBatchFirst, prevD + confirm), kBatchGuess) : kBatchFirst;
       std::vector<uint32_t> nz(maxm + 1);
       while (!stop) {
         if (m == maxm) {
@@ -156,7 +161,7 @@ void reconstruct_adaptive(const zr_params* params, uint32_t confirm, zr_blackbox
           throw Error(ZR_EPROBE);
         }
         const uint32_t B = std::min(batch, maxm - m);
-        batch = std::min(2 * batch, kBatchMax);
+        batch = kBatchMax;
         uint64_t* rows = vals + (size_t)(m + 1) * t;
         call_bb(bb, ctx, P, k, k == 1 ? 1 : t, P.y.data(), X.data() + m + 1, B, rows, s);
         if (k >= 2 && t) {
@@ -184,6 +189,7 @@ void reconstruct_adaptive(const zr_params* params, uint32_t confirm, zr_blackbox
       }
       const uint32_t D = stop - confirm;
       if (deg_found) deg_found[kv] = D;
+      prevD = D;
       const LiftConsts L = lift_consts(P, kv, X, D + 1, A, s);
       lift_stage(P, kv, cur, vals, D + 1, L.W, L.ypow, *kp, nxt, s, d_status);
     }
