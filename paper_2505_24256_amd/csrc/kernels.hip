@@ -65,9 +65,7 @@ constexpr uint64_t kChunkStateBytes = 4ull << 30;
 // producer's step is about 4.4 values, 8.7 with its Horner sum), are as even
 // as the sum allows; R = 40: 7 for tile 3 and 6 + 5 on each other SIMD
 // against 6 everywhere (t = 10^5: 90.0 -> 87.9 ms, 5*10^5: 4% faster).
-static void pc_widths(uint32_t R, uint32_t ntile, uint32_t RT, bool dchain, uint32_t tw[8]) {
-  for (uint32_t k = 0; k < 8; ++k) tw[k] = k < ntile ? RT : 0;
-  if (ntile != kPcMaxTiles || RT < 2 || RT + 1 > kPcUnevenMax) return;
+static void pc_widths_search(uint32_t R, uint32_t RT, bool dchain, uint32_t tw[7]) {
   const double prod = dchain ? 4.4 : 8.7;
   auto cost = [&](const uint32_t* w) {
     double c = prod + w[3];
@@ -75,7 +73,7 @@ static void pc_widths(uint32_t R, uint32_t ntile, uint32_t RT, bool dchain, uint
     return c;
   };
   uint32_t best[7], w[7];
-  for (uint32_t k = 0; k < 7; ++k) best[k] = tw[k];
+  for (uint32_t k = 0; k < 7; ++k) best[k] = RT;
   double bc = cost(best);
   uint32_t bsum = 7 * RT;
   for (uint32_t code = 0; code < 2187; ++code) {  // 3^7 choices of RT - 1, RT, RT + 1
@@ -90,6 +88,30 @@ static void pc_widths(uint32_t R, uint32_t ntile, uint32_t RT, bool dchain, uint
     }
   }
   for (uint32_t k = 0; k < 7; ++k) tw[k] = best[k];
+}
+
+static void pc_widths(uint32_t R, uint32_t ntile, uint32_t RT, bool dchain, uint32_t tw[8]) {
+  for (uint32_t k = 0; k < 8; ++k) tw[k] = k < ntile ? RT : 0;
+  if (ntile != kPcMaxTiles || RT < 2 || RT + 1 > kPcUnevenMax || R > kPcMaxR) return;
+  // the search once per (R, dchain), at the first plan (static initialisation
+  // is thread-safe)
+  struct Table {
+    uint8_t w[kPcMaxR + 1][2][7];
+  };
+  static const Table T = [] {
+    Table t{};
+    for (uint32_t r = 1; r <= kPcMaxR; ++r)
+      for (uint32_t d = 0; d < 2; ++d) {
+        const uint32_t rt = cdiv(r, kPcMaxTiles);
+        uint32_t x[7];
+        for (uint32_t k = 0; k < 7; ++k) x[k] = rt;
+        if (rt >= 2 && rt + 1 <= kPcUnevenMax) pc_widths_search(r, rt, d != 0, x);
+        for (uint32_t k = 0; k < 7; ++k) t.w[r][d][k] = (uint8_t)x[k];
+      }
+    return t;
+  }();
+  if (cdiv(R, kPcMaxTiles) != RT) return;
+  for (uint32_t k = 0; k < 7; ++k) tw[k] = T.w[R][dchain ? 1 : 0][k];
 }
 
 // true when the plan's producer/consumer tiles are not all RT wide
