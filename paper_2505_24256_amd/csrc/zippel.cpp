@@ -785,7 +785,7 @@ zr_status zr_recorder_create(zr_recorder** rec, zr_blackbox_fn inner, void* inne
 
 void zr_recorder_destroy(zr_recorder* rec) {
   if (!rec) return;
-  for (auto& r : rec->recs) hipFree(r.d);
+  for (auto& r : rec->recs) (void)hipFree(r.d);  // nothing to report to: the handle is gone either way
   delete rec;
 }
 
