@@ -51,7 +51,7 @@ MUL32_PER_MULMOD = 4
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by the copy-probe calibration
 # (profiles/k_vs_dots_pc_n8_d40_t5e5_hbm_counters.md).  Valid only for the
 # kernel sources the counters were taken on (None: not measured for them).
-DOTS_TRAFFIC = {"sources_sha16": "cd2a9586f3258194", "bytes_per_launch": 7711215705}
+DOTS_TRAFFIC = {"sources_sha16": "e1ba96d12974ac06", "bytes_per_launch": 7713177498}
 
 HEADLINE_STAGE = 8  # the last variable of the n = 8 workload
 

@@ -64,11 +64,14 @@ constexpr uint64_t kChunkStateBytes = 16ull << 30;
 // and (2, 6) share SIMDs 1, 2 and 3, and the busiest SIMD paces the barriers.
 // With seven consumers the widths may differ from RT by one (at most
 // kPcUnevenMax) so that the loads, counted in consumer values per step (the
-// producer's step is about 4.4 values, 8.7 with its Horner sum), are as even
-// as the sum allows; R = 40: 7 for tile 3 and 6 + 5 on each other SIMD
-// against 6 everywhere (t = 10^5: 90.0 -> 87.9 ms, 5*10^5: 4% faster).
+// producer's step, about 22 vector instructions, is worth about 3.6 values,
+// 7.1 with its Horner sum), are as even as the sum allows; R = 40: 7 for
+// tile 3 and 6 + 5 on each other SIMD against 6 everywhere (t = 10^5: 90.0 ->
+// 87.9 ms, 5*10^5: 4% faster).  With the producer's step counted as 4.4 and
+// 8.7 values (its cost before its Shoup product lost five instructions), R = 37
+// took 6, 6, 5, 5, 5, 5, 5 and ran 1.7% slower than with 5, 5, 5, 7, 5, 5, 5.
 static void pc_widths_search(uint32_t R, uint32_t RT, bool dchain, uint32_t tw[7]) {
-  const double prod = dchain ? 4.4 : 8.7;
+  const double prod = dchain ? 3.6 : 7.1;
   auto cost = [&](const uint32_t* w) {
     double c = prod + w[3];
     for (uint32_t k = 0; k < 3; ++k) c = std::max(c, (double)(w[k] + w[k + 4]));

@@ -82,15 +82,15 @@ __device__ __forceinline__ uint32_t pack_word_pc(uint32_t r, uint32_t w, uint32_
 
 // Shoup product x*w mod p in [0, 2p) for any 64-bit x (w < p, wp its Shoup
 // quotient floor(w 2^64 / p)), for the producer's chain.  The high half of
-// x*wp takes four 32x32->64 multiplies; the one carry out of the middle
-// column is found by a compare, so no partial sum has to be zero-extended.
+// x*wp takes four 32x32->64 multiplies; the middle column is summed as a
+// 65-bit value, so its carry travels through add-with-carry instructions
+// (a compare and select for it cost three more vector instructions a step).
 __device__ __forceinline__ uint64_t shoup_lazy_v(uint64_t x, uint64_t w, uint64_t wp, uint64_t p) {
   const uint32_t x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32);
   const uint32_t w0 = (uint32_t)wp, w1 = (uint32_t)(wp >> 32);
-  const uint64_t b = (uint64_t)x1 * w0 + __umulhi(x0, w0);  // < 2^64
-  const uint64_t s = (uint64_t)x0 * w1 + b;                  // mod 2^64
-  const uint64_t cy = s < b ? (1ull << 32) : 0;              // carry out of bit 64
-  const uint64_t qh = (uint64_t)x1 * w1 + (s >> 32) + cy;    // high half of x*wp
+  const uint64_t b = (uint64_t)x1 * w0 + __umulhi(x0, w0);                          // < 2^64
+  const unsigned __int128 s = (unsigned __int128)((uint64_t)x0 * w1) + b;            // < 2^65
+  const uint64_t qh = (uint64_t)x1 * w1 + (uint64_t)(s >> 32);                       // high half of x*wp
   return x * w - qh * p;
 }
 
@@ -604,6 +604,11 @@ __device__ __forceinline__ void vs_dots_pc_body(const VsArgs& a, uint32_t rb, ui
     uint64_t h = 0;
     const_as<uint64_t> Mc = (const_as<uint64_t>)a.Mc;
     const uint64_t p2 = 2 * M.p;  // below 2^64 since p < 2^63
+    // a copy of 2p kept in vector registers: the select that adds it back
+    // would otherwise move it from scalar registers at every step (one scalar
+    // operand per vector instruction besides the lane mask)
+    uint64_t p2v = p2;
+    asm volatile("" : "+v"(p2v));
     uint32_t r = hi;  // the next step is r - 1
     uint64_t cur[8], nxt[8];
 #pragma unroll
@@ -621,8 +626,8 @@ __device__ __forceinline__ void vs_dots_pc_body(const VsArgs& a, uint32_t rb, ui
               // q and h kept in [0, 2p); the consumers' column sums take any
               // q below 2^64.  cur[u] - 2p is uniform (scalar unit).
               qbuf[it & 1][g8 * 8 + u][lane] = q;
-              if (HORNER) h = add_lazy2p(shoup_lazy_v(h, m, mp, M.p), q - p2, p2);
-              q = add_lazy2p(shoup_lazy_v(q, m, mp, M.p), cur[u] - p2, p2);
+              if (HORNER) h = add_lazy2p(shoup_lazy_v(h, m, mp, M.p), q - p2, p2v);
+              q = add_lazy2p(shoup_lazy_v(q, m, mp, M.p), cur[u] - p2, p2v);
             }
           }
           r = rn;
