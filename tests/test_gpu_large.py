@@ -110,3 +110,24 @@ def test_headline_solve_size_multiply_back(zr):
     bad = a[7].copy()
     bad[123_456] = (int(bad[123_456]) + 1) % p
     assert int(oracle.vandermonde_apply(p, m, bad, 77, 1)[0]) != int(rhs[7, 76])
+
+
+def test_solve_t1e6_multiply_back(zr):
+    """One system of t = 10^6 unknowns and 40 right-hand sides, above the
+    benchmark's size: 286 chunks in 22 launches that share 13 partial-sum
+    slots (the chunk count set by the L2 size of the packed rows, not by the
+    bound on the per-chunk state).  Checked by the defining property at
+    sampled equations, as for t = 5*10^5."""
+    p = synth.make_prime()
+    t, R = 1_000_000, 40
+    g = synth.SplitMix64(654)
+    m = g.uniform_block(1, p, t)
+    assert len(np.unique(m)) == t
+    rhs = g.uniform_block(0, p, t * R).reshape(R, t)
+    _note(f"solve t={t} R={R}")
+    a, st = zr.vandermonde_solve(p, m, rhs)
+    assert st == 0
+    _note("multiply-back at sampled equations")
+    for j in (0, 13, R - 1):
+        for i in (1, 1 + (j * 77_777 + 11) % t, t):
+            assert int(oracle.vandermonde_apply(p, m, a[j], i, 1)[0]) == int(rhs[j, i - 1]), (j, i)
