@@ -183,6 +183,13 @@ def batched_vs_plain(zr, synth, args, stream):
         k, ms = zr.timing_get(name)
         if k:
             breakdown[name] = {"launches": k, "ms_total": round(ms, 2)}
+    # the persistent dot-product passes of the timed run against their work
+    # (dot products and chains of q of every system, 4 32-bit multiplies each)
+    solve_kernel = None
+    if "batch_dots" in breakdown and breakdown["batch_dots"]["ms_total"] > 0:
+        tops = 4.0 * _dots_work(cnt) / (breakdown["batch_dots"]["ms_total"] * 1e-3) / 1e12
+        solve_kernel = {"kernel": "k_b_dots_pc", "achieved_TOPs": round(tops, 3),
+                        "frac_of_derived_peak": round(tops / MUL32_PEAK_TOPS, 4)}
     _progress(f"batched {times}, with graphs {tg:.3f}; plain one at a time")
     # plain, one at a time, same recordings
     for r in recs:
@@ -212,6 +219,7 @@ def batched_vs_plain(zr, synth, args, stream):
         "speedup": round(tp / tb, 3), "mulmods": cnt["mulmods"], "bit_exact": bool(exact),
         "band_choices": tuned, "setup_seconds": {"generate": round(t_gen, 1), "record": round(t_rec, 1)},
         "timed_run": {"seconds": round(t_timed, 3), "per_kernel": breakdown},
+        "solve_kernel": solve_kernel,
     }
 
 
