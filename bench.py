@@ -228,8 +228,9 @@ def served(zr, synth, args, stream):
     t_N and t_D log-uniform in 10..5*10^3, Q(0) = 1.  Each request's samples are
     recorded once (its run alone, device black box), then replayed for every
     timed pass: one at a time; all submitted at once (saturated throughput);
-    and Poisson arrivals at 0.7 x the saturated rate, admitted by device
-    footprint and advanced in continuous batches (latency p50/p99)."""
+    and Poisson arrivals at 0.7 x the saturated rate and at a fixed rate,
+    admitted by device footprint and advanced in continuous batches (latency
+    p50/p99)."""
     import math
     import torch
     g = synth.SplitMix64(5005)
@@ -304,7 +305,14 @@ def served(zr, synth, args, stream):
         t += -math.log(1.0 - g.next() / 2.0 ** 64) / rate
         arr.append(t)
     span, lat, st, same = serve(arr)
-    _progress(f"served: saturated {sat:.1f} req/s, Poisson at {rate:.1f} req/s")
+    # Poisson arrivals at a fixed rate as well, so that latencies compare
+    # across builds whose saturated rates differ
+    arr_f, t = [], 0.0
+    for _ in ws:
+        t += -math.log(1.0 - g.next() / 2.0 ** 64) / args.serve_fixed_rate
+        arr_f.append(t)
+    span_f, lat_f, st_f, same_f = serve(arr_f)
+    _progress(f"served: saturated {sat:.1f} req/s, Poisson at {rate:.1f} and {args.serve_fixed_rate:.0f} req/s")
     return {
         "workload": f"{len(ws)} rational requests P/Q, n=5, total degree<=20, t_N and t_D log-uniform in 10..5*10^3, "
                     "Q(0)=1; Poisson arrivals at 0.7 x the saturated throughput",
@@ -314,9 +322,13 @@ def served(zr, synth, args, stream):
                                    "p99": round(float(np.percentile(lat, 99)) * 1e3, 2)},
                     "steps": st["steps"], "peak_active": st["peak_active"],
                     "peak_footprint_bytes": st["peak_footprint"]},
+        "poisson_fixed_rate": {"rate_per_s": args.serve_fixed_rate, "requests_per_s": round(len(ws) / span_f, 2),
+                               "latency_ms": {"p50": round(statistics.median(lat_f) * 1e3, 2),
+                                              "p99": round(float(np.percentile(lat_f, 99)) * 1e3, 2)},
+                               "steps": st_f["steps"], "peak_active": st_f["peak_active"]},
         "one_at_a_time": {"requests_per_s": round(len(ws) / sum(lat1), 2), "latency_ms": {
             "p50": round(statistics.median(lat1) * 1e3, 2), "p99": round(float(np.percentile(lat1, 99)) * 1e3, 2)}},
-        "identical_to_alone": bool(same and same_sat),
+        "identical_to_alone": bool(same and same_sat and same_f),
         "slots": args.serve_slots, "budget_gib": args.serve_budget_gib,
     }
 
@@ -631,6 +643,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-slots", type=int, default=256)
     ap.add_argument("--serve-budget-gib", type=int, default=16)
+    ap.add_argument("--serve-fixed-rate", type=float, default=1000.0,
+                    help="arrival rate (requests/s) of the served leg's fixed-rate Poisson pass")
     ap.add_argument("--solve-variant", default="producer_consumer", choices=["waves", "producer_consumer"],
                     help="dot-product pass of the one-system solve")
     args = ap.parse_args()

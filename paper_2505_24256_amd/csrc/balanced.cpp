@@ -33,20 +33,32 @@ static std::vector<int32_t> d2h_i32(const int32_t* d, size_t n, hipStream_t s) {
 }
 
 // Build a univariate skeleton (in variable 0) from host coefficients c[0..deg].
-void host_skeleton(const Params& P, const std::vector<uint64_t>& c, DevArena& keep, Skeleton& S,
-                          hipStream_t s) {
+// Host arrays of the stage-1 skeleton with coefficients c (c_r of x_1^r):
+// the nonzero r in order, exponents in the variable-0 row of the SoA layout,
+// monomial values y_1^r.  Returns the term count.
+uint32_t stage1_skeleton_host(const Params& P, const std::vector<uint64_t>& c, std::vector<uint16_t>& exps,
+                              std::vector<uint64_t>& coef, std::vector<uint64_t>& mono) {
   std::vector<uint32_t> idx;
   for (uint32_t r = 0; r < c.size(); ++r)
     if (c[r]) idx.push_back(r);
   const uint32_t t = (uint32_t)idx.size();
-  S.alloc(keep, P.nvars, t);
-  std::vector<uint16_t> exps((size_t)P.nvars * std::max<uint32_t>(t, 1), 0);
-  std::vector<uint64_t> coef(std::max<uint32_t>(t, 1)), mono(std::max<uint32_t>(t, 1));
+  exps.assign((size_t)P.nvars * std::max<uint32_t>(t, 1), 0);
+  coef.assign(std::max<uint32_t>(t, 1), 0);
+  mono.assign(std::max<uint32_t>(t, 1), 0);
   for (uint32_t l = 0; l < t; ++l) {
-    exps[l] = (uint16_t)idx[l];  // variable 0 row of the SoA layout
+    exps[l] = (uint16_t)idx[l];
     coef[l] = c[idx[l]];
     mono[l] = zr_pow(P.M, P.y[0], idx[l]);
   }
+  return t;
+}
+
+void host_skeleton(const Params& P, const std::vector<uint64_t>& c, DevArena& keep, Skeleton& S,
+                          hipStream_t s) {
+  std::vector<uint16_t> exps;
+  std::vector<uint64_t> coef, mono;
+  const uint32_t t = stage1_skeleton_host(P, c, exps, coef, mono);
+  S.alloc(keep, P.nvars, t);
   if (t) {
     h2d(S.exps, exps.data(), (size_t)P.nvars * t * 2, s);
     h2d(S.coef, coef.data(), (size_t)t * 8, s);

@@ -106,6 +106,8 @@ void upload_start(const Params& P, const StageConsts& K, DevArena& keep, Skeleto
 void check_slices(const std::vector<int32_t>& st, const std::vector<int32_t>& dA, const std::vector<int32_t>& dB,
                   uint32_t bn, uint32_t bd, int32_t& rhoN, int32_t& rhoD);
 void host_skeleton(const Params& P, const std::vector<uint64_t>& c, DevArena& keep, Skeleton& S, hipStream_t s);
+uint32_t stage1_skeleton_host(const Params& P, const std::vector<uint64_t>& c, std::vector<uint16_t>& exps,
+                              std::vector<uint64_t>& coef, std::vector<uint64_t>& mono);
 void balanced_stage1(const Params& P, zr_blackbox_fn bb, void* ctx, DevArena& keep, Skeleton& SN, Skeleton& SD,
                      hipStream_t s);
 void balanced_finish(const Params& P, zr_blackbox_fn bb, void* ctx, Skeleton& SN, Skeleton& SD, hipStream_t s,

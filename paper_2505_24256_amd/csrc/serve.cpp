@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdlib.h>
+#include <string.h>
 
 #include <algorithm>
 #include <deque>
@@ -94,8 +95,11 @@ struct Server {
   zr_server_stats stats{};
   int32_t* hbuf = nullptr;  // pinned read-back buffer
   size_t hcap = 0;
+  void* dbuf = nullptr;  // pinned read-back buffer of finishing requests
+  size_t dcap = 0;
   ~Server() {
     if (hbuf) (void)hipHostFree(hbuf);
+    if (dbuf) (void)hipHostFree(dbuf);
     for (Request* r : pending) delete r;
     for (Request* r : active) delete r;
     for (auto& kv : done) {
@@ -108,21 +112,230 @@ struct Server {
 
 namespace {
 
-void finish(Server& S, Request& r) {
-  if (r.status == ZR_OK) {
-    try {
-      if (r.balanced) {
-        balanced_finish(*r.P, r.bb, r.ctx, r.SN, r.SD, S.s, &r.num, &r.den);
-      } else {
-        if (r.P->last == r.P->nvars && r.P->nprobes) check_probes(*r.P, r.bb, r.ctx, r.SN, nullptr, S.s);
-        download(r.SN, S.s, &r.num);
+// Device parts of finishing the requests that ended at a step, batched over
+// them: the constant term of each balanced denominator (zero when that
+// skeleton has no constant monomial; skeletons are in lexicographic order, so
+// it can only be the first term), then the scaling of each result by one
+// constant.
+struct ConstTermJob {
+  const uint16_t* exps;  // SoA [nvars][t]
+  const uint64_t* coef;
+  uint32_t t, nvars;
+  uint64_t* out;
+};
+
+__global__ void k_const_terms(uint32_t n, const ConstTermJob* __restrict__ jobs) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const ConstTermJob& j = jobs[i];
+  bool zero = j.t > 0;
+  for (uint32_t v = 0; v < j.nvars; ++v) zero = zero && j.exps[(size_t)v * j.t] == 0;
+  *j.out = zero ? j.coef[0] : 0;
+}
+
+struct ScaleJob {
+  uint64_t* v;
+  uint64_t n;
+  uint64_t c, cp;  // the factor and its Shoup quotient
+};
+
+// one workgroup per job
+__global__ void k_scale_jobs(zr_mod M, const ScaleJob* __restrict__ jobs) {
+  const ScaleJob& j = jobs[blockIdx.x];
+  for (uint64_t i = threadIdx.x; i < j.n; i += blockDim.x) j.v[i] = zr_shoup(M, j.v[i], j.c, j.cp);
+}
+
+// Host memory for one step's read-backs, pinned, grown as needed.
+void* pinned(Server& S, size_t bytes) {
+  if (S.dcap < bytes) {
+    if (S.dbuf) check(hipHostFree(S.dbuf));
+    S.dbuf = nullptr;
+    S.dcap = 0;
+    const size_t n = std::max<size_t>(bytes, 1 << 20);
+    check(hipHostMalloc(&S.dbuf, n, hipHostMallocDefault));
+    S.dcap = n;
+  }
+  return S.dbuf;
+}
+
+// The results of every request that ended at this step (its last stage done,
+// or failed).  Per request this is what the one-request paths do after their
+// last stage (balanced_finish, check_probes, download), with the same
+// black-box calls in the same order, but the device work of all requests is
+// enqueued together and read back in three host synchronisations per step
+// instead of up to nine per request.
+void finish_batch(Server& S, const std::vector<Request*>& ended) {
+  hipStream_t s = S.s;
+  DevArena A(s);
+  auto fail = [](Request& r, int32_t code) {
+    zr_poly_free(&r.num);
+    zr_poly_free(&r.den);
+    r.status = code;
+  };
+  std::vector<Request*> ok;
+  for (Request* r : ended)
+    if (r->status == ZR_OK) ok.push_back(r);
+  // ---- normalisation of complete balanced results: D(0) = 1
+  std::vector<Request*> norm;
+  for (Request* r : ok)
+    if (r->balanced && r->P->last == r->P->nvars) norm.push_back(r);
+  if (!norm.empty()) {
+    uint64_t* d_c0 = A.alloc<uint64_t>(norm.size());
+    std::vector<ConstTermJob> cj;
+    for (size_t q = 0; q < norm.size(); ++q) cj.push_back(ConstTermJob{norm[q]->SD.exps, norm[q]->SD.coef,
+                                                                       norm[q]->SD.t, norm[q]->SD.nvars, d_c0 + q});
+    Blob b;
+    const size_t o = b.add(cj);
+    char* d = b.upload(A, s);
+    hipLaunchKernelGGL(k_const_terms, dim3(((uint32_t)cj.size() + 63) / 64), dim3(64), 0, s, (uint32_t)cj.size(),
+                       (const ConstTermJob*)(d + o));
+    check(hipGetLastError());
+    uint64_t* c0 = (uint64_t*)pinned(S, norm.size() * 8);
+    check(hipMemcpyAsync(c0, d_c0, norm.size() * 8, hipMemcpyDeviceToHost, s));
+    check(hipStreamSynchronize(s));
+    std::vector<ScaleJob> sc;
+    for (size_t q = 0; q < norm.size(); ++q) {
+      Request& r = *norm[q];
+      if (c0[q] == 0) {
+        fail(r, ZR_ENORM);
+        continue;
       }
-    } catch (const Error& e) {
-      zr_poly_free(&r.num);
-      zr_poly_free(&r.den);
-      r.status = e.code;
+      const uint64_t ci = zr_inv(S.M, c0[q]), cip = zr_shoup_pre(S.M, ci);
+      if (r.SN.t) sc.push_back(ScaleJob{r.SN.coef, r.SN.t, ci, cip});
+      if (r.SD.t) sc.push_back(ScaleJob{r.SD.coef, r.SD.t, ci, cip});
+    }
+    if (!sc.empty()) {
+      Blob sb;
+      const size_t so = sb.add(sc);
+      char* ds = sb.upload(A, s);
+      hipLaunchKernelGGL(k_scale_jobs, dim3((uint32_t)sc.size()), dim3(256), 0, s, S.M, (const ScaleJob*)(ds + so));
+      check(hipGetLastError());
     }
   }
+  // ---- probes: black-box values and the results' values at the probe points
+  struct ProbeSet {
+    Request* r;
+    size_t off;  // first of 3 np result words
+  };
+  std::vector<ProbeSet> ps;
+  size_t pwords = 0;
+  for (Request* r : ok)
+    if (r->status == ZR_OK && r->P->last == r->P->nvars && r->P->nprobes) {
+      ps.push_back(ProbeSet{r, pwords});
+      pwords += 3 * (size_t)r->P->nprobes;
+    }
+  std::vector<uint64_t> pres;
+  if (!ps.empty()) {
+    uint64_t* d_res = A.alloc<uint64_t>(pwords);
+    check(fill_u64(d_res, 0, pwords, s));
+    for (ProbeSet& e : ps) {
+      Request& r = *e.r;
+      const Params& P = *r.P;
+      const Skeleton* D = r.balanced ? &r.SD : nullptr;
+      const uint32_t np = P.nprobes, nv = P.nvars;
+      uint32_t ld = 1;
+      for (uint32_t v = 0; v < nv; ++v) ld = std::max(ld, std::max(P.deg[v], D ? P.deg_den[v] : 0u) + 1);
+      std::vector<uint64_t> tab((size_t)np * nv * ld, 0);
+      for (uint32_t q = 0; q < np; ++q)
+        for (uint32_t v = 0; v < nv; ++v) {
+          uint64_t acc = 1 % P.p;
+          for (uint32_t d = 0; d < ld; ++d) {
+            tab[((size_t)q * nv + v) * ld + d] = acc;
+            acc = zr_mul(P.M, acc, P.probes[(size_t)q * nv + v]);
+          }
+        }
+      Blob tb;
+      const size_t to = tb.add(tab);
+      const uint64_t* d_tab = (const uint64_t*)(tb.upload(A, s) + to);
+      uint64_t* d_part = A.alloc<uint64_t>(2 * (size_t)np * kPolyEvalBlocks);
+      uint64_t* res = d_res + e.off;
+      try {
+        for (uint32_t q = 0; q < np; ++q) {
+          const uint64_t* pt = P.probes.data() + (size_t)q * nv;
+          call_bb(r.bb, r.ctx, P, nv, 1, pt, pt + (nv - 1), 1, res + q, s);
+          const uint64_t* tq = d_tab + (size_t)q * nv * ld;
+          uint64_t* pq = d_part + (size_t)2 * q * kPolyEvalBlocks;
+          if (r.SN.t)
+            check(poly_eval_point(P.M, r.SN.t, nv, r.SN.exps, r.SN.t, r.SN.coef, tq, ld, res + np + q, pq, s));
+          if (D && D->t)
+            check(poly_eval_point(P.M, D->t, nv, D->exps, D->t, D->coef, tq, ld, res + 2 * np + q,
+                                  pq + kPolyEvalBlocks, s));
+        }
+      } catch (const Error& x) {
+        fail(r, x.code);
+      }
+    }
+    uint64_t* h = (uint64_t*)pinned(S, pwords * 8);
+    check(hipMemcpyAsync(h, d_res, pwords * 8, hipMemcpyDeviceToHost, s));
+    check(hipStreamSynchronize(s));
+    for (ProbeSet& e : ps) {
+      Request& r = *e.r;
+      if (r.status != ZR_OK) continue;
+      const uint32_t np = r.P->nprobes;
+      const uint64_t* res = h + e.off;
+      for (uint32_t q = 0; q < np; ++q) {
+        const uint64_t f = res[q], nvl = res[np + q];
+        if (r.balanced ? nvl != zr_mul(r.P->M, f, res[2 * np + q]) : nvl != f) {
+          fail(r, ZR_EPROBE);
+          break;
+        }
+      }
+    }
+  }
+  // ---- results: every skeleton gathered into one buffer, one read-back
+  struct Out {
+    const Skeleton* S;
+    zr_poly* dst;
+    Request* r;
+    size_t eoff, coff;  // bytes into the gathered buffer
+  };
+  std::vector<Out> outs;
+  size_t bytes = 0;
+  auto align8 = [](size_t x) { return (x + 7) & ~(size_t)7; };
+  for (Request* r : ok) {
+    if (r->status != ZR_OK) continue;
+    outs.push_back(Out{&r->SN, &r->num, r, 0, 0});
+    if (r->balanced) outs.push_back(Out{&r->SD, &r->den, r, 0, 0});
+  }
+  if (outs.empty()) return;
+  std::vector<CopyJob> cp;
+  for (Out& o : outs) {
+    o.eoff = bytes;
+    bytes = align8(bytes + (size_t)o.S->t * o.S->nvars * 2);
+    o.coff = bytes;
+    bytes += (size_t)o.S->t * 8;
+  }
+  char* d_all = (char*)A.alloc<uint64_t>(std::max<size_t>(bytes / 8, 1));
+  for (Out& o : outs) {
+    cp.push_back(CopyJob{o.S->exps, d_all + o.eoff, (size_t)o.S->t * o.S->nvars * 2});
+    cp.push_back(CopyJob{o.S->coef, d_all + o.coff, (size_t)o.S->t * 8});
+  }
+  batched_copy(cp, s);
+  char* h = (char*)pinned(S, std::max<size_t>(bytes, 8));
+  check(hipMemcpyAsync(h, d_all, std::max<size_t>(bytes, 8), hipMemcpyDeviceToHost, s));
+  check(hipStreamSynchronize(s));
+  for (Out& o : outs) {
+    Request& r = *o.r;
+    if (r.status != ZR_OK) continue;
+    const uint32_t t = o.S->t, nv = o.S->nvars;
+    zr_poly* out = o.dst;
+    out->nvars = nv;
+    out->nterms = t;
+    out->exps = (uint16_t*)malloc(sizeof(uint16_t) * std::max<size_t>((size_t)t * nv, 1));
+    out->coeffs = (uint64_t*)malloc(sizeof(uint64_t) * std::max<uint32_t>(t, 1));
+    if (!out->exps || !out->coeffs) {
+      fail(r, ZR_ENOMEM);
+      continue;
+    }
+    const uint16_t* soa = (const uint16_t*)(h + o.eoff);
+    for (uint32_t l = 0; l < t; ++l)
+      for (uint32_t v = 0; v < nv; ++v) out->exps[(size_t)l * nv + v] = soa[(size_t)v * t + l];
+    if (t) memcpy(out->coeffs, h + o.coff, (size_t)t * 8);
+  }
+}
+
+// Bookkeeping of a request that ended: its slot, status word and footprint.
+void retire(Server& S, Request& r) {
   r.finished = true;
   r.finished_step = S.steps;
   r.arena.reset();
@@ -136,7 +349,108 @@ void finish(Server& S, Request& r) {
   if (r.status != ZR_OK) S.stats.failed += 1;
 }
 
-// One stage for every active request (stage r.k + 1).
+// Stage 1 of the balanced requests admitted at this step, all in one pass:
+// each request's samples on x_1 (its own black-box call), one Thiele launch
+// over all of them, one read-back of their degrees, statuses and coefficients,
+// and one upload of the new skeletons, which are copied into each request's
+// own arena.  Per request the arithmetic is that of balanced_stage1, which
+// takes three host synchronisations and two uploads per request instead.
+void stage1_batch(Server& S, const std::vector<Request*>& fresh, DevArena& A) {
+  hipStream_t s = S.s;
+  const size_t nf = fresh.size();
+  std::vector<uint32_t> n1(nf);
+  std::vector<std::vector<uint64_t>> X(nf);
+  std::vector<size_t> xo(nf), co(nf);
+  Blob xb;
+  size_t cwords = 0;
+  for (size_t q = 0; q < nf; ++q) {
+    const Params& P = *fresh[q]->P;
+    n1[q] = P.nnodes[0] + 1;
+    X[q] = P.node_list(0, n1[q]);
+    xo[q] = xb.add(X[q]);
+    co[q] = cwords;  // A then B, n1 + 1 coefficients each
+    cwords += 2 * ((size_t)n1[q] + 1);
+  }
+  char* dx = xb.upload(A, s);
+  uint64_t* coef = A.alloc<uint64_t>(std::max<size_t>(cwords, 1));
+  int32_t* flags = A.alloc<int32_t>(3 * nf);
+  std::vector<ThieleJob> tj;
+  std::vector<size_t> jq;  // fresh index of each job
+  for (size_t q = 0; q < nf; ++q) {
+    Request& r = *fresh[q];
+    uint64_t* F = A.alloc<uint64_t>(n1[q]);
+    const size_t sw = thiele_scratch_words(1, n1[q]);
+    uint64_t* scr = sw ? A.alloc<uint64_t>(sw) : nullptr;
+    try {
+      call_bb(r.bb, r.ctx, *r.P, 1, 1, r.P->y.data(), X[q].data(), n1[q], F, s);
+    } catch (const Error& e) {
+      r.status = e.code;
+      continue;
+    }
+    tj.push_back(ThieleJob{1, n1[q], (const uint64_t*)(dx + xo[q]), F, coef + co[q], coef + co[q] + n1[q] + 1,
+                           flags + 3 * q, flags + 3 * q + 1, flags + 3 * q + 2, scr});
+    jq.push_back(q);
+  }
+  if (tj.empty()) return;
+  {
+    uint32_t max_nk = 0;
+    for (const ThieleJob& j : tj) max_nk = std::max(max_nk, j.nk);
+    const uint32_t per = thiele_slices_per_block(max_nk);
+    std::vector<uint32_t> tprefix{0};
+    for (const ThieleJob& j : tj) tprefix.push_back(tprefix.back() + (j.T + per - 1) / per);
+    Blob tb;
+    const size_t oj = tb.add(tj), op = tb.add(tprefix);
+    char* dt = tb.upload(A, s);
+    check(thiele_slices_batch(S.M, (uint32_t)tj.size(), (const uint32_t*)(dt + op), tprefix.back(), max_nk,
+                              (const ThieleJob*)(dt + oj), s));
+  }
+  std::vector<int32_t> hf(3 * nf);
+  std::vector<uint64_t> hc(std::max<size_t>(cwords, 1));
+  check(hipMemcpyAsync(hf.data(), flags, hf.size() * 4, hipMemcpyDeviceToHost, s));
+  d2h_sync(hc.data(), coef, hc.size() * 8, s);
+  // the skeletons of every request, uploaded together
+  Blob sb;
+  struct Put {
+    size_t off;
+    void* dst;
+    size_t bytes;
+  };
+  std::vector<Put> puts;
+  auto put = [&](const Params& P, const std::vector<uint64_t>& c, DevArena& keep, Skeleton& Sk) {
+    std::vector<uint16_t> e;
+    std::vector<uint64_t> cf, mo;
+    const uint32_t t = stage1_skeleton_host(P, c, e, cf, mo);
+    Sk.alloc(keep, P.nvars, t);
+    if (!t) return;
+    puts.push_back(Put{sb.add(e.data(), (size_t)P.nvars * t), Sk.exps, (size_t)P.nvars * t * 2});
+    puts.push_back(Put{sb.add(cf.data(), t), Sk.coef, (size_t)t * 8});
+    puts.push_back(Put{sb.add(mo.data(), t), Sk.mono, (size_t)t * 8});
+  };
+  for (size_t q : jq) {
+    Request& r = *fresh[q];
+    const Params& P = *r.P;
+    int32_t rn, rd;
+    try {
+      check_slices({hf[3 * q + 2]}, {hf[3 * q]}, {hf[3 * q + 1]}, P.deg[0], P.deg_den[0], rn, rd);
+    } catch (const Error& e) {
+      r.status = e.code;
+      continue;
+    }
+    const uint64_t* ca = hc.data() + co[q];
+    const uint64_t* cb = ca + n1[q] + 1;
+    r.arena = std::make_shared<DevArena>(s);
+    put(P, std::vector<uint64_t>(ca, ca + rn + 1), *r.arena, r.SN);
+    put(P, std::vector<uint64_t>(cb, cb + rd + 1), *r.arena, r.SD);
+    r.k = 1;
+  }
+  if (!puts.empty()) {
+    char* ds = sb.upload(A, s);
+    std::vector<CopyJob> cp;
+    for (const Put& u : puts) cp.push_back(CopyJob{ds + u.off, u.dst, u.bytes});
+    batched_copy(cp, s);
+  }
+}
+
 void advance(Server& S) {
   const zr_mod& M = S.M;
   hipStream_t s = S.s;
@@ -147,17 +461,9 @@ void advance(Server& S) {
   // ---- balanced requests at stage 1: univariate Thiele (small, per request);
   // they take part in the batched stages from the next step on
   std::vector<Request*> fresh;
-  for (Request* r : act) {
-    if (!r->balanced || r->k != 0) continue;
-    try {
-      r->arena = std::make_shared<DevArena>(s);
-      balanced_stage1(*r->P, r->bb, r->ctx, *r->arena, r->SN, r->SD, s);
-      r->k = 1;
-    } catch (const Error& e) {
-      r->status = e.code;
-    }
-    fresh.push_back(r);
-  }
+  for (Request* r : act)
+    if (r->balanced && r->k == 0) fresh.push_back(r);
+  if (!fresh.empty()) stage1_batch(S, fresh, A);
   // ---- polynomial requests at stage 1 start from the constant skeleton
   {
     std::vector<uint32_t> nv;
@@ -202,7 +508,14 @@ void advance(Server& S) {
     std::vector<size_t> xo;
     for (auto& b : bal) xo.push_back(xb.add(b.X));
     char* dxb = xb.upload(A, s);
+    // every request's slice degrees and statuses in one device block, so that
+    // one copy reads them back
     size_t hwords = 0;
+    for (auto& b : bal) {
+      b.hoff = hwords;
+      hwords += 3 * (size_t)std::max<uint32_t>(b.T, 1);
+    }
+    int32_t* dflags = A.alloc<int32_t>(hwords);
     std::vector<ThieleJob> tj;
     std::vector<VapplyJob> vj;
     for (size_t q = 0; q < bal.size(); ++q) {
@@ -213,15 +526,13 @@ void advance(Server& S) {
       b.F = A.alloc<uint64_t>((size_t)b.nk * T1);
       b.cA = A.alloc<uint64_t>((size_t)(b.nk + 1) * T1);
       b.cB = A.alloc<uint64_t>((size_t)(b.nk + 1) * T1);
-      b.dgA = A.alloc<int32_t>(3 * (size_t)T1);
+      b.dgA = dflags + b.hoff;
       b.dgB = b.dgA + T1;
       b.dst = b.dgB + T1;
       b.nprev = A.alloc<uint64_t>(T1);
       b.dprev = A.alloc<uint64_t>(T1);
       const size_t sw = thiele_scratch_words(b.T, b.nk);
       uint64_t* scr = sw ? A.alloc<uint64_t>(sw) : nullptr;
-      b.hoff = hwords;
-      hwords += 3 * (size_t)T1;
       try {
         call_bb(r.bb, r.ctx, *r.P, r.k + 1, b.T, r.P->y.data(), b.X.data(), b.nk, b.F, s);
       } catch (const Error& e) {
@@ -270,10 +581,8 @@ void advance(Server& S) {
       S.hcap = std::max<size_t>(hwords, 1 << 16);
     }
     int32_t* hbuf = S.hbuf;
-    for (auto& b : bal)
-      if (b.r->status == ZR_OK)
-        check(hipMemcpyAsync(hbuf + b.hoff, b.dgA, 3 * (size_t)std::max<uint32_t>(b.T, 1) * 4,
-                             hipMemcpyDeviceToHost, s));
+    // (the blocks of requests whose black box failed are read too, and ignored)
+    check(hipMemcpyAsync(hbuf, dflags, hwords * 4, hipMemcpyDeviceToHost, s));
     check(hipStreamSynchronize(s));
     hflags.assign(hbuf, hbuf + hwords);
   }
@@ -484,10 +793,13 @@ zr_status zr_server_step(zr_server* srv, uint32_t* n_active, uint32_t* n_pending
       advance(S);
       S.steps += 1;
       S.stats.steps = S.steps;
-      std::vector<Request*> keep;
+      std::vector<Request*> keep, ended;
+      for (Request* r : S.active)
+        if (r->status != ZR_OK || r->k >= r->P->last) ended.push_back(r);
+      if (!ended.empty()) finish_batch(S, ended);
       for (Request* r : S.active) {
         if (r->status != ZR_OK || r->k >= r->P->last) {
-          finish(S, *r);
+          retire(S, *r);
           S.done[r->id] = r;
           ++fin;
         } else {

@@ -147,6 +147,66 @@ def test_served_arrivals_mixed_kinds_and_failures(zr):
     srv.close()
 
 
+def _lying_at_probes(base, sched):
+    """A black box that is right everywhere except at the schedule's probe
+    points (a single point whose last coordinate is a probe's), where it adds 1."""
+    last = {int(v) for v in sched.probes[:, -1]}
+
+    def f(k, i_first, ni, y, anchor, xk):
+        v = np.asarray(base(k, i_first, ni, y, anchor, xk), dtype=np.uint64).copy()
+        if ni == 1 and len(xk) == 1 and int(xk[0]) in last:
+            v[0] = np.uint64((int(v[0]) + 1) % sched.p)
+        return v
+    return f
+
+
+def test_served_finish_failures(zr):
+    """Requests that fail while their results are finished (a probe that
+    disagrees, a denominator without a constant term) fail alone, with the
+    status the one-request path gives; the others in the same steps equal
+    their runs alone."""
+    ws = _rational_mix(6, 3)
+    p = ws[0].p
+    pw = synth.poly_workload("probe", 3, 6, 60, 77, 1777, p=p)
+    num = synth.SparsePoly(p, 2, np.array([[0, 0], [1, 1]], dtype=np.uint16), np.array([4, 9], dtype=np.uint64))
+    den = synth.SparsePoly(p, 2, np.array([[1, 0], [0, 2]], dtype=np.uint16), np.array([1, 3], dtype=np.uint64))
+    dn, dd = [2, 2], [2, 2]
+    sn = synth.make_schedule(p, 2, [synth.thiele_nodes_needed(a, b) for a, b in zip(dn, dd)], 4, 1)
+    srv = zr.Server(p, hbm_budget=1 << 30, max_active=16)
+    ids = {}
+    for w in ws:
+        ids[srv.submit(w.deg_num, _box(zr, w.num, w.den), sched=w.schedule, deg_den=w.deg_den)] = ("ok", w)
+    ids[srv.submit(dn, _box(zr, num.sorted(), den.sorted()), sched=sn, deg_den=dd)] = ("norm", None)
+    rw = ws[1]
+    lie_r = zr.HostBlackBox(_lying_at_probes(synth.BlackBox(rw.num, rw.den).eval, rw.schedule), rw.num.nvars)
+    ids[srv.submit(rw.deg_num, lie_r, sched=rw.schedule, deg_den=rw.deg_den)] = ("probe", None)
+    lie_p = zr.HostBlackBox(_lying_at_probes(synth.BlackBox(pw.hidden).eval, pw.schedule), pw.hidden.nvars)
+    ids[srv.submit(pw.deg, lie_p, sched=pw.schedule)] = ("probe", None)
+    res = _run(srv, list(ids))
+    st = srv.stats()
+    _note(f"stats {st}")
+    assert st["completed"] == len(ids) and st["failed"] == 3
+    # the one-request paths give the same statuses
+    with pytest.raises(zr.ZippelError) as ei:
+        zr.balanced_reconstruct(p, dn, dd, _box(zr, num.sorted(), den.sorted()), sched=sn)
+    assert ei.value.code == zr.ZR_ENORM
+    with pytest.raises(zr.ZippelError) as ei:
+        zr.reconstruct(p, pw.deg, zr.HostBlackBox(_lying_at_probes(synth.BlackBox(pw.hidden).eval, pw.schedule),
+                                                  pw.hidden.nvars), sched=pw.schedule)
+    assert ei.value.code == zr.ZR_EPROBE
+    for i, (kind, w) in ids.items():
+        status, n_, d_ = res[i]
+        if kind == "norm":
+            assert status == zr.ZR_ENORM
+        elif kind == "probe":
+            assert status == zr.ZR_EPROBE
+        else:
+            ast, an, ad = _alone(zr, w)
+            assert status == ast == zr.ZR_OK
+            assert _same(n_, an) and _same(d_, ad)
+    srv.close()
+
+
 def test_served_admission_by_footprint(zr):
     """A budget below every request's footprint: requests run one at a time
     (a request that does not fit still runs when nothing else is active), and
