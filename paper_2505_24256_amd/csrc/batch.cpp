@@ -194,13 +194,20 @@ static void reconstruct_batch(uint32_t n, const zr_params* params, zr_blackbox_f
     DevArena A(s);
     std::vector<EvalJob> ej;
     std::vector<uint32_t> owner;
-    std::vector<uint64_t> tabs;
     std::vector<size_t> toff;
     std::vector<uint32_t> lds;
     size_t np_total = 0;
     for (uint32_t i = 0; i < n; ++i)
       if (st[i] == ZR_OK && P[i]->last == P[i]->nvars) np_total += P[i]->nprobes;
     uint64_t* d_res = A.alloc<uint64_t>(2 * std::max<size_t>(np_total, 1));
+    // the probe points go up once; their power tables are built on the device
+    Blob pb;
+    std::vector<size_t> poff(n, 0);
+    size_t twords = 0;
+    for (uint32_t i = 0; i < n; ++i)
+      if (st[i] == ZR_OK && P[i]->last == P[i]->nvars && P[i]->nprobes) poff[i] = pb.add(P[i]->probes);
+    char* dpts = pb.upload(A, s);
+    std::vector<PowJob> pj;
     size_t pi = 0;
     for (uint32_t i = 0; i < n; ++i) {
       if (st[i] != ZR_OK || P[i]->last != P[i]->nvars) continue;
@@ -215,24 +222,18 @@ static void reconstruct_batch(uint32_t n, const zr_params* params, zr_blackbox_f
         } catch (const Error& e) {
           st[i] = e.code;
         }
-        toff.push_back(tabs.size());
+        toff.push_back(twords);
         lds.push_back(ld);
-        for (uint32_t v = 0; v < nv; ++v) {
-          uint64_t a = 1 % p;
-          for (uint32_t d = 0; d < ld; ++d) {
-            tabs.push_back(a);
-            a = zr_mul(M, a, pt[v]);
-          }
-        }
+        pj.push_back(PowJob{(const uint64_t*)(dpts + poff[i]) + (size_t)q * nv, nullptr, nv, ld});
+        twords += (size_t)nv * ld;
         owner.push_back(i);
       }
     }
     if (pi) {
-      Blob b;
-      const size_t o = b.add(tabs);
-      char* d = b.upload(A, s);
-      for (size_t q = 0; q < pi; ++q)
-        ej.push_back(EvalJob{&cur[owner[q]], (const uint64_t*)(d + o) + toff[q], lds[q], d_res + pi + q});
+      uint64_t* tabs = A.alloc<uint64_t>(twords);
+      for (size_t q = 0; q < pi; ++q) pj[q].tab = tabs + toff[q];
+      batched_power_tables(M, pj, s);
+      for (size_t q = 0; q < pi; ++q) ej.push_back(EvalJob{&cur[owner[q]], tabs + toff[q], lds[q], d_res + pi + q});
       batched_eval(M, ej, s);
       std::vector<uint64_t> r(2 * pi);
       d2h_sync(r.data(), d_res, r.size() * 8, s);
@@ -253,15 +254,18 @@ static void reconstruct_batch(uint32_t n, const zr_params* params, zr_blackbox_f
       words += S.t + ((size_t)S.nvars * S.t + 3) / 4;
     }
     uint64_t* d = A.alloc<uint64_t>(std::max<size_t>(words, 1));
+    // coefficients as they are, exponents turned term-major on the device
+    std::vector<TransposeJob> tr;
     for (uint32_t i = 0; i < n; ++i) {
       if (st[i] != ZR_OK) continue;
       const Skeleton& S = cur[i];
       cp.push_back(CopyJob{S.coef, d + off[i], (size_t)S.t * 8});
-      cp.push_back(CopyJob{S.exps, d + off[i] + S.t, (size_t)S.nvars * S.t * 2});
+      tr.push_back(TransposeJob{S.exps, (uint16_t*)(d + off[i] + S.t), S.t, S.nvars});
     }
     batched_copy(cp, s);
-    std::vector<uint64_t> h(std::max<size_t>(words, 1));
-    d2h_sync(h.data(), d, words * 8, s);
+    batched_exps_to_terms(tr, s);
+    std::unique_ptr<uint64_t[]> h(new uint64_t[std::max<size_t>(words, 1)]);  // filled by the copy: no zeroing
+    d2h_sync(h.get(), d, words * 8, s);
     for (uint32_t i = 0; i < n; ++i) {
       if (st[i] != ZR_OK) continue;
       const Skeleton& S = cur[i];
@@ -278,10 +282,8 @@ static void reconstruct_batch(uint32_t n, const zr_params* params, zr_blackbox_f
         st[i] = ZR_ENOMEM;
         continue;
       }
-      memcpy(o.coeffs, h.data() + off[i], (size_t)S.t * 8);
-      const uint16_t* soa = (const uint16_t*)(h.data() + off[i] + S.t);
-      for (uint32_t l = 0; l < S.t; ++l)
-        for (uint32_t v = 0; v < S.nvars; ++v) o.exps[(size_t)l * S.nvars + v] = soa[(size_t)v * S.t + l];
+      memcpy(o.coeffs, h.get() + off[i], (size_t)S.t * 8);
+      memcpy(o.exps, h.get() + off[i] + S.t, (size_t)S.t * S.nvars * 2);
     }
   }
 }

@@ -1134,6 +1134,60 @@ void batched_copy(const std::vector<CopyJob>& jobs, hipStream_t s) {
   check(hipGetLastError());
 }
 
+__global__ void k_b_exps_to_terms(uint32_t n, const uint32_t* __restrict__ prefix,
+                                  const TransposeJob* __restrict__ sys) {
+  const uint32_t s = seg_find(prefix, n, blockIdx.x);
+  const TransposeJob& b = sys[s];
+  const uint64_t i = (uint64_t)(blockIdx.x - prefix[s]) * blockDim.x + threadIdx.x;  // l * nvars + v
+  if (i < (uint64_t)b.t * b.nvars) {
+    const uint64_t l = i / b.nvars, v = i % b.nvars;
+    b.dst[i] = b.src[v * b.t + l];
+  }
+}
+
+void batched_exps_to_terms(const std::vector<TransposeJob>& jobs, hipStream_t s) {
+  std::vector<TransposeJob> tj;
+  Segs seg;
+  for (const auto& j : jobs) {
+    if (!j.t || !j.nvars) continue;
+    tj.push_back(j);
+    seg.add(cdiv((uint64_t)j.t * j.nvars, 256));
+  }
+  if (tj.empty()) return;
+  DevArena A(s);
+  Blob b;
+  const size_t o = b.add(tj), op = b.add(seg.prefix);
+  char* d = b.upload(A, s);
+  hipLaunchKernelGGL(k_b_exps_to_terms, dim3(seg.total()), dim3(256), 0, s, seg.n(), (const uint32_t*)(d + op),
+                     (const TransposeJob*)(d + o));
+  check(hipGetLastError());
+}
+
+__global__ void k_b_powers(zr_mod M, uint32_t n, const PowJob* __restrict__ jobs) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const PowJob& j = jobs[i];
+  for (uint32_t v = 0; v < j.nv; ++v) {
+    const uint64_t x = j.pt[v];
+    uint64_t a = 1 % M.p;
+    for (uint32_t d = 0; d < j.ld; ++d) {
+      j.tab[(size_t)v * j.ld + d] = a;
+      a = zr_mul(M, a, x);
+    }
+  }
+}
+
+void batched_power_tables(const zr_mod& M, const std::vector<PowJob>& jobs, hipStream_t s) {
+  if (jobs.empty()) return;
+  DevArena A(s);
+  Blob b;
+  const size_t o = b.add(jobs);
+  char* d = b.upload(A, s);
+  hipLaunchKernelGGL(k_b_powers, dim3(cdiv((uint32_t)jobs.size(), 64u)), dim3(64), 0, s, M, (uint32_t)jobs.size(),
+                     (const PowJob*)(d + o));
+  check(hipGetLastError());
+}
+
 void batched_eval(const zr_mod& M, const std::vector<EvalJob>& jobs, hipStream_t s) {
   if (jobs.empty()) return;
   DevArena A(s);

@@ -111,6 +111,23 @@ struct CopyJob {
 };
 void batched_copy(const std::vector<CopyJob>& jobs, hipStream_t s);
 
+// Exponent arrays from the skeletons' SoA layout [nvars][t] to the results'
+// term-major layout [t][nvars], many in one launch.
+struct TransposeJob {
+  const uint16_t* src;
+  uint16_t* dst;
+  uint32_t t, nvars;
+};
+void batched_exps_to_terms(const std::vector<TransposeJob>& jobs, hipStream_t s);
+
+// Power tables of points: tab[v][d] = pt[v]^d for v < nv, d < ld (device).
+struct PowJob {
+  const uint64_t* pt;
+  uint64_t* tab;
+  uint32_t nv, ld;
+};
+void batched_power_tables(const zr_mod& M, const std::vector<PowJob>& jobs, hipStream_t s);
+
 // Host-to-device upload of many small host arrays in one copy (pinned staging).
 class Blob {
  public:
