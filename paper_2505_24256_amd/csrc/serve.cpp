@@ -224,31 +224,42 @@ void finish_batch(Server& S, const std::vector<Request*>& ended) {
       ps.push_back(ProbeSet{r, pwords});
       pwords += 3 * (size_t)r->P->nprobes;
     }
-  std::vector<uint64_t> pres;
   if (!ps.empty()) {
     uint64_t* d_res = A.alloc<uint64_t>(pwords);
     check(fill_u64(d_res, 0, pwords, s));
-    for (ProbeSet& e : ps) {
-      Request& r = *e.r;
+    // the probe points go up once; their power tables are built on the device
+    Blob pb;
+    std::vector<size_t> poff(ps.size()), toff(ps.size());
+    std::vector<uint32_t> lds(ps.size());
+    size_t twords = 0;
+    for (size_t e = 0; e < ps.size(); ++e) {
+      const Params& P = *ps[e].r->P;
+      const bool bal = ps[e].r->balanced;
+      uint32_t ld = 1;
+      for (uint32_t v = 0; v < P.nvars; ++v) ld = std::max(ld, std::max(P.deg[v], bal ? P.deg_den[v] : 0u) + 1);
+      lds[e] = ld;
+      poff[e] = pb.add(P.probes);
+      toff[e] = twords;
+      twords += (size_t)P.nprobes * P.nvars * ld;
+    }
+    char* dpts = pb.upload(A, s);
+    uint64_t* d_tabs = A.alloc<uint64_t>(twords);
+    std::vector<PowJob> pj;
+    for (size_t e = 0; e < ps.size(); ++e) {
+      const Params& P = *ps[e].r->P;
+      for (uint32_t q = 0; q < P.nprobes; ++q)
+        pj.push_back(PowJob{(const uint64_t*)(dpts + poff[e]) + (size_t)q * P.nvars,
+                            d_tabs + toff[e] + (size_t)q * P.nvars * lds[e], P.nvars, lds[e]});
+    }
+    batched_power_tables(S.M, pj, s);
+    for (size_t e = 0; e < ps.size(); ++e) {
+      Request& r = *ps[e].r;
       const Params& P = *r.P;
       const Skeleton* D = r.balanced ? &r.SD : nullptr;
-      const uint32_t np = P.nprobes, nv = P.nvars;
-      uint32_t ld = 1;
-      for (uint32_t v = 0; v < nv; ++v) ld = std::max(ld, std::max(P.deg[v], D ? P.deg_den[v] : 0u) + 1);
-      std::vector<uint64_t> tab((size_t)np * nv * ld, 0);
-      for (uint32_t q = 0; q < np; ++q)
-        for (uint32_t v = 0; v < nv; ++v) {
-          uint64_t acc = 1 % P.p;
-          for (uint32_t d = 0; d < ld; ++d) {
-            tab[((size_t)q * nv + v) * ld + d] = acc;
-            acc = zr_mul(P.M, acc, P.probes[(size_t)q * nv + v]);
-          }
-        }
-      Blob tb;
-      const size_t to = tb.add(tab);
-      const uint64_t* d_tab = (const uint64_t*)(tb.upload(A, s) + to);
+      const uint32_t np = P.nprobes, nv = P.nvars, ld = lds[e];
+      const uint64_t* d_tab = d_tabs + toff[e];
       uint64_t* d_part = A.alloc<uint64_t>(2 * (size_t)np * kPolyEvalBlocks);
-      uint64_t* res = d_res + e.off;
+      uint64_t* res = d_res + ps[e].off;
       try {
         for (uint32_t q = 0; q < np; ++q) {
           const uint64_t* pt = P.probes.data() + (size_t)q * nv;
