@@ -281,13 +281,10 @@ def served(zr, synth, args, stream):
                 continue
             srv.step()
             tn = time.perf_counter() - t0
-            for rid, i in list(ids.items()):
-                if i in fin:
-                    continue
-                r = srv.poll(rid)
-                if r is not None:
-                    fin[i] = tn
-                    res[i] = r
+            for rid in srv.finished():
+                i = ids[rid]
+                fin[i] = tn
+                res[i] = srv.poll(rid)
         stats = srv.stats()
         srv.close()
         lat = [fin[i] - arrivals[i] for i in range(len(ws))]

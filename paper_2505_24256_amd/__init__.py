@@ -28,7 +28,7 @@ EXPORTS = [
     "zr_recorder_blackbox", "zr_timing_enable", "zr_timing_reset", "zr_timing_get", "zr_last_counters",
     "zr_microbench", "zippel_reconstruct_batch", "zr_autotune", "zr_tuning_get", "zr_tuning_set",
     "zr_server_create", "zr_server_destroy", "zr_server_submit", "zr_server_step", "zr_server_poll",
-    "zr_server_get_stats", "zr_batch_graphs", "zr_solve_variant", "zr_thiele_slices",
+    "zr_server_get_stats", "zr_server_finished", "zr_batch_graphs", "zr_solve_variant", "zr_thiele_slices",
     "zr_vandermonde_solve", "zr_vandermonde_solve_noalloc", "zippel_reconstruct_rational", "zr_qpoly_free",
     "zr_skeleton_solve", "zippel_reconstruct_multi", "zippel_reconstruct_adaptive",
 ]
@@ -143,6 +143,8 @@ def lib():
         L.zr_server_step.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32)]
         L.zr_server_poll.argtypes = [vp, u64, ctypes.POINTER(i32), ctypes.POINTER(ZrPoly), ctypes.POINTER(ZrPoly)]
         L.zr_server_get_stats.argtypes = [vp, ctypes.POINTER(ZrServerStats)]
+        L.zr_server_finished.argtypes = [vp, ctypes.POINTER(u64), u32]
+        L.zr_server_finished.restype = u32
         L.zr_tuning_get.argtypes = [ctypes.POINTER(ZrBandChoice)]
         L.zr_tuning_set.argtypes = [ctypes.POINTER(ZrBandChoice)]
         for n in ("zr_copy_h2d", "zr_copy_d2h", "zr_copy_d2d"):
@@ -610,6 +612,16 @@ class Server:
         if not bal:
             lib().zr_poly_free(ctypes.byref(den))
         return status.value, n, d
+
+    def finished(self, cap: int = 4096):
+        """Ids of the requests that finished since the previous call."""
+        out = []
+        buf = (ctypes.c_uint64 * cap)()
+        while True:
+            n = lib().zr_server_finished(self.handle, buf, cap)
+            out.extend(buf[:n])
+            if n < cap:
+                return out
 
     def stats(self):
         s = ZrServerStats()

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <deque>
 #include <map>
+#include <unordered_set>
 #include <memory>
 #include <vector>
 
@@ -92,6 +93,8 @@ struct Server {
   std::deque<Request*> pending;
   std::vector<Request*> active;
   std::map<uint64_t, Request*> done;
+  std::unordered_set<uint64_t> waiting;  // ids submitted and not yet finished
+  std::vector<uint64_t> newly_done;      // finished since the last zr_server_finished
   zr_server_stats stats{};
   int32_t* hbuf = nullptr;  // pinned read-back buffer
   size_t hcap = 0;
@@ -772,6 +775,7 @@ zr_status zr_server_submit(zr_server* srv, const zr_params* params, int balanced
     }
     check(fill_i32(r->d_status, 0, 1, S.s));
     *id = r->id;
+    S.waiting.insert(r->id);
     S.pending.push_back(r.release());
     S.stats.submitted += 1;
     return ZR_OK;
@@ -812,6 +816,8 @@ zr_status zr_server_step(zr_server* srv, uint32_t* n_active, uint32_t* n_pending
         if (r->status != ZR_OK || r->k >= r->P->last) {
           retire(S, *r);
           S.done[r->id] = r;
+          S.waiting.erase(r->id);
+          S.newly_done.push_back(r->id);
           ++fin;
         } else {
           // the next stage's estimate from the skeletons just built
@@ -839,13 +845,7 @@ int zr_server_poll(zr_server* srv, uint64_t id, int32_t* status, zr_poly* num, z
   if (!srv) return ZR_EINVAL;
   Server& S = srv->impl;
   auto it = S.done.find(id);
-  if (it == S.done.end()) {
-    for (Request* r : S.pending)
-      if (r->id == id) return 1;
-    for (Request* r : S.active)
-      if (r->id == id) return 1;
-    return ZR_EINVAL;
-  }
+  if (it == S.done.end()) return S.waiting.count(id) ? 1 : ZR_EINVAL;
   Request* r = it->second;
   if (status) *status = r->status;
   if (num) *num = r->num;
@@ -855,6 +855,15 @@ int zr_server_poll(zr_server* srv, uint64_t id, int32_t* status, zr_poly* num, z
   S.done.erase(it);
   delete r;
   return 0;
+}
+
+uint32_t zr_server_finished(zr_server* srv, uint64_t* ids, uint32_t cap) {
+  if (!srv || (!ids && cap)) return 0;
+  Server& S = srv->impl;
+  const uint32_t n = (uint32_t)std::min<size_t>(cap, S.newly_done.size());
+  std::copy(S.newly_done.begin(), S.newly_done.begin() + n, ids);
+  S.newly_done.erase(S.newly_done.begin(), S.newly_done.begin() + n);
+  return n;
 }
 
 zr_status zr_server_get_stats(zr_server* srv, zr_server_stats* out) {

@@ -182,7 +182,18 @@ def test_served_finish_failures(zr):
     ids[srv.submit(rw.deg_num, lie_r, sched=rw.schedule, deg_den=rw.deg_den)] = ("probe", None)
     lie_p = zr.HostBlackBox(_lying_at_probes(synth.BlackBox(pw.hidden).eval, pw.schedule), pw.hidden.nvars)
     ids[srv.submit(pw.deg, lie_p, sched=pw.schedule)] = ("probe", None)
-    res = _run(srv, list(ids))
+    # results collected through the finished-ids query: every id exactly once
+    res = {}
+    steps = 0
+    while len(res) < len(ids):
+        srv.step()
+        steps += 1
+        assert steps < 100
+        for rid in srv.finished():
+            assert rid in ids and rid not in res
+            res[rid] = srv.poll(rid)
+            assert res[rid] is not None
+    assert srv.finished() == []
     st = srv.stats()
     _note(f"stats {st}")
     assert st["completed"] == len(ids) and st["failed"] == 3
