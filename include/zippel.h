@@ -411,10 +411,11 @@ zr_status zr_server_step(zr_server* srv, uint32_t* n_active, uint32_t* n_pending
  * unknown id.  num or den NULL discards that output. */
 int zr_server_poll(zr_server* srv, uint64_t id, int32_t* status, zr_poly* num, zr_poly* den);
 /* Ids of the requests that finished since the previous call, in the order they
- * finished: up to cap of them are written to ids and their count returned (the
- * rest are kept for the next call; 0 for a NULL server, or NULL ids with cap
- * above 0).  A serving loop then collects exactly those results with
- * zr_server_poll instead of polling every request still in flight. */
+ * finished, leaving out those already collected with zr_server_poll: up to cap
+ * of them are written to ids and their count returned (the rest are kept for
+ * the next call; 0 for a NULL server, or NULL ids with cap above 0).  A serving
+ * loop then collects exactly those results with zr_server_poll instead of
+ * polling every request still in flight. */
 uint32_t zr_server_finished(zr_server* srv, uint64_t* ids, uint32_t cap);
 zr_status zr_server_get_stats(zr_server* srv, zr_server_stats* stats);
 

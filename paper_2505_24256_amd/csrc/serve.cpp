@@ -818,6 +818,14 @@ zr_status zr_server_step(zr_server* srv, uint32_t* n_active, uint32_t* n_pending
           S.done[r->id] = r;
           S.waiting.erase(r->id);
           S.newly_done.push_back(r->id);
+          // a caller that only polls never drains the list: drop the ids
+          // already collected once they outnumber the uncollected ones
+          if (S.newly_done.size() > 2 * S.done.size() + 4096) {
+            std::vector<uint64_t> keep_ids;
+            for (uint64_t x : S.newly_done)
+              if (S.done.count(x)) keep_ids.push_back(x);
+            S.newly_done.swap(keep_ids);
+          }
           ++fin;
         } else {
           // the next stage's estimate from the skeletons just built
@@ -860,9 +868,12 @@ int zr_server_poll(zr_server* srv, uint64_t id, int32_t* status, zr_poly* num, z
 uint32_t zr_server_finished(zr_server* srv, uint64_t* ids, uint32_t cap) {
   if (!srv || (!ids && cap)) return 0;
   Server& S = srv->impl;
-  const uint32_t n = (uint32_t)std::min<size_t>(cap, S.newly_done.size());
-  std::copy(S.newly_done.begin(), S.newly_done.begin() + n, ids);
-  S.newly_done.erase(S.newly_done.begin(), S.newly_done.begin() + n);
+  // ids already collected through zr_server_poll are skipped
+  uint32_t n = 0;
+  size_t i = 0;
+  for (; i < S.newly_done.size() && n < cap; ++i)
+    if (S.done.count(S.newly_done[i])) ids[n++] = S.newly_done[i];
+  S.newly_done.erase(S.newly_done.begin(), S.newly_done.begin() + i);
   return n;
 }
 

@@ -233,3 +233,23 @@ def test_served_admission_by_footprint(zr):
         ast, an, ad = _alone(zr, w)
         assert status == ast == zr.ZR_OK and _same(num, an) and _same(den, ad)
     srv.close()
+
+
+def test_served_finished_skips_polled(zr):
+    """zr_server_finished lists each finished request once and leaves out the
+    ones already collected with zr_server_poll."""
+    p = synth.make_prime()
+    ps = [synth.poly_workload(f"f{i}", 3, 6, 30 + 10 * i, 500 + i, 1500 + i, p=p) for i in range(5)]
+    srv = zr.Server(p, hbm_budget=1 << 30, max_active=8)
+    ids = [srv.submit(w.deg, _box(zr, w.hidden), sched=w.schedule) for w in ps]
+    while srv.stats()["completed"] < len(ids):
+        srv.step()
+    early = {ids[1]: srv.poll(ids[1]), ids[3]: srv.poll(ids[3])}
+    rest = srv.finished()
+    assert sorted(rest) == sorted(set(ids) - set(early))
+    assert srv.finished() == []
+    for i, w in zip(ids, ps):
+        r = early[i] if i in early else srv.poll(i)
+        assert r[0] == zr.ZR_OK
+        assert np.array_equal(r[1][0], w.hidden.exps) and np.array_equal(r[1][1], w.hidden.coefs)
+    srv.close()
