@@ -6,6 +6,7 @@
 
 #include <memory>
 #include <mutex>
+#include <map>
 #include <vector>
 
 #include "../../include/zippel.h"
@@ -31,6 +32,7 @@ void d2h_sync(void* h, const void* d, size_t bytes, hipStream_t s);
 struct DevArena {
   hipStream_t s;
   int dev = 0;
+  std::multimap<size_t, void*>* free_list = nullptr;  // the block cache's free list of (dev, s)
   std::vector<std::pair<void*, size_t>> blocks;
   explicit DevArena(hipStream_t st);
   ~DevArena();

@@ -46,12 +46,19 @@ size_t size_class(size_t bytes) {
 }
 }  // namespace
 
-DevArena::DevArena(hipStream_t st) : s(st) { (void)hipGetDevice(&dev); }
+// The arena keeps a pointer to its (device, stream) free list: entries of the
+// cache's map are never removed, so the pointer stays valid.
+DevArena::DevArena(hipStream_t st) : s(st) {
+  (void)hipGetDevice(&dev);
+  BlockCache& C = block_cache();
+  std::lock_guard<std::mutex> g(C.mu);
+  free_list = &C.free[{dev, s}];
+}
 
 DevArena::~DevArena() {
   BlockCache& C = block_cache();
   std::lock_guard<std::mutex> g(C.mu);
-  auto& fl = C.free[{dev, s}];
+  auto& fl = *free_list;
   for (auto& b : blocks) fl.emplace(b.second, b.first);
 }
 
@@ -60,7 +67,7 @@ void* DevArena::raw(size_t bytes) {
   BlockCache& C = block_cache();
   {
     std::lock_guard<std::mutex> g(C.mu);
-    auto& fl = C.free[{dev, s}];
+    auto& fl = *free_list;
     auto it = fl.find(cls);
     if (it != fl.end()) {
       void* p = it->second;
