@@ -131,3 +131,23 @@ def test_solve_t1e6_multiply_back(zr):
     for j in (0, 13, R - 1):
         for i in (1, 1 + (j * 77_777 + 11) % t, t):
             assert int(oracle.vandermonde_apply(p, m, a[j], i, 1)[0]) == int(rhs[j, i - 1]), (j, i)
+
+
+def test_solve_t2e6_multiply_back(zr):
+    """One system of t = 2*10^6 unknowns and 40 right-hand sides, where the
+    bound on the per-chunk state (16 GiB) sets the chunk count: 357 chunks of
+    5 603 steps in 60 launches that share 6 partial-sum slots.  Checked by the
+    defining property at sampled equations."""
+    p = synth.make_prime()
+    t, R = 2_000_000, 40
+    g = synth.SplitMix64(987)
+    m = g.uniform_block(1, p, t)
+    assert len(np.unique(m)) == t
+    rhs = g.uniform_block(0, p, t * R).reshape(R, t)
+    _note(f"solve t={t} R={R} (about 40 s)")
+    a, st = zr.vandermonde_solve(p, m, rhs)
+    assert st == 0
+    _note("multiply-back at sampled equations")
+    for j in (0, R - 1):
+        for i in (1, 1 + (j * 99_991 + 7) % t, t):
+            assert int(oracle.vandermonde_apply(p, m, a[j], i, 1)[0]) == int(rhs[j, i - 1]), (j, i)
